@@ -1,0 +1,167 @@
+"""FP64 reference of the learned part -- TEST INFRASTRUCTURE ONLY.
+
+Follows the paper's Sec. II.B (training data and MLP): the network input is
+{T, p, F(Y)} with F the Box-Cox transform (Eq. 7, lambda = 0.1), the output is
+the change of the mass fractions over the step, u* = Y(t+dt) - Y(t), hidden
+layers use GELU and the parameters are fitted with Adam on the data loss
+(Eq. 8).  Readings where the text is silent or garbled:
+
+* Eq. 7 prints x^{lambda-1}/lambda; the stated mapping of [0, 1] onto
+  [-1/lambda, 0] fixes it as (x^lambda - 1)/lambda (log x when lambda = 0);
+  negative mass fractions (integration round-off) are clamped to 0 first.
+* Inputs and outputs are z-scored per feature with training-split statistics
+  (sigma floored at 1e-12).
+* GELU is the exact x Phi(x) form.
+* Operands are rounded to bfloat16 (round-to-nearest-even) exactly where the
+  GPU rounds them: weights, the network input and every hidden activation;
+  the backward pass rounds the output gradient and every pre-activation
+  gradient.  Sums are accumulated in float64 here.
+* Adam follows Kingma & Ba (2015), Algorithm 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import erf
+
+LAMBDA = 0.1
+SQRT2 = np.sqrt(2.0)
+
+
+# ----------------------------------------------------------------------------
+# transforms
+# ----------------------------------------------------------------------------
+def box_cox(x, lam=LAMBDA):
+    """Eq. 7 (reading above): (x^lam - 1)/lam, or log x for lam = 0."""
+    x = np.maximum(np.asarray(x, np.float64), 0.0)
+    if lam == 0.0:
+        return np.log(x)
+    return (np.power(x, lam) - 1.0) / lam
+
+
+def gelu(x):
+    """x Phi(x) with Phi the standard normal CDF."""
+    return 0.5 * x * (1.0 + erf(x / SQRT2))
+
+
+def gelu_grad(x):
+    """d/dx [x Phi(x)] = Phi(x) + x phi(x)."""
+    return 0.5 * (1.0 + erf(x / SQRT2)) + x * np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even) via float32; returns float64.
+
+    float64 -> float32 first (as the GPU holds float32 values), then the 16
+    low bits of the float32 pattern are rounded away."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def f32(x):
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+
+# ----------------------------------------------------------------------------
+# features and normalisation
+# ----------------------------------------------------------------------------
+def raw_features(T, p, Y):
+    """[F(Y_1..Y_K), T, p] per cell (input set of Sec. II.B)."""
+    return np.concatenate([box_cox(Y), np.asarray(T, np.float64)[:, None],
+                           np.asarray(p, np.float64)[:, None]], axis=1)
+
+
+def norm_stats(X, floor=1e-12):
+    mu = X.mean(0)
+    sd = np.maximum(X.std(0), floor)
+    return mu, sd
+
+
+# ----------------------------------------------------------------------------
+# the network
+# ----------------------------------------------------------------------------
+def init_params(dims, seed):
+    """He-uniform weights (U[-sqrt(6/fan_in), +]), zero biases.  W[l] is (in, out)."""
+    rng = np.random.default_rng(seed)
+    Ws, bs = [], []
+    for i in range(len(dims) - 1):
+        lim = np.sqrt(6.0 / dims[i])
+        Ws.append(f32(rng.uniform(-lim, lim, (dims[i], dims[i + 1]))))
+        bs.append(np.zeros(dims[i + 1]))
+    return Ws, bs
+
+
+def forward(Ws, bs, X, quantize=True):
+    """MLP forward.  Returns (output, cache).  With ``quantize`` the operands
+    are bfloat16-rounded where the GPU rounds them (see module docstring)."""
+    q = bf16 if quantize else (lambda a: a)
+    a = q(X)
+    cache = {"A": [a], "Z": []}
+    L = len(Ws)
+    for i in range(L):
+        z = a @ q(Ws[i]) + bs[i]
+        if quantize:
+            z = f32(z)
+        cache["Z"].append(z)
+        if i < L - 1:
+            a = q(gelu(z))
+            cache["A"].append(a)
+        else:
+            a = z
+    return a, cache
+
+
+def mse_loss(out, target):
+    """Eq. 8 on normalised outputs: mean over samples and outputs."""
+    d = out - target
+    return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def backward(Ws, bs, cache, dout, quantize=True):
+    """Gradients of the loss w.r.t. W[l] (in, out) and b[l]."""
+    q = bf16 if quantize else (lambda a: a)
+    L = len(Ws)
+    gW = [None] * L
+    gb = [None] * L
+    dz = q(dout)
+    for i in range(L - 1, -1, -1):
+        a = cache["A"][i]
+        gW[i] = a.T @ dz
+        gb[i] = dz.sum(0)
+        if i > 0:
+            da = dz @ q(Ws[i]).T
+            dz = q(da * gelu_grad(cache["Z"][i - 1]))
+    return gW, gb
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015, Alg. 1).  Returns (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ----------------------------------------------------------------------------
+# output side
+# ----------------------------------------------------------------------------
+def element_matrix(composition, element_mass):
+    """E[e, k] = n_ek A_e / W_k: element e's mass fraction carried by species k."""
+    comp = np.asarray(composition, np.float64)
+    W = comp @ np.asarray(element_mass, np.float64)
+    return (comp * np.asarray(element_mass)[None, :]).T / W[None, :]
+
+
+def project_delta(Emat, Y, dY, floor=1e-30):
+    """Element-conserving correction of dY (weights w_k = max(Y_k + dY_k, floor)):
+    dY <- dY - w E^T (E w E^T)^-1 E dY, so that E dY = 0."""
+    out = np.empty_like(dY)
+    for c in range(dY.shape[0]):
+        w = np.maximum(Y[c] + dY[c], floor)
+        A = (Emat * w[None, :]) @ Emat.T
+        lam = np.linalg.solve(A, Emat @ dY[c])
+        out[c] = dY[c] - w * (Emat.T @ lam)
+    return out
