@@ -1,0 +1,260 @@
+/*
+ * chemk.h -- C ABI of the MI355X (gfx950) chemistry-advance library.
+ *
+ * The library advances the thermochemical state (T, p, Y_1..Y_K) of every
+ * cell of a reacting-flow solver over one flow time step dt, either by direct
+ * integration (DI) of the stiff kinetics ODEs or by a multilayer perceptron
+ * that stands in for DI, and evaluates the thermal properties around that
+ * step.  This is the chemistry part of the GPU-ANN LES method of Zhang et al.
+ * (Sec. II): the ODE system of Eq. 1, integrated over a step to give the pair
+ * of Eq. 2 per cell; the ANN replacement of Sec. II.A/II.B (inputs {T, p,
+ * F(Y)}, output Y(t+dt) - Y(t), Box-Cox transform of Eq. 7, GELU MLP trained
+ * with Adam on the loss of Eq. 8); and the property update of Sec. II.A
+ * (temperature from enthalpy by Newton's method on temperature polynomials).
+ *
+ * Conventions shared by every call:
+ *  - All state arrays are caller-owned DEVICE memory on the context's GPU,
+ *    FP64 unless stated, and must stay valid until the work enqueued on
+ *    `stream` has completed.  Y is row-major (n, K): Y[c*K + k].
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous: CHEMK_OK means "validated and enqueued".  The
+ *    library never synchronises unless a call says so.
+ *  - Host-side argument checks run before anything is enqueued; on error
+ *    nothing is enqueued, outputs are untouched and chemk_last_error()
+ *    returns a message (thread-local, valid until the next call on the
+ *    same thread).
+ *  - Units: SI for T [K], p [Pa], h [J/kg], cp [J/(kg K)], time [s]; the
+ *    mechanism's rate parameters are cgs (mol, cm, s) with Ea in cal/mol.
+ */
+#ifndef CHEMK_H
+#define CHEMK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+enum {
+    CHEMK_OK = 0,
+    CHEMK_E_ARG = 1,          /* bad argument (null pointer, size, option)        */
+    CHEMK_E_MECH = 2,         /* mechanism rejected (not element-conserving, ...) */
+    CHEMK_E_HIP = 3,          /* HIP runtime error                                 */
+    CHEMK_E_DT = 4,           /* ANN advance with a dt other than the trained one  */
+    CHEMK_E_OOM = 5,          /* device allocation failed                          */
+    CHEMK_E_STATE = 6,        /* call out of order (e.g. ANN used before set-up)   */
+    CHEMK_E_UNSUPPORTED = 7   /* size outside what the kernels support             */
+};
+
+/* ---- per-cell outcome codes written to `status` -------------------------- */
+enum {
+    CHEMK_CELL_OK = 0,
+    CHEMK_CELL_MAX_STEPS = 1, /* integrator hit max_steps or a step underflow     */
+    CHEMK_CELL_T_RANGE = 2,   /* final T outside [200, 4000] K                    */
+    CHEMK_CELL_NONFINITE = 3, /* non-finite state                                 */
+    CHEMK_CELL_NEWTON = 4,    /* T from enthalpy failed (h outside the T range)    */
+    CHEMK_CELL_SINGULAR = 6,  /* singular iteration matrix                        */
+    CHEMK_CELL_ROUTED_DI = 8  /* info bit (ANN mode): the cell was advanced by DI */
+};
+
+/* Largest species count: one wavefront (64 lanes) holds the K+1 unknowns. */
+#define CHEMK_MAX_SPECIES 63
+#define CHEMK_MAX_REACTIONS 4096
+#define CHEMK_MAX_ELEMENTS 8
+
+typedef struct chemk_mech chemk_mech;
+typedef struct chemk_ctx chemk_ctx;
+
+/* ---- mechanism ------------------------------------------------------------
+ * Reaction j reads  sum_i reactants[2j+i]  (+M)  <=>  sum_i products[2j+i] (+M),
+ * slot value -1 = empty, a species may appear in both slots (2A).  Rates are
+ * mass action with k_f = A T^beta exp(-Ea/(R_c T)) (cgs, Ea in cal/mol), the
+ * reverse rate from the equilibrium constant K_c = K_p (p0/(R_u T))^dnu with
+ * p0 = 101325 Pa and K_p from the NASA-7 Gibbs energies, and third bodies with
+ * unit efficiencies ([M] = p/(R_u T)) multiplying both directions.  NASA-7 is
+ * single range: cp/R = a1 + a2 T + .. + a5 T^4, h/RT = a1 + a2 T/2 + .. + a6/T,
+ * s/R = a1 ln T + a2 T + .. + a7.  All arrays are HOST memory, copied.      */
+typedef struct {
+    int32_t n_elements;           /* E, 1..CHEMK_MAX_ELEMENTS                     */
+    int32_t n_species;            /* K, 1..CHEMK_MAX_SPECIES                      */
+    int32_t n_reactions;          /* R, 0..CHEMK_MAX_REACTIONS                    */
+    const double *element_mass;   /* [E] g/mol, > 0                               */
+    const int32_t *composition;   /* [K*E] atoms of element e in species k, >= 0  */
+    const double *nasa7;          /* [K*7]                                        */
+    const int32_t *reactants;     /* [R*2] species index or -1                    */
+    const int32_t *products;      /* [R*2] species index or -1                    */
+    const double *log_A;          /* [R] natural log of A, cgs                    */
+    const double *beta;           /* [R]                                          */
+    const double *Ea;             /* [R] cal/mol                                  */
+    const int32_t *third_body;    /* [R] 0/1                                      */
+    const int32_t *reversible;    /* [R] 0/1                                      */
+} chemk_mech_desc;
+
+/* Validate and copy a mechanism.  Rejects (CHEMK_E_MECH, message in
+ * chemk_last_error) reactions that do not conserve every element, empty
+ * sides, out-of-range indices, species without atoms and non-finite numbers. */
+int chemk_mech_create(const chemk_mech_desc *desc, chemk_mech **out);
+void chemk_mech_free(chemk_mech *mech);
+int chemk_mech_info(const chemk_mech *mech, int32_t *K, int32_t *R, int32_t *E);
+
+/* A context owns the device copy of one mechanism plus scratch, queues,
+ * captured graphs, the autotune cache and the optional network, on `device`.
+ * The mechanism may be freed after this call.                               */
+int chemk_ctx_create(int device, const chemk_mech *mech, chemk_ctx **out);
+void chemk_ctx_free(chemk_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *chemk_last_error(void);
+
+/* ---- properties (Sec. II.A: thermal property update) --------------------- */
+
+/* Mixture cp [J/(kg K)] and h [J/kg] of n cells at (T[c], Y[c,:]). */
+int chemk_thermo(chemk_ctx *ctx, int64_t n, const double *T, const double *Y,
+                 double *cp, double *h, void *stream);
+
+/* T from the mixture enthalpy: Newton on h(T, Y) = h[c] starting from the
+ * value in T[c] (relative tolerance 1e-12, at most 50 iterations), then
+ * bisection on [200, 4000] K.  T is in/out; status[c] = 0 or
+ * CHEMK_CELL_NEWTON (h outside [h(200 K), h(4000 K)]; T left unchanged). */
+int chemk_T_from_h(chemk_ctx *ctx, int64_t n, const double *h, const double *Y,
+                   double *T, int32_t *status, void *stream);
+
+/* Right-hand side of Eq. 1 at constant p: dydt[c*(K+1) + k] = dY_k/dt for
+ * k < K and dT/dt at k = K.                                                  */
+int chemk_rhs(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+              const double *Y, double *dydt, void *stream);
+
+/* Analytic Jacobian of chemk_rhs w.r.t. (Y_1..Y_K, T), row-major (K+1)^2 per
+ * cell: J[c*(K+1)^2 + i*(K+1) + j] = d f_i / d y_j.                          */
+int chemk_jacobian(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+                   const double *Y, double *J, void *stream);
+
+/* ---- the chemistry advance (Eqs. 1-2) --------------------------------------- */
+enum { CHEMK_MODE_DI = 0, CHEMK_MODE_ANN = 1 };
+
+typedef struct {
+    int32_t mode;            /* CHEMK_MODE_DI or CHEMK_MODE_ANN                    */
+    int32_t max_steps;       /* DI step limit per cell (default 100000)            */
+    double rtol;             /* DI relative tolerance (default 1e-7)               */
+    double atol_Y;           /* DI absolute tolerance on Y (default 1e-14)         */
+    double atol_T;           /* DI absolute tolerance on T [K] (default 1e-6)      */
+    double h0_frac;          /* first trial step = h0_frac * dt (default 1e-3)     */
+    int32_t bins;            /* stiffness bins; 0 = autotuned / cached choice      */
+    int32_t waves_per_cu;    /* persistent DI residency; 0 = autotuned / default   */
+    int32_t use_graph;       /* 1 = capture the whole step in a hipGraph and replay */
+    int32_t project;         /* 1 = FP64 element projection of the output (default) */
+} chemk_opts;
+
+void chemk_opts_default(chemk_opts *opts);
+
+/* Advance n cells over dt in place.  T [n] and Y [n,K] are in/out, p [n] in.
+ * DI: adaptive Rosenbrock (RODAS, order 4(3)) on y = (Y, T); the final T is
+ * recovered from the conserved mixture enthalpy and Y is projected so that
+ * element masses equal the input's to FP64 round-off.
+ * ANN: the trained network predicts Y(t+dt) - Y(t); the prediction is
+ * element-projected; cells outside the training envelope or whose prediction
+ * fails the checks (non-finite, Y_k below -neg_tol) are advanced by DI in the
+ * same call and get CHEMK_CELL_ROUTED_DI set in status.  dt must equal the
+ * trained dt (relative 1e-12) else CHEMK_E_DT and nothing is touched.
+ * status [n] (required) receives the per-cell code; nsteps [n] (optional,
+ * NULL allowed) receives the accepted+rejected DI step count (0 for ANN).   */
+int chemk_advance(chemk_ctx *ctx, int64_t n, double *T, const double *p, double *Y,
+                  double dt, const chemk_opts *opts, int32_t *status, int32_t *nsteps,
+                  void *stream);
+
+/* Stiffness-batching autotuner (the "bins / tile shape" choice of the DI
+ * path): runs DI on COPIES of the n given cells for a small grid of
+ * (stiffness bins, persistent waves per CU), times each with HIP events on
+ * `stream`, stores the fastest in the context (used whenever opts->bins or
+ * opts->waves_per_cu is 0) and returns it in best[0] = bins,
+ * best[1] = waves_per_cu, best_ms[0] = its time.  Synchronises `stream`.
+ * The state arrays are not modified.                                         */
+int chemk_autotune(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+                   const double *Y, double dt, const chemk_opts *opts, int32_t best[2],
+                   double *best_ms, void *stream);
+
+/* Phase timing (profiling aid).  While enabled, chemk_advance runs eagerly
+ * (use_graph is ignored) and brackets each phase's launches with HIP events
+ * on the caller's stream; chemk_timing_read synchronises the stream and
+ * returns, per phase, the summed milliseconds and the number of launches
+ * since the last read (then resets).  Phases: */
+enum {
+    CHEMK_PHASE_DI = 0,        /* persistent DI kernel (DI mode)                  */
+    CHEMK_PHASE_BINNING = 1,   /* stiffness key, histogram, queue                  */
+    CHEMK_PHASE_INGEST = 2,    /* ANN: features, envelope test                     */
+    CHEMK_PHASE_MLP = 3,       /* ANN: the MLP GEMMs                               */
+    CHEMK_PHASE_POST = 4,      /* ANN: de-normalise, project, check, T             */
+    CHEMK_PHASE_FALLBACK = 5,  /* ANN: DI on the routed cells                      */
+    CHEMK_NUM_PHASES = 6
+};
+int chemk_timing(chemk_ctx *ctx, int32_t enable);
+int chemk_timing_read(chemk_ctx *ctx, double ms[CHEMK_NUM_PHASES],
+                      int64_t launches[CHEMK_NUM_PHASES], void *stream);
+
+/* Counters of the last chemk_advance on this context (synchronises stream):
+ * out[0] cells routed to DI, out[1] total DI steps, out[2] cells with a
+ * non-zero status (ignoring the routed bit).                                 */
+int chemk_last_counters(chemk_ctx *ctx, int64_t out[3], void *stream);
+
+/* ---- the learned part (Sec. II.B) ------------------------------------------
+ * One MLP: dims[0] = K + 2 inputs (Box-Cox(max(Y,0)) with lambda = 0.1, T, p,
+ * each z-scored), hidden dims[1..L-1] with GELU, dims[L] = K outputs (the
+ * z-scored change of Y over dt).  BF16 operands on MFMA with FP32
+ * accumulation; FP32 master weights for training.  Parameter vector layout
+ * (host, FP32): for each layer l: W_l [dims[l] x dims[l+1]] row-major, then
+ * b_l [dims[l+1]].                                                           */
+int chemk_ann_create(chemk_ctx *ctx, const int32_t *dims, int32_t n_layers);
+int chemk_ann_param_count(chemk_ctx *ctx, int64_t *count);
+int chemk_ann_set_weights(chemk_ctx *ctx, const float *params, int64_t count);
+int chemk_ann_get_weights(chemk_ctx *ctx, float *params, int64_t count);
+
+/* Normalisation (host arrays): mu_x/sd_x [K+2] over raw features, mu_y/sd_y
+ * [K] over Y(t+dt)-Y(t); dt is the step the network is trained for.          */
+int chemk_ann_set_norm(chemk_ctx *ctx, const double *mu_x, const double *sd_x,
+                       const double *mu_y, const double *sd_y, double dt);
+int chemk_ann_get_norm(chemk_ctx *ctx, double *mu_x, double *sd_x, double *mu_y,
+                       double *sd_y, double *dt);
+
+/* Training envelope (host arrays): raw-feature box lo/hi [K+2]; a cell with
+ * any feature outside it is routed to DI.  neg_tol: predicted Y_k below
+ * -neg_tol routes the cell to DI.                                            */
+int chemk_ann_set_envelope(chemk_ctx *ctx, const double *lo, const double *hi, double neg_tol);
+int chemk_ann_get_envelope(chemk_ctx *ctx, double *lo, double *hi, double *neg_tol);
+
+/* Device: compute the normalisation from n training pairs (state, state after
+ * dt) and store it (sd floored at 1e-12), plus the envelope box of the raw
+ * features widened by `widen` times its span on each side.                   */
+int chemk_ann_fit_norm(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+                       const double *Y, const double *Y_next, double dt, double widen,
+                       double neg_tol, void *stream);
+
+/* Device: pack training pairs into network space: X [n, F] BF16 (F = dims[0]
+ * rounded up to 32, zero padded, stored as uint16 bit patterns) and the
+ * z-scored targets Z [n, K] FP32.                                             */
+int chemk_ann_pack(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+                   const double *Y, const double *Y_next, uint16_t *X, float *Z,
+                   void *stream);
+
+/* Network forward on packed inputs X [n, F] (BF16 bits): out [n, K] FP32, the
+ * z-scored prediction.  Test hook and batch inference.                        */
+int chemk_ann_forward_packed(chemk_ctx *ctx, int64_t n, const uint16_t *X, float *out,
+                             void *stream);
+
+/* One training step on rows idx[0..B-1] of (X, Z): forward with saved
+ * activations, MSE on the z-scored outputs (Eq. 8), backward, Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, step counter kept in the context) with learning rate
+ * lr.  loss (device FP32 scalar, may be NULL) receives the batch loss before
+ * the update.  grads (device FP32 [param_count], may be NULL) receives the
+ * gradient; with update = 0 the weights are left unchanged.                   */
+int chemk_ann_train_step(chemk_ctx *ctx, const int32_t *idx, int32_t B, const uint16_t *X,
+                         const float *Z, float lr, int32_t update, float *loss, float *grads,
+                         void *stream);
+
+/* Reset the Adam moments and step counter. */
+int chemk_ann_reset_optimizer(chemk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEMK_H */

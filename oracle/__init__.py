@@ -34,6 +34,19 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def default_threads() -> int:
+    """Host threads for the oracle: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when set (oversubscribed spinning threads slow it down)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 class _Mech(C.Structure):
     _fields_ = [("E", C.c_int32), ("K", C.c_int32), ("R", C.c_int32),
                 ("emass", C.c_void_p), ("comp", C.c_void_p), ("nasa", C.c_void_p),
@@ -199,7 +212,7 @@ class OracleMech:
         ns = np.zeros(n, np.int32)
         o = _Opts(rtol, atol_Y, atol_T, h0_frac, max_steps, int(project), int(newton_T))
         lib().or_advance(self.ref, n, T, p, Y, float(dt), C.byref(o), st, ns,
-                         int(nthreads or os.cpu_count() or 1))
+                         int(nthreads or default_threads()))
         return T, Y, st, ns
 
 

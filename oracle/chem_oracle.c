@@ -510,14 +510,14 @@ int or_rodas(int N, or_fun f, or_fun jac, void *ctx, double *y, double tend,
             need_jac = 1;
             st->naccept++;
             if (fixed_h <= 0) {
-                double fc = err > 0 ? 0.9 * pow(err, -0.25) : 5.0;
+                double fc = err > 0 ? 0.9 / sqrt(sqrt(err)) : 5.0;
                 fc = fmin(5.0, fmax(0.2, fc));
                 if (rejected) fc = fmin(fc, 1.0);
                 h *= fc;
             }
             rejected = 0;
         } else {
-            double fc = fmax(0.2, 0.9 * pow(err, -0.25));
+            double fc = fmax(0.2, 0.9 / sqrt(sqrt(err)));
             h *= fc;
             rejected = 1;
             st->nreject++;
@@ -666,11 +666,12 @@ int or_advance_cell(const or_mech *m, double *T, double p, double *Y, double dt,
     return 0;
 }
 
-/* All cells, OpenMP over cells (dynamic schedule, chunk 64). */
+/* All cells, OpenMP over cells (dynamic schedule, one cell at a time: a cell
+ * costs milliseconds, so the scheduling overhead is negligible). */
 void or_advance(const or_mech *m, int64_t n, double *T, const double *p, double *Y,
                 double dt, const or_opts *o, int32_t *status, int32_t *nsteps, int nthreads)
 {
-#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int64_t c = 0; c < n; ++c) {
         or_stats st = {0, 0, 0, 0.0};
         status[c] = or_advance_cell(m, T + c, p[c], Y + c * m->K, dt, o, &st);

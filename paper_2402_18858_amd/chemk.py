@@ -1,0 +1,292 @@
+"""Python binding of libchemk.so (argument marshalling only).
+
+Every call forwards device pointers of torch tensors and the current HIP
+stream to the C ABI declared in include/chemk.h; all arithmetic runs in the
+library's gfx950 kernels.  There is no fallback: if the shared library is
+missing or cannot be loaded, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchemk.so")
+
+OK, E_ARG, E_MECH, E_HIP, E_DT, E_OOM, E_STATE, E_UNSUPPORTED = range(8)
+CELL_OK, CELL_MAX_STEPS, CELL_T_RANGE, CELL_NONFINITE, CELL_NEWTON = 0, 1, 2, 3, 4
+CELL_SINGULAR, CELL_ROUTED_DI = 6, 8
+MODE_DI, MODE_ANN = 0, 1
+
+
+class ChemkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"chemk error {code}: {msg}")
+        self.code = code
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("n_elements", C.c_int32), ("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("element_mass", C.c_void_p), ("composition", C.c_void_p),
+                ("nasa7", C.c_void_p), ("reactants", C.c_void_p), ("products", C.c_void_p),
+                ("log_A", C.c_void_p), ("beta", C.c_void_p), ("Ea", C.c_void_p),
+                ("third_body", C.c_void_p), ("reversible", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("max_steps", C.c_int32), ("rtol", C.c_double),
+                ("atol_Y", C.c_double), ("atol_T", C.c_double), ("h0_frac", C.c_double),
+                ("bins", C.c_int32), ("waves_per_cu", C.c_int32), ("use_graph", C.c_int32),
+                ("project", C.c_int32)]
+
+
+_vp = C.c_void_p
+_i64 = C.c_int64
+_SIGS = {
+    "chemk_mech_create": (C.c_int, [C.POINTER(MechDesc), C.POINTER(_vp)]),
+    "chemk_mech_free": (None, [_vp]),
+    "chemk_mech_info": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]),
+    "chemk_ctx_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
+    "chemk_ctx_free": (None, [_vp]),
+    "chemk_last_error": (C.c_char_p, []),
+    "chemk_thermo": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "chemk_T_from_h": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "chemk_rhs": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "chemk_jacobian": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "chemk_opts_default": (None, [C.POINTER(Opts)]),
+    "chemk_advance": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts), _vp,
+                                _vp, _vp]),
+    "chemk_autotune": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp]),
+    "chemk_last_counters": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp]),
+    "chemk_timing": (C.c_int, [_vp, C.c_int32]),
+    "chemk_timing_read": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), _vp]),
+    "chemk_ann_create": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_int32]),
+    "chemk_ann_param_count": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
+    "chemk_ann_set_weights": (C.c_int, [_vp, _vp, _i64]),
+    "chemk_ann_get_weights": (C.c_int, [_vp, _vp, _i64]),
+    "chemk_ann_set_norm": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double]),
+    "chemk_ann_get_norm": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "chemk_ann_set_envelope": (C.c_int, [_vp, _vp, _vp, C.c_double]),
+    "chemk_ann_get_envelope": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "chemk_ann_fit_norm": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
+                                     C.c_double, _vp]),
+    "chemk_ann_pack": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "chemk_ann_forward_packed": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
+    "chemk_ann_train_step": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, C.c_float, C.c_int32,
+                                       _vp, _vp, _vp]),
+    "chemk_ann_reset_optimizer": (C.c_int, [_vp]),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(hipcc, gfx950); there is no fallback path")
+lib = C.CDLL(LIB_PATH)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(code):
+    if code != OK:
+        raise ChemkError(code, lib.chemk_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib.chemk_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Mechanism:
+    """Validated host copy of a mechanism (chemk_mech)."""
+
+    def __init__(self, mech):
+        self._keep = dict(
+            em=np.ascontiguousarray(mech.element_mass, np.float64),
+            comp=np.ascontiguousarray(mech.composition, np.int32),
+            nasa=np.ascontiguousarray(mech.nasa7, np.float64),
+            reac=np.ascontiguousarray(mech.reactants, np.int32),
+            prod=np.ascontiguousarray(mech.products, np.int32),
+            lnA=np.ascontiguousarray(mech.log_A, np.float64),
+            beta=np.ascontiguousarray(mech.beta, np.float64),
+            Ea=np.ascontiguousarray(mech.Ea, np.float64),
+            tb=np.ascontiguousarray(mech.third_body, np.int32),
+            rev=np.ascontiguousarray(mech.reversible, np.int32))
+        k = self._keep
+        d = MechDesc(len(mech.elements), k["comp"].shape[0], k["reac"].shape[0],
+                     *(k[n].ctypes.data for n in ("em", "comp", "nasa", "reac", "prod", "lnA",
+                                                  "beta", "Ea", "tb", "rev")))
+        h = C.c_void_p()
+        _check(lib.chemk_mech_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        K, R, E = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib.chemk_mech_info(h, C.byref(K), C.byref(R), C.byref(E)))
+        self.K, self.R, self.E = K.value, R.value, E.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.chemk_mech_free(h)
+            self.handle = None
+
+
+class Context:
+    """A chemk_ctx on one GPU: device tables of the mechanism, scratch, graphs."""
+
+    def __init__(self, mech, device: int = 0):
+        self.mech = mech if isinstance(mech, Mechanism) else Mechanism(mech)
+        h = C.c_void_p()
+        _check(lib.chemk_ctx_create(int(device), self.mech.handle, C.byref(h)))
+        self.handle = h
+        self.K = self.mech.K
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.chemk_ctx_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- properties ----
+    def thermo(self, T, Y, cp, h, stream=None):
+        _check(lib.chemk_thermo(self.handle, T.numel(), _ptr(T), _ptr(Y), _ptr(cp), _ptr(h),
+                                _stream(stream)))
+
+    def T_from_h(self, h, Y, T, status, stream=None):
+        _check(lib.chemk_T_from_h(self.handle, T.numel(), _ptr(h), _ptr(Y), _ptr(T),
+                                  _ptr(status), _stream(stream)))
+
+    def rhs(self, T, p, Y, out, stream=None):
+        _check(lib.chemk_rhs(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y), _ptr(out),
+                             _stream(stream)))
+
+    def jacobian(self, T, p, Y, out, stream=None):
+        _check(lib.chemk_jacobian(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y), _ptr(out),
+                                  _stream(stream)))
+
+    # ---- advance ----
+    def advance(self, T, p, Y, dt, status, nsteps=None, opts=None, stream=None, n=None):
+        o = opts if opts is not None else default_opts()
+        n = T.numel() if n is None else n
+        _check(lib.chemk_advance(self.handle, n, _ptr(T), _ptr(p), _ptr(Y), float(dt),
+                                 C.byref(o), _ptr(status), _ptr(nsteps), _stream(stream)))
+
+    def autotune(self, T, p, Y, dt, opts=None, stream=None):
+        o = opts if opts is not None else default_opts()
+        best = (C.c_int32 * 2)()
+        ms = C.c_double()
+        _check(lib.chemk_autotune(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y), float(dt),
+                                  C.byref(o), best, C.byref(ms), _stream(stream)))
+        return int(best[0]), int(best[1]), ms.value
+
+    def last_counters(self, stream=None):
+        out = (C.c_int64 * 3)()
+        _check(lib.chemk_last_counters(self.handle, out, _stream(stream)))
+        return {"routed": out[0], "di_steps": out[1], "failed": out[2]}
+
+    PHASES = ("di", "binning", "ingest", "mlp", "post", "fallback")
+
+    def timing(self, enable=True):
+        _check(lib.chemk_timing(self.handle, int(bool(enable))))
+
+    def timing_read(self, stream=None):
+        ms = (C.c_double * 6)()
+        nl = (C.c_int64 * 6)()
+        _check(lib.chemk_timing_read(self.handle, ms, nl, _stream(stream)))
+        return {ph: (ms[i], nl[i]) for i, ph in enumerate(self.PHASES)}
+
+    # ---- learned part ----
+    def ann_create(self, dims):
+        d = (C.c_int32 * len(dims))(*dims)
+        _check(lib.chemk_ann_create(self.handle, d, len(dims) - 1))
+        self.dims = list(dims)
+
+    def ann_param_count(self):
+        c = C.c_int64()
+        _check(lib.chemk_ann_param_count(self.handle, C.byref(c)))
+        return c.value
+
+    def ann_set_weights(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, np.float32)
+        _check(lib.chemk_ann_set_weights(self.handle, p.ctypes.data, p.size))
+
+    def ann_get_weights(self):
+        n = self.ann_param_count()
+        p = np.zeros(n, np.float32)
+        _check(lib.chemk_ann_get_weights(self.handle, p.ctypes.data, n))
+        return p
+
+    def ann_set_norm(self, mu_x, sd_x, mu_y, sd_y, dt):
+        arrs = [np.ascontiguousarray(a, np.float64) for a in (mu_x, sd_x, mu_y, sd_y)]
+        _check(lib.chemk_ann_set_norm(self.handle, *(a.ctypes.data for a in arrs), float(dt)))
+
+    def ann_get_norm(self):
+        F, K = self.K + 2, self.K
+        mx, sx, my, sy = np.zeros(F), np.zeros(F), np.zeros(K), np.zeros(K)
+        dt = C.c_double()
+        _check(lib.chemk_ann_get_norm(self.handle, mx.ctypes.data, sx.ctypes.data,
+                                      my.ctypes.data, sy.ctypes.data, C.byref(dt)))
+        return mx, sx, my, sy, dt.value
+
+    def ann_set_envelope(self, lo, hi, neg_tol):
+        lo = np.ascontiguousarray(lo, np.float64)
+        hi = np.ascontiguousarray(hi, np.float64)
+        _check(lib.chemk_ann_set_envelope(self.handle, lo.ctypes.data, hi.ctypes.data,
+                                          float(neg_tol)))
+
+    def ann_get_envelope(self):
+        F = self.K + 2
+        lo, hi = np.zeros(F), np.zeros(F)
+        nt = C.c_double()
+        _check(lib.chemk_ann_get_envelope(self.handle, lo.ctypes.data, hi.ctypes.data,
+                                          C.byref(nt)))
+        return lo, hi, nt.value
+
+    def ann_fit_norm(self, T, p, Y, Y_next, dt, widen=0.02, neg_tol=1e-6, stream=None):
+        _check(lib.chemk_ann_fit_norm(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y),
+                                      _ptr(Y_next), float(dt), float(widen), float(neg_tol),
+                                      _stream(stream)))
+
+    def ann_pack(self, T, p, Y, Y_next, X, Z, stream=None):
+        _check(lib.chemk_ann_pack(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y),
+                                  _ptr(Y_next), _ptr(X), _ptr(Z), _stream(stream)))
+
+    def ann_forward_packed(self, X, out, n=None, stream=None):
+        n = X.shape[0] if n is None else n
+        _check(lib.chemk_ann_forward_packed(self.handle, n, _ptr(X), _ptr(out), _stream(stream)))
+
+    def ann_train_step(self, idx, X, Z, lr, update=True, loss=None, grads=None, stream=None):
+        _check(lib.chemk_ann_train_step(self.handle, _ptr(idx), idx.numel(), _ptr(X), _ptr(Z),
+                                        float(lr), int(bool(update)), _ptr(loss), _ptr(grads),
+                                        _stream(stream)))
+
+    def ann_reset_optimizer(self):
+        _check(lib.chemk_ann_reset_optimizer(self.handle))

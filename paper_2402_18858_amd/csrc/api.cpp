@@ -1,0 +1,647 @@
+// api.cpp -- the C ABI: argument validation, mechanism tables, contexts, the
+// DI/ANN step sequencing, graph capture and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "chemk.h"
+#include "chemk_dev.h"
+#include "chemk_internal.h"
+#include "ann_internal.h"
+
+using namespace chemk;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(CHEMK_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                            \
+    } while (0)
+
+extern "C" const char *chemk_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// mechanism (host copy)
+// ---------------------------------------------------------------------------
+struct chemk_mech {
+    int E = 0, K = 0, R = 0;
+    std::vector<double> emass, nasa, lnA, beta, Ea;
+    std::vector<int> comp, reac, prod, tb, rev;
+};
+
+extern "C" int chemk_mech_create(const chemk_mech_desc *d, chemk_mech **out) {
+    g_err.clear();
+    if (!d || !out) return fail(CHEMK_E_ARG, "null descriptor or output pointer");
+    *out = nullptr;
+    const int E = d->n_elements, K = d->n_species, R = d->n_reactions;
+    if (E < 1 || E > CHEMK_MAX_ELEMENTS)
+        return fail(CHEMK_E_MECH, "n_elements=%d outside [1, %d]", E, CHEMK_MAX_ELEMENTS);
+    if (K < 1 || K > CHEMK_MAX_SPECIES)
+        return fail(CHEMK_E_MECH, "n_species=%d outside [1, %d]", K, CHEMK_MAX_SPECIES);
+    if (R < 0 || R > CHEMK_MAX_REACTIONS)
+        return fail(CHEMK_E_MECH, "n_reactions=%d outside [0, %d]", R, CHEMK_MAX_REACTIONS);
+    if (!d->element_mass || !d->composition || !d->nasa7)
+        return fail(CHEMK_E_ARG, "null element_mass / composition / nasa7");
+    if (R > 0 && (!d->reactants || !d->products || !d->log_A || !d->beta || !d->Ea ||
+                  !d->third_body || !d->reversible))
+        return fail(CHEMK_E_ARG, "null reaction array");
+    auto m = std::make_unique<chemk_mech>();
+    m->E = E;
+    m->K = K;
+    m->R = R;
+    m->emass.assign(d->element_mass, d->element_mass + E);
+    m->comp.assign(d->composition, d->composition + (size_t)K * E);
+    m->nasa.assign(d->nasa7, d->nasa7 + (size_t)K * 7);
+    for (int e = 0; e < E; ++e)
+        if (!(std::isfinite(m->emass[e]) && m->emass[e] > 0))
+            return fail(CHEMK_E_MECH, "element %d: mass must be finite and > 0", e);
+    for (int k = 0; k < K; ++k) {
+        int atoms = 0;
+        for (int e = 0; e < E; ++e) {
+            if (m->comp[k * E + e] < 0)
+                return fail(CHEMK_E_MECH, "species %d: negative atom count", k);
+            atoms += m->comp[k * E + e];
+        }
+        if (atoms == 0) return fail(CHEMK_E_MECH, "species %d has no atoms", k);
+        for (int j = 0; j < 7; ++j)
+            if (!std::isfinite(m->nasa[k * 7 + j]))
+                return fail(CHEMK_E_MECH, "species %d: non-finite NASA-7 coefficient", k);
+    }
+    if (R > 0) {
+        m->reac.assign(d->reactants, d->reactants + 2 * R);
+        m->prod.assign(d->products, d->products + 2 * R);
+        m->lnA.assign(d->log_A, d->log_A + R);
+        m->beta.assign(d->beta, d->beta + R);
+        m->Ea.assign(d->Ea, d->Ea + R);
+        m->tb.assign(d->third_body, d->third_body + R);
+        m->rev.assign(d->reversible, d->reversible + R);
+    }
+    for (int j = 0; j < R; ++j) {
+        int nr = 0, np = 0;
+        std::vector<long> bal(E, 0);
+        for (int i = 0; i < 2; ++i) {
+            const int a = m->reac[2 * j + i], b = m->prod[2 * j + i];
+            if (a < -1 || a >= K || b < -1 || b >= K)
+                return fail(CHEMK_E_MECH, "reaction %d: species index out of range", j);
+            if (a >= 0) {
+                ++nr;
+                for (int e = 0; e < E; ++e) bal[e] -= m->comp[a * E + e];
+            }
+            if (b >= 0) {
+                ++np;
+                for (int e = 0; e < E; ++e) bal[e] += m->comp[b * E + e];
+            }
+        }
+        if (m->reac[2 * j] < 0 || m->prod[2 * j] < 0)
+            return fail(CHEMK_E_MECH, "reaction %d: slot 0 of each side must be filled", j);
+        (void)nr;
+        (void)np;
+        for (int e = 0; e < E; ++e)
+            if (bal[e] != 0)
+                return fail(CHEMK_E_MECH, "reaction %d does not conserve element %d", j, e);
+        if (!std::isfinite(m->lnA[j]) || !std::isfinite(m->beta[j]) || !std::isfinite(m->Ea[j]))
+            return fail(CHEMK_E_MECH, "reaction %d: non-finite Arrhenius parameter", j);
+        if ((m->tb[j] != 0 && m->tb[j] != 1) || (m->rev[j] != 0 && m->rev[j] != 1))
+            return fail(CHEMK_E_MECH, "reaction %d: flags must be 0 or 1", j);
+    }
+    *out = m.release();
+    return CHEMK_OK;
+}
+
+extern "C" void chemk_mech_free(chemk_mech *m) { delete m; }
+
+extern "C" int chemk_mech_info(const chemk_mech *m, int32_t *K, int32_t *R, int32_t *E) {
+    if (!m) return fail(CHEMK_E_ARG, "null mechanism");
+    if (K) *K = m->K;
+    if (R) *R = m->R;
+    if (E) *E = m->E;
+    return CHEMK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct GraphKey {
+    int64_t n;
+    const void *T, *p, *Y, *st, *ns;
+    double dt;
+    int mode, bins, wpc, max_steps, project;
+    double rtol, atolY, atolT, h0;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(n, T, p, Y, st, ns, dt, mode, bins, wpc, max_steps, project, rtol, atolY,
+                        atolT, h0) < std::tie(o.n, o.T, o.p, o.Y, o.st, o.ns, o.dt, o.mode, o.bins,
+                                              o.wpc, o.max_steps, o.project, o.rtol, o.atolY,
+                                              o.atolT, o.h0);
+    }
+};
+
+struct chemk_ctx {
+    int device = 0;
+    int cu_count = 256;
+    int K = 0, R = 0, E = 0, N = 0;
+    DevMech dm{};
+    void *tables = nullptr;
+    // DI scratch, grown on demand
+    int64_t cap = 0;
+    int *bin = nullptr, *queue = nullptr;
+    int *small = nullptr;                 // [0] counter, [1] n_items, [2..] hist/offs
+    unsigned long long *stats = nullptr;  // [0] routed, [1] steps, [2] failed
+    int tuned_bins = 0, tuned_wpc = 0;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    AnnState *ann = nullptr;
+    PhaseTimer timer;
+};
+
+static constexpr int kMaxBins = 256;
+
+// accessors for the learned part (ann.hip)
+AnnState *&ctx_ann(chemk_ctx *c) { return c->ann; }
+int ctx_device(chemk_ctx *c) { return c->device; }
+int ctx_K(chemk_ctx *c) { return c->K; }
+void ctx_set_error(const char *msg) { g_err = msg; }
+chemk::DevMech ctx_devmech(chemk_ctx *c) { return c->dm; }
+
+static int set_device(chemk_ctx *c) {
+    HIP_TRY(hipSetDevice(c->device));
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_ctx_create(int device, const chemk_mech *m, chemk_ctx **out) {
+    g_err.clear();
+    if (!m || !out) return fail(CHEMK_E_ARG, "null mechanism or output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(CHEMK_E_ARG, "device %d outside [0, %d)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(CHEMK_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950",
+                    device, prop.gcnArchName);
+    auto c = std::make_unique<chemk_ctx>();
+    c->device = device;
+    c->cu_count = prop.multiProcessorCount;
+    c->K = m->K;
+    c->R = m->R;
+    c->E = m->E;
+    c->N = m->K + 1;
+    const int K = m->K, R = m->R, E = m->E;
+    if (di_template_N(c->N) < 0) return fail(CHEMK_E_UNSUPPORTED, "K=%d too large", K);
+    if (di_lds_bytes(K, R, di_template_N(c->N)) > 64 * 1024)
+        return fail(CHEMK_E_UNSUPPORTED, "mechanism needs %zu bytes of LDS per wave (> 64 KiB)",
+                    di_lds_bytes(K, R, di_template_N(c->N)));
+
+    // host-side tables
+    std::vector<double> W(K), invW(K);
+    for (int k = 0; k < K; ++k) {
+        double w = 0;
+        for (int e = 0; e < E; ++e) w += m->comp[k * E + e] * m->emass[e];
+        W[k] = w;
+        invW[k] = 1.0 / w;
+    }
+    std::vector<int4> rsp(std::max(R, 1));
+    std::vector<double4> rpar(std::max(R, 1));
+    std::vector<int4> rflag(std::max(R, 1));
+    std::vector<std::vector<std::pair<int, double>>> inc(K);
+    for (int j = 0; j < R; ++j) {
+        int a0 = m->reac[2 * j], a1 = m->reac[2 * j + 1], p0 = m->prod[2 * j],
+            p1 = m->prod[2 * j + 1];
+        // keep filled slots first
+        if (a0 < 0) std::swap(a0, a1);
+        if (p0 < 0) std::swap(p0, p1);
+        rsp[j] = make_int4(a0, a1, p0, p1);
+        const int nf = (a0 >= 0) + (a1 >= 0), nr = (p0 >= 0) + (p1 >= 0);
+        rpar[j] = make_double4(m->lnA[j], m->beta[j], m->Ea[j] / RC_CAL, 0.0);
+        rflag[j] = make_int4(m->tb[j], m->rev[j], nr - nf, nf + 16 * nr);
+        std::map<int, double> nu;
+        if (a0 >= 0) nu[a0] -= 1;
+        if (a1 >= 0) nu[a1] -= 1;
+        if (p0 >= 0) nu[p0] += 1;
+        if (p1 >= 0) nu[p1] += 1;
+        for (auto &kv : nu)
+            if (kv.second != 0.0) inc[kv.first].push_back({j, kv.second});
+    }
+    std::vector<int> inc_start(K + 1, 0), inc_r;
+    std::vector<double> inc_nu;
+    for (int k = 0; k < K; ++k) {
+        inc_start[k + 1] = inc_start[k] + (int)inc[k].size();
+        for (auto &pr : inc[k]) {
+            inc_r.push_back(pr.first);
+            inc_nu.push_back(pr.second);
+        }
+    }
+    if (inc_r.empty()) {
+        inc_r.push_back(0);
+        inc_nu.push_back(0.0);
+    }
+    std::vector<double> Emat((size_t)E * K);
+    for (int e = 0; e < E; ++e)
+        for (int k = 0; k < K; ++k) Emat[e * K + k] = m->comp[k * E + e] * m->emass[e] / W[k];
+
+    // one device allocation, 256-byte aligned pieces
+    struct Piece {
+        const void *src;
+        size_t bytes;
+        size_t off;
+    };
+    std::vector<Piece> pcs = {
+        {W.data(), W.size() * 8, 0},
+        {invW.data(), invW.size() * 8, 0},
+        {m->nasa.data(), m->nasa.size() * 8, 0},
+        {rsp.data(), rsp.size() * sizeof(int4), 0},
+        {rpar.data(), rpar.size() * sizeof(double4), 0},
+        {rflag.data(), rflag.size() * sizeof(int4), 0},
+        {inc_start.data(), inc_start.size() * 4, 0},
+        {inc_r.data(), inc_r.size() * 4, 0},
+        {inc_nu.data(), inc_nu.size() * 8, 0},
+        {Emat.data(), Emat.size() * 8, 0}};
+    size_t tot = 0;
+    for (auto &pc : pcs) {
+        pc.off = tot;
+        tot += (pc.bytes + 255) & ~size_t(255);
+    }
+    std::vector<char> host(tot, 0);
+    for (auto &pc : pcs) std::memcpy(host.data() + pc.off, pc.src, pc.bytes);
+    if (hipMalloc(&c->tables, tot) != hipSuccess)
+        return fail(CHEMK_E_OOM, "hipMalloc(%zu) for mechanism tables failed", tot);
+    HIP_TRY(hipMemcpy(c->tables, host.data(), tot, hipMemcpyHostToDevice));
+    char *b = (char *)c->tables;
+    DevMech &dm = c->dm;
+    dm.K = K;
+    dm.R = R;
+    dm.E = E;
+    dm.N = K + 1;
+    dm.W = (const double *)(b + pcs[0].off);
+    dm.invW = (const double *)(b + pcs[1].off);
+    dm.nasa = (const double *)(b + pcs[2].off);
+    dm.rsp = (const int4 *)(b + pcs[3].off);
+    dm.rpar = (const double4 *)(b + pcs[4].off);
+    dm.rflag = (const int4 *)(b + pcs[5].off);
+    dm.inc_start = (const int *)(b + pcs[6].off);
+    dm.inc_r = (const int *)(b + pcs[7].off);
+    dm.inc_nu = (const double *)(b + pcs[8].off);
+    dm.Emat = (const double *)(b + pcs[9].off);
+
+    if (hipMalloc(&c->small, sizeof(int) * (2 + 2 * kMaxBins)) != hipSuccess ||
+        hipMalloc(&c->stats, sizeof(unsigned long long) * 4) != hipSuccess)
+        return fail(CHEMK_E_OOM, "hipMalloc of context counters failed");
+    HIP_TRY(hipMemset(c->stats, 0, sizeof(unsigned long long) * 4));
+    *out = c.release();
+    return CHEMK_OK;
+}
+
+extern "C" void chemk_ctx_free(chemk_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second);
+    ann_destroy(c->ann);
+    hipFree(c->tables);
+    hipFree(c->bin);
+    hipFree(c->queue);
+    hipFree(c->small);
+    hipFree(c->stats);
+    delete c;
+}
+
+static int ensure_capacity(chemk_ctx *c, int64_t n) {
+    if (n <= c->cap) return CHEMK_OK;
+    hipFree(c->bin);
+    hipFree(c->queue);
+    c->bin = c->queue = nullptr;
+    c->cap = 0;
+    if (hipMalloc(&c->bin, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&c->queue, sizeof(int) * n) != hipSuccess)
+        return fail(CHEMK_E_OOM, "hipMalloc of DI queues for %lld cells failed", (long long)n);
+    c->cap = n;
+    // graphs captured with the old queues are stale
+    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    return CHEMK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// properties
+// ---------------------------------------------------------------------------
+static int check_n(int64_t n) {
+    if (n < 0) return fail(CHEMK_E_ARG, "n=%lld < 0", (long long)n);
+    if (n > (int64_t)std::numeric_limits<int>::max())
+        return fail(CHEMK_E_UNSUPPORTED, "n=%lld above 2^31-1", (long long)n);
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_thermo(chemk_ctx *c, int64_t n, const double *T, const double *Y,
+                            double *cp, double *h, void *stream) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    if (int r = check_n(n)) return r;
+    if (n == 0) return CHEMK_OK;
+    if (!T || !Y || !cp || !h) return fail(CHEMK_E_ARG, "null array");
+    if (int r = set_device(c)) return r;
+    HIP_TRY(launch_thermo(c->dm, n, T, Y, cp, h, (hipStream_t)stream));
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_T_from_h(chemk_ctx *c, int64_t n, const double *h, const double *Y,
+                              double *T, int32_t *status, void *stream) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    if (int r = check_n(n)) return r;
+    if (n == 0) return CHEMK_OK;
+    if (!T || !Y || !h || !status) return fail(CHEMK_E_ARG, "null array");
+    if (int r = set_device(c)) return r;
+    HIP_TRY(launch_T_from_h(c->dm, n, h, Y, T, status, (hipStream_t)stream));
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_rhs(chemk_ctx *c, int64_t n, const double *T, const double *p,
+                         const double *Y, double *dydt, void *stream) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    if (int r = check_n(n)) return r;
+    if (n == 0) return CHEMK_OK;
+    if (!T || !p || !Y || !dydt) return fail(CHEMK_E_ARG, "null array");
+    if (int r = set_device(c)) return r;
+    HIP_TRY(launch_rhs(c->dm, n, T, p, Y, dydt, (hipStream_t)stream));
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_jacobian(chemk_ctx *c, int64_t n, const double *T, const double *p,
+                              const double *Y, double *J, void *stream) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    if (int r = check_n(n)) return r;
+    if (n == 0) return CHEMK_OK;
+    if (!T || !p || !Y || !J) return fail(CHEMK_E_ARG, "null array");
+    if (int r = set_device(c)) return r;
+    HIP_TRY(launch_jacobian(c->dm, n, T, p, Y, J, (hipStream_t)stream));
+    return CHEMK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// advance
+// ---------------------------------------------------------------------------
+extern "C" void chemk_opts_default(chemk_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->mode = CHEMK_MODE_DI;
+    o->max_steps = 100000;
+    o->rtol = 1e-7;
+    o->atol_Y = 1e-14;
+    o->atol_T = 1e-6;
+    o->h0_frac = 1e-3;
+    o->bins = 0;
+    o->waves_per_cu = 0;
+    o->use_graph = 0;
+    o->project = 1;
+}
+
+static int check_opts(const chemk_opts *o) {
+    if (!o) return fail(CHEMK_E_ARG, "null options");
+    if (o->mode != CHEMK_MODE_DI && o->mode != CHEMK_MODE_ANN)
+        return fail(CHEMK_E_ARG, "mode=%d unknown", o->mode);
+    if (!(o->rtol > 0 && o->rtol < 1)) return fail(CHEMK_E_ARG, "rtol must be in (0, 1)");
+    if (!(o->atol_Y >= 0) || !(o->atol_T >= 0)) return fail(CHEMK_E_ARG, "atol must be >= 0");
+    if (!(o->h0_frac > 0 && o->h0_frac <= 1)) return fail(CHEMK_E_ARG, "h0_frac must be in (0, 1]");
+    if (o->max_steps < 1) return fail(CHEMK_E_ARG, "max_steps must be >= 1");
+    if (o->bins < 0 || o->bins > kMaxBins)
+        return fail(CHEMK_E_ARG, "bins=%d outside [0, %d]", o->bins, kMaxBins);
+    if (o->waves_per_cu < 0 || o->waves_per_cu > 32)
+        return fail(CHEMK_E_ARG, "waves_per_cu=%d outside [0, 32]", o->waves_per_cu);
+    return CHEMK_OK;
+}
+
+static void resolve_tuning(const chemk_ctx *c, const chemk_opts *o, int &bins, int &wpc) {
+    bins = o->bins > 0 ? o->bins : (c->tuned_bins > 0 ? c->tuned_bins : 16);
+    wpc = o->waves_per_cu > 0 ? o->waves_per_cu : (c->tuned_wpc > 0 ? c->tuned_wpc : 8);
+}
+
+// Enqueue the DI step over all n cells.  queue order from the stiffness bins.
+static int enqueue_di(chemk_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
+                      const chemk_opts *o, int bins, int wpc, int32_t *status, int32_t *nsteps,
+                      hipStream_t s) {
+    int *counter = c->small, *n_items = c->small + 1;
+    int *hist = c->small + 2, *offs = c->small + 2 + kMaxBins;
+    HIP_TRY(launch_zero_u64(c->stats, 4, s));
+    HIP_TRY(launch_zero_ints(counter, 1, s));
+    HIP_TRY(launch_set_int(n_items, (int)n, s));
+    const int *queue = nullptr;
+    if (bins > 1) {
+        c->timer.begin(CHEMK_PHASE_BINNING, s);
+        HIP_TRY(launch_binning(c->dm, (int)n, T, p, Y, dt, bins, c->bin, hist, offs, c->queue, s));
+        c->timer.end(CHEMK_PHASE_BINNING, s);
+        queue = c->queue;
+    }
+    const int64_t grid64 = std::min<int64_t>(n, (int64_t)c->cu_count * wpc);
+    c->timer.begin(CHEMK_PHASE_DI, s);
+    HIP_TRY(launch_di(c->dm, (int)grid64, n_items, queue, counter, T, p, Y, dt, o->rtol,
+                      o->atol_Y, o->atol_T, o->h0_frac, o->max_steps, o->project, status, nsteps,
+                      c->stats, 0, s));
+    c->timer.end(CHEMK_PHASE_DI, s);
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p, double *Y,
+                             double dt, const chemk_opts *o, int32_t *status, int32_t *nsteps,
+                             void *stream) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    if (int r = check_n(n)) return r;
+    if (int r = check_opts(o)) return r;
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEMK_E_ARG, "dt must be finite and > 0");
+    if (n == 0) return CHEMK_OK;
+    if (!T || !p || !Y || !status) return fail(CHEMK_E_ARG, "null array");
+    if (o->mode == CHEMK_MODE_ANN) {
+        if (!c->ann || !ann_ready(c->ann))
+            return fail(CHEMK_E_STATE, "ANN mode needs chemk_ann_create, weights and norm first");
+        const double tdt = ann_dt(c->ann);
+        if (!(std::fabs(dt - tdt) <= 1e-12 * std::fabs(tdt)))
+            return fail(CHEMK_E_DT, "dt=%.17g differs from the trained dt=%.17g", dt, tdt);
+    }
+    if (int r = set_device(c)) return r;
+    if (int r = ensure_capacity(c, n)) return r;
+    hipStream_t s = (hipStream_t)stream;
+    int bins, wpc;
+    resolve_tuning(c, o, bins, wpc);
+
+    auto enqueue = [&]() -> int {
+        if (o->mode == CHEMK_MODE_DI)
+            return enqueue_di(c, n, T, p, Y, dt, o, bins, wpc, status, nsteps, s);
+        AnnStepArgs a{n, T, p, Y, dt, o->rtol, o->atol_Y, o->atol_T, o->h0_frac, o->max_steps,
+                      o->project, status, nsteps, c->cu_count * wpc, c->queue, c->small,
+                      c->small + 1, c->stats, &c->dm, &c->timer};
+        hipError_t e = ann_enqueue_step(c->ann, a, s);
+        if (e != hipSuccess)
+            return fail(CHEMK_E_HIP, "ANN step: %s", hipGetErrorString(e));
+        return CHEMK_OK;
+    };
+    if (!o->use_graph || c->timer.on) return enqueue();
+
+    GraphKey key{n, T, p, Y, status, nsteps, dt, o->mode, bins, wpc, o->max_steps, o->project,
+                 o->rtol, o->atol_Y, o->atol_T, o->h0_frac};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        hipStream_t cs = s;
+        hipStream_t own = nullptr;
+        if (!cs) {   // capture needs a non-default stream
+            HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+            cs = own;
+        }
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipStream_t saved = s;
+        s = cs;
+        int r = enqueue();
+        s = saved;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (own) hipStreamDestroy(own);
+        if (r) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(CHEMK_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(CHEMK_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        it = c->graphs.emplace(key, ge).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, s));
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_last_counters(chemk_ctx *c, int64_t out[3], void *stream) {
+    g_err.clear();
+    if (!c || !out) return fail(CHEMK_E_ARG, "null argument");
+    if (int r = set_device(c)) return r;
+    unsigned long long h[4];
+    HIP_TRY(hipMemcpyAsync(h, c->stats, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    for (int i = 0; i < 3; ++i) out[i] = (int64_t)h[i];
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_timing(chemk_ctx *c, int32_t enable) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    c->timer.on = enable != 0;
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_timing_read(chemk_ctx *c, double ms[CHEMK_NUM_PHASES],
+                                 int64_t launches[CHEMK_NUM_PHASES], void *stream) {
+    g_err.clear();
+    if (!c || !ms || !launches) return fail(CHEMK_E_ARG, "null argument");
+    if (int r = set_device(c)) return r;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    for (int p = 0; p < CHEMK_NUM_PHASES; ++p) {
+        double acc = 0.0;
+        for (auto &pr : c->timer.done[p]) {
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+            acc += t;
+        }
+        ms[p] = acc;
+        launches[p] = (int64_t)c->timer.done[p].size();
+    }
+    c->timer.release_all();
+    return CHEMK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: grid over (bins, waves per CU) on copies of the state
+// ---------------------------------------------------------------------------
+extern "C" int chemk_autotune(chemk_ctx *c, int64_t n, const double *T, const double *p,
+                              const double *Y, double dt, const chemk_opts *o, int32_t best[2],
+                              double *best_ms, void *stream) {
+    g_err.clear();
+    if (!c || !best) return fail(CHEMK_E_ARG, "null argument");
+    if (int r = check_n(n)) return r;
+    if (int r = check_opts(o)) return r;
+    if (n == 0 || !T || !p || !Y) return fail(CHEMK_E_ARG, "autotune needs cells");
+    if (int r = set_device(c)) return r;
+    if (int r = ensure_capacity(c, n)) return r;
+    hipStream_t s = (hipStream_t)stream;
+    const int K = c->K;
+    double *Tc = nullptr, *Yc = nullptr;
+    int *st = nullptr;
+    if (hipMalloc(&Tc, 8 * n) != hipSuccess || hipMalloc(&Yc, 8 * n * K) != hipSuccess ||
+        hipMalloc(&st, 4 * n) != hipSuccess) {
+        hipFree(Tc);
+        hipFree(Yc);
+        hipFree(st);
+        return fail(CHEMK_E_OOM, "autotune copies");
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int bins_grid[] = {1, 8, 32};
+    const int wpc_grid[] = {4, 8, 12};
+    double bestt = 1e300;
+    int bb = 16, bw = 8;
+    chemk_opts oo = *o;
+    oo.mode = CHEMK_MODE_DI;
+    oo.use_graph = 0;
+    int rc = CHEMK_OK;
+    for (int b : bins_grid)
+        for (int w : wpc_grid) {
+            if (hipMemcpyAsync(Tc, T, 8 * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(Yc, Y, 8 * n * K, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                rc = fail(CHEMK_E_HIP, "autotune copy");
+                goto done;
+            }
+            hipEventRecord(e0, s);
+            if ((rc = enqueue_di(c, n, Tc, p, Yc, dt, &oo, b, w, st, nullptr, s))) goto done;
+            hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(CHEMK_E_HIP, "autotune sync");
+                goto done;
+            }
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < bestt) {
+                bestt = ms;
+                bb = b;
+                bw = w;
+            }
+        }
+    c->tuned_bins = bb;
+    c->tuned_wpc = bw;
+    best[0] = bb;
+    best[1] = bw;
+    if (best_ms) *best_ms = bestt;
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(Tc);
+    hipFree(Yc);
+    hipFree(st);
+    return rc;
+}

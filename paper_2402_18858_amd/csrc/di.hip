@@ -1,0 +1,557 @@
+// di.hip -- direct integration (DI) of the per-cell kinetics ODEs (Eq. 1) over one
+// flow step (Eq. 2) on gfx950.
+//
+// Design: one wavefront per cell.  Lane i < N holds component i of
+// y = (Y_1..Y_K, T) and row i of the iteration matrix (1/(h gamma)) I - J in
+// registers (N is a template parameter so the row is a register array).  The
+// Jacobian is assembled in the wave's LDS slice, LU with partial pivoting
+// broadcasts each pivot row through LDS and keeps the permutation implicit,
+// and the triangular solves broadcast one solution component per step.
+// Integrator: RODAS (Hairer & Wanner, Solving ODEs II, Sec. VI.4), the
+// stiffly accurate Rosenbrock method of order 4 with an embedded order-3
+// estimate, in its transformed form; weighted-RMS error control.
+// Scheduling: a persistent grid pulls cells from a queue with one atomic per
+// cell; the queue is ordered by a stiffness estimate (expensive bins first)
+// so that the tail of the launch is short.
+#include "chemk_dev.h"
+#include "chemk_internal.h"
+
+namespace chemk {
+
+// RODAS coefficients, transformed form (published values, Hairer & Wanner).
+__constant__ double kA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.544, 0, 0, 0, 0},
+    {0.9466785280815826, 0.2557011698983284, 0, 0, 0},
+    {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0}};
+__constant__ double kC[6][5] = {
+    {0, 0, 0, 0, 0},
+    {-5.6688, 0, 0, 0, 0},
+    {-2.430093356833875, -0.2063599157091915, 0, 0, 0},
+    {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0},
+    {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160, 0},
+    {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
+     -6.058818238834054}};
+constexpr double kGamma = 0.25;
+
+// ---------------------------------------------------------------------------
+// dense LU of the iteration matrix, one row per lane, implicit pivoting.
+// On return a[] of the lane that was chosen at step k holds U row k (columns
+// >= k) and its L multipliers (columns < k); piv[k] = that lane; mystep = k.
+// Returns false if a pivot is exactly zero.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ bool wave_lu(double (&a)[N], int &mystep, const Lds &L) {
+    const int lane = lane_id();
+    mystep = lane < N ? N : -1;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const bool open = mystep == N;
+        const int p = wave_argmax(fabs(a[k]), open);
+        if (lane == p) {
+            mystep = k;
+            L.piv[k] = p;
+        }
+        const double pv = bcast(a[k], p);
+        if (pv == 0.0) ok = false;
+        // rows not yet chosen eliminate column k; chosen rows see l = 0
+        const double l = open ? a[k] / pv : 0.0;
+        a[k] = open ? l : a[k];
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) a[j] = fma(-l, bcast(a[j], p), a[j]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_sync();
+    return ok;
+}
+
+// Store the factors to LDS (row of lane i at L.J[i*ld], overwriting the
+// Jacobian) and return 1/U_kk for the lane that pivoted at step k.
+template <int N>
+__device__ __forceinline__ double wave_store_lu(const double (&a)[N], int mystep, const Lds &L) {
+    const int lane = lane_id();
+    double rd = 0.0;
+    if (lane < N) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            L.J[lane * L.ld + j] = a[j];
+            if (j == mystep) rd = 1.0 / a[j];
+        }
+    }
+    wave_sync();
+    return rd;
+}
+
+// Solve (LU) x = b with the factors in LDS; b is this lane's component and the
+// solution component of lane i is returned in lane i.
+__device__ __forceinline__ double wave_solve(const Lds &L, int n, int mystep, double rdiag,
+                                             double b) {
+    const int lane = lane_id();
+    const double *row = L.J + lane * L.ld;
+    // forward: the lane that pivoted at step k holds z_k; later rows subtract l z_k
+#pragma unroll 1
+    for (int k = 0; k < n; ++k) {
+        const int p = uniform(L.piv[k]);
+        const double z = bcast(b, p);
+        if (mystep > k) b -= row[k] * z;
+    }
+    // backward: x_k = z_k / U_kk in the pivot lane; earlier pivot rows subtract
+    double x = 0.0;
+#pragma unroll 1
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = uniform(L.piv[k]);
+        const double xk = bcast(b * rdiag, p);
+        if (mystep >= 0 && mystep < k) b -= row[k] * xk;
+        if (lane == k) x = xk;
+    }
+    return x;
+}
+
+struct DIParams {
+    double rtol, atolY, atolT, h0_frac;
+    int max_steps, project;
+};
+
+// Element projection of the lane's Y_k onto the element masses of Yin
+// (weights w_k = max(Y_k, 1e-30)):  Y <- Y - w E^T (E w E^T)^-1 (E Y - E Yin).
+// The E x E system is assembled with wave sums, solved by lane 0 in LDS
+// (partial pivoting) and the multipliers are read back by every lane.
+__device__ __forceinline__ double wave_project(const DevMech &m, const Lds &L, double Yk,
+                                               double Yin) {
+    const int lane = lane_id();
+    const int K = m.K, E = m.E;
+    const bool sp = lane < K;
+    const double w = sp ? fmax(Yk, 1e-30) : 0.0;
+    double *A = L.u;    // [E*E]
+    double *r = L.hs;   // [E]
+    for (int a = 0; a < E; ++a) {
+        const double Ea = sp ? m.Emat[a * K + lane] : 0.0;
+        const double ra = wave_sum(Ea * Yk) - wave_sum(Ea * Yin);
+        if (lane == 0) r[a] = ra;
+        for (int b = a; b < E; ++b) {
+            const double Eb = sp ? m.Emat[b * K + lane] : 0.0;
+            const double v = wave_sum(Ea * w * Eb);
+            if (lane == 0) {
+                A[a * E + b] = v;
+                A[b * E + a] = v;
+            }
+        }
+    }
+    wave_sync();
+    if (lane == 0) {
+        bool ok = true;
+        for (int k = 0; k < E && ok; ++k) {
+            int p = k;
+            double best = fabs(A[k * E + k]);
+            for (int i = k + 1; i < E; ++i)
+                if (fabs(A[i * E + k]) > best) {
+                    best = fabs(A[i * E + k]);
+                    p = i;
+                }
+            if (best == 0.0) {
+                ok = false;
+                break;
+            }
+            if (p != k) {
+                for (int j = 0; j < E; ++j) {
+                    const double t = A[k * E + j];
+                    A[k * E + j] = A[p * E + j];
+                    A[p * E + j] = t;
+                }
+                const double t = r[k];
+                r[k] = r[p];
+                r[p] = t;
+            }
+            for (int i = k + 1; i < E; ++i) {
+                const double l = A[i * E + k] / A[k * E + k];
+                for (int j = k; j < E; ++j) A[i * E + j] -= l * A[k * E + j];
+                r[i] -= l * r[k];
+            }
+        }
+        if (ok) {
+            for (int i = E - 1; i >= 0; --i) {
+                for (int j = i + 1; j < E; ++j) r[i] -= A[i * E + j] * r[j];
+                r[i] /= A[i * E + i];
+            }
+        } else {
+            for (int i = 0; i < E; ++i) r[i] = 0.0;
+        }
+    }
+    wave_sync();
+    double acc = 0.0;
+    for (int e = 0; e < E; ++e) acc += (sp ? m.Emat[e * K + lane] : 0.0) * r[e];
+    wave_sync();
+    return sp ? Yk - w * acc : Yk;
+}
+
+// Mixture enthalpy h/R [K mol/g] and cp/R [mol/g] (per unit mass, R factored out).
+__device__ __forceinline__ void wave_h_cp(const DevMech &m, double T, double Yk, double &hR,
+                                          double &cR) {
+    const int lane = lane_id();
+    double cpR = 0.0, hRT = 0.0, iw = 0.0;
+    const double invT = 1.0 / T;
+    if (lane < m.K) {
+        sp_cp_h(m.nasa + 7 * lane, T, invT, cpR, hRT);
+        iw = m.invW[lane];
+    }
+    hR = wave_sum(Yk * hRT * iw) * T;
+    cR = wave_sum(Yk * cpR * iw);
+}
+
+// Newton on h(T) = h0 then bisection on [200, 4000] K (same rule as the
+// property kernel).  Returns 0 or CHEMK_CELL_NEWTON.
+__device__ __forceinline__ int wave_T_from_h(const DevMech &m, double h0R, double Yk,
+                                             double &T) {
+    double Tg = T;
+    for (int it = 0; it < 50; ++it) {
+        double hR, cR;
+        wave_h_cp(m, Tg, Yk, hR, cR);
+        const double dT = (hR - h0R) / cR;
+        Tg -= dT;
+        if (!isfinite(Tg)) break;
+        if (fabs(dT) <= 1e-12 * fabs(Tg)) {
+            if (Tg >= 200.0 && Tg <= 4000.0) {
+                T = Tg;
+                return 0;
+            }
+            break;
+        }
+    }
+    double lo = 200.0, hi = 4000.0, hlo, hhi, c;
+    wave_h_cp(m, lo, Yk, hlo, c);
+    wave_h_cp(m, hi, Yk, hhi, c);
+    if (!(hlo <= h0R && h0R <= hhi)) return CHEMK_CELL_NEWTON;
+    for (int it = 0; it < 200 && hi - lo > 1e-13 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        double hm;
+        wave_h_cp(m, mid, Yk, hm, c);
+        if (hm < h0R) lo = mid;
+        else hi = mid;
+    }
+    T = 0.5 * (lo + hi);
+    return 0;
+}
+
+// Integrate one cell over dt.  y: this lane's component (in/out).  Returns the
+// cell status; nsteps receives the number of attempted steps.
+template <int N>
+__device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, double dt,
+                       const DIParams &o, int &nsteps) {
+    const int lane = lane_id();
+    const int K = m.K, Na = K + 1;
+    const bool act = lane < Na;
+    const double atol = lane < K ? o.atolY : o.atolT;
+    const double yin = y;
+    // conserved enthalpy at the start
+    double h0R, cdummy;
+    wave_h_cp(m, bcast(y, K), lane < K ? y : 0.0, h0R, cdummy);
+
+    double a[N];
+    double u0, u1, u2, u3, u4, u5;
+    double f0 = 0.0;
+    double t = 0.0, h = o.h0_frac * dt;
+    bool need_jac = true, rejected = false;
+    int nst = 0, status = 0;
+    int mystep = -1;
+    while (t < dt) {
+        if (nst >= o.max_steps) {
+            status = CHEMK_CELL_MAX_STEPS;
+            break;
+        }
+        bool last = false;
+        if (t + h >= dt * (1.0 - 1e-14) || t + h >= dt) {
+            h = dt - t;
+            last = true;
+        }
+        if (h <= 1e-20 * dt || h <= 0.0) {
+            status = CHEMK_CELL_MAX_STEPS;
+            break;
+        }
+        if (need_jac) {
+            f0 = wave_f_jac(m, L, p_cgs, y);
+            need_jac = false;
+        }
+        ++nst;
+        const double fac = 1.0 / (h * kGamma);
+        // iteration matrix row: fac I - J (identity on padded rows)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double jv = (lane < Na && j < Na) ? L.J[lane * L.ld + j] : 0.0;
+            a[j] = (j == lane ? fac : 0.0) - jv;
+        }
+        if (!wave_lu<N>(a, mystep, L)) {
+            status = CHEMK_CELL_SINGULAR;
+            break;
+        }
+        // the factors replace the Jacobian in LDS: a rejected step re-evaluates J
+        const double rdiag = wave_store_lu<N>(a, mystep, L);
+        need_jac = true;
+        const double ih = 1.0 / h;
+        // stage 1
+        u0 = wave_solve(L, N, mystep, rdiag, f0);
+        double yt = y + kA[1][0] * u0;
+        double fs = wave_rhs(m, L, p_cgs, yt);
+        u1 = wave_solve(L, N, mystep, rdiag, fs + kC[1][0] * ih * u0);
+        yt = y + kA[2][0] * u0 + kA[2][1] * u1;
+        fs = wave_rhs(m, L, p_cgs, yt);
+        u2 = wave_solve(L, N, mystep, rdiag, fs + ih * (kC[2][0] * u0 + kC[2][1] * u1));
+        yt = y + kA[3][0] * u0 + kA[3][1] * u1 + kA[3][2] * u2;
+        fs = wave_rhs(m, L, p_cgs, yt);
+        u3 = wave_solve(L, N, mystep, rdiag,
+                           fs + ih * (kC[3][0] * u0 + kC[3][1] * u1 + kC[3][2] * u2));
+        yt = y + kA[4][0] * u0 + kA[4][1] * u1 + kA[4][2] * u2 + kA[4][3] * u3;
+        fs = wave_rhs(m, L, p_cgs, yt);
+        u4 = wave_solve(
+            L, N, mystep, rdiag,
+            fs + ih * (kC[4][0] * u0 + kC[4][1] * u1 + kC[4][2] * u2 + kC[4][3] * u3));
+        yt = yt + u4;   // embedded (order 3) solution
+        fs = wave_rhs(m, L, p_cgs, yt);
+        u5 = wave_solve(L, N, mystep, rdiag,
+                           fs + ih * (kC[5][0] * u0 + kC[5][1] * u1 + kC[5][2] * u2 +
+                                      kC[5][3] * u3 + kC[5][4] * u4));
+        const double ynew = yt + u5;
+        const double sc = atol + o.rtol * fmax(fabs(y), fabs(ynew));
+        const double e = act ? u5 / sc : 0.0;
+        double err = sqrt(wave_sum(e * e) / Na);
+        const bool finite = isfinite(err);
+        if (!finite) {
+            h *= 0.2;
+            rejected = true;
+            continue;
+        }
+        if (err <= 1.0) {
+            t = last ? dt : t + h;
+            y = act ? ynew : 0.0;
+            double fc = err > 0.0 ? 0.9 / sqrt(sqrt(err)) : 5.0;
+            fc = fmin(5.0, fmax(0.2, fc));
+            if (rejected) fc = fmin(fc, 1.0);
+            h *= fc;
+            rejected = false;
+        } else {
+            h *= fmax(0.2, 0.9 / sqrt(sqrt(err)));
+            rejected = true;
+        }
+    }
+    nsteps = nst;
+    if (status == 0) {
+        // non-finite state anywhere -> status 3
+        const double bad = isfinite(y) ? 0.0 : 1.0;
+        if (wave_sum(bad) > 0.0) status = CHEMK_CELL_NONFINITE;
+    }
+    if (status == 0) {
+        double Yk = lane < K ? y : 0.0;
+        if (o.project) Yk = wave_project(m, L, Yk, lane < K ? yin : 0.0);
+        double T = bcast(y, K);
+        const int st = wave_T_from_h(m, h0R, Yk, T);
+        if (st) {
+            status = st;
+        } else {
+            y = lane < K ? Yk : (lane == K ? T : 0.0);
+            if (T < 200.0 || T > 4000.0) status = CHEMK_CELL_T_RANGE;
+        }
+    }
+    if (status != 0 && status != CHEMK_CELL_T_RANGE) y = yin;   // leave the state untouched
+    return status;
+}
+
+// Persistent DI kernel: waves pull items from the queue until it is drained.
+// Register budget per template: the iteration-matrix row (2N VGPRs) plus the
+// stage vectors and scalars; the minimum waves per SIMD is set so the
+// compiler keeps everything in registers at the highest residency it allows.
+template <int N>
+struct DIOcc {
+    static constexpr int waves = N <= 24 ? 4 : (N <= 40 ? 3 : 2);
+};
+
+template <int N>
+__global__ void __launch_bounds__(64, DIOcc<N>::waves) di_kernel(DevMech m, const int *__restrict__ n_items_p,
+                                                const int *__restrict__ queue, int *counter,
+                                                double *T, const double *p, double *Y,
+                                                double dt, DIParams o, int *status,
+                                                int *nsteps, unsigned long long *stats,
+                                                int status_or) {
+    extern __shared__ double lds[];
+    const Lds L = carve_lds(lds, m.K, m.R, N);
+    const int lane = lane_id();
+    const int K = m.K;
+    const int n_items = *n_items_p;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(counter, 1);
+        item = uniform(item);
+        if (item >= n_items) break;
+        const int c = queue ? queue[item] : item;
+        double y = 0.0;
+        if (lane < K) y = Y[(size_t)c * K + lane];
+        else if (lane == K) y = T[c];
+        int ns = 0;
+        const int st = di_cell<N>(m, L, p[c] * PA_TO_CGS, y, dt, o, ns);
+        if (lane < K) Y[(size_t)c * K + lane] = y;
+        else if (lane == K) T[c] = y;
+        if (lane == 0) {
+            status[c] = st | status_or;
+            if (nsteps) nsteps[c] = ns;
+            atomicAdd(&stats[1], (unsigned long long)ns);
+            if (st) atomicAdd(&stats[2], 1ull);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stiffness key, histogram and queue (binning)
+// ---------------------------------------------------------------------------
+// key = log10 of dt * max_k |dY_k/dt| / (|Y_k| + 1e-8) over the species, plus
+// a temperature term; one wave per cell, one RHS evaluation.
+__global__ void __launch_bounds__(64) stiffness_key_kernel(DevMech m, int n, const double *T,
+                                                           const double *p, const double *Y,
+                                                           double dt, int bins, int *bin_out) {
+    extern __shared__ double lds[];
+    const Lds L = carve_lds(lds, m.K, m.R, 1);
+    const int lane = lane_id();
+    const int K = m.K;
+    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+        double y = 0.0;
+        if (lane < K) y = Y[(size_t)c * K + lane];
+        else if (lane == K) y = T[c];
+        const double f = wave_rhs(m, L, p[c] * PA_TO_CGS, y);
+        double act = lane < K ? fabs(f) * dt / (fabs(y) + 1e-8) : 0.0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) act = fmax(act, __shfl_xor(act, off, WAVE));
+        if (lane == 0) {
+            // map log10(activity) in [-6, 6] onto bins-1 .. 0 (bin 0 = most active)
+            double lg = isfinite(act) ? log10(act + 1e-30) : 6.0;
+            double x = (6.0 - lg) / 12.0 * bins;
+            int b = (int)floor(x);
+            b = b < 0 ? 0 : (b >= bins ? bins - 1 : b);
+            bin_out[c] = b;
+        }
+    }
+}
+
+__global__ void zero_ints_kernel(int *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void set_int_kernel(int *p, int v) { *p = v; }
+
+__global__ void histogram_kernel(const int *bin, int n, int bins, int *hist) {
+    __shared__ int h[256];
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&h[bin[i]], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// exclusive scan of the histogram (bin 0 first); one thread.
+__global__ void scan_kernel(const int *hist, int bins, int *offs) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int acc = 0;
+        for (int b = 0; b < bins; ++b) {
+            offs[b] = acc;
+            acc += hist[b];
+        }
+    }
+}
+
+__global__ void scatter_kernel(const int *bin, int n, int *offs, int *queue) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int pos = atomicAdd(&offs[bin[i]], 1);
+        queue[pos] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+int di_template_N(int Nreal) {
+    static const int exact[] = {10, 33, 54};
+    for (int e : exact)
+        if (e == Nreal) return e;
+    static const int buckets[] = {16, 24, 32, 40, 48, 56, 64};
+    for (int b : buckets)
+        if (Nreal <= b) return b;
+    return -1;
+}
+
+size_t di_lds_bytes(int K, int R, int N) {
+    return sizeof(double) * (size_t)lds_doubles_per_wave(K, R, N);
+}
+
+template <int N>
+static hipError_t launch_di_N(const DevMech &m, int grid, const int *n_items, const int *queue,
+                              int *counter, double *T, const double *p, double *Y, double dt,
+                              const DIParams &o, int *status, int *nsteps,
+                              unsigned long long *stats, int status_or, hipStream_t s) {
+    const size_t lds = di_lds_bytes(m.K, m.R, N);
+    hipLaunchKernelGGL(di_kernel<N>, dim3(grid), dim3(64), lds, s, m, n_items, queue, counter, T,
+                       p, Y, dt, o, status, nsteps, stats, status_or);
+    return hipGetLastError();
+}
+
+hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *queue,
+                     int *counter, double *T, const double *p, double *Y, double dt,
+                     double rtol, double atolY, double atolT, double h0_frac, int max_steps,
+                     int project, int *status, int *nsteps, unsigned long long *stats,
+                     int status_or, hipStream_t s) {
+    DIParams o{rtol, atolY, atolT, h0_frac, max_steps, project};
+    switch (di_template_N(m.N)) {
+#define CASE_N(NN) \
+    case NN:       \
+        return launch_di_N<NN>(m, grid, n_items, queue, counter, T, p, Y, dt, o, status, nsteps, stats, status_or, s);
+        CASE_N(10)
+        CASE_N(16)
+        CASE_N(24)
+        CASE_N(32)
+        CASE_N(33)
+        CASE_N(40)
+        CASE_N(48)
+        CASE_N(54)
+        CASE_N(56)
+        CASE_N(64)
+#undef CASE_N
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_binning(const DevMech &m, int n, const double *T, const double *p,
+                          const double *Y, double dt, int bins, int *bin, int *hist, int *offs,
+                          int *queue, hipStream_t s) {
+    const size_t lds = di_lds_bytes(m.K, m.R, 1);
+    const int grid_key = n < 8192 ? n : 8192;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, s, hist, bins);
+    hipLaunchKernelGGL(stiffness_key_kernel, dim3(grid_key), dim3(64), lds, s, m, n, T, p, Y, dt,
+                       bins, bin);
+    const int g = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(histogram_kernel, dim3(g), dim3(256), 0, s, bin, n, bins, hist);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, s, hist, bins, offs);
+    hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(256), 0, s, bin, n, offs, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int *p, int v, hipStream_t s) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+}  // namespace chemk

@@ -1,0 +1,242 @@
+"""Training-data generation and training of the MLP that stands in for DI.
+
+Everything numeric runs in libchemk: the DI kernel integrates the ignition
+trajectories and labels every pair, the property kernels give temperatures,
+and the network is fitted by the library's own forward/backward GEMM and
+Adam kernels (chemk_ann_train_step).  This module only sequences the calls,
+draws seeded random numbers and keeps the bookkeeping (splits, schedules).
+
+Data recipe (paper Sec. II.B, adapted to the synthetic mechanisms):
+  * 0-D constant-pressure ignition trajectories from fuel/air at
+    phi ~ U[0.5, 1.5], T0 ~ U[900, 1500] K, recorded on a geometric time grid
+    and perturbed by 5 % Gaussian noise on Y and 20 K on T;
+  * mixing-line states between cold fuel/air (300-600 K) and burnt states
+    (the paper's remedy for entrainment states, Sec. II.B);
+  * states of the flame-block recipe drawn with seeds disjoint from the
+    benchmark's (coverage of the LES-like cell population);
+  * labels: DI over dt; 10 % of the pairs are held out and judged against DI.
+"""
+from __future__ import annotations
+
+import math
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def mlp_flops_per_cell(dims):
+    """Algorithmic FLOPs of one forward pass (2 per multiply-add, unpadded)."""
+    return sum(2 * dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+
+
+def default_dims(K):
+    return [K + 2, 1024, 512, 256, K]
+
+
+def init_params(dims, seed):
+    """He-uniform weights, zero biases, in the public parameter layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(dims) - 1):
+        lim = math.sqrt(6.0 / dims[i])
+        parts.append(rng.uniform(-lim, lim, dims[i] * dims[i + 1]).astype(np.float32))
+        parts.append(np.zeros(dims[i + 1], np.float32))
+    return np.concatenate(parts)
+
+
+def _advance(ctx, T, P, Y, dt, st, max_steps=100000):
+    from . import chemk
+    ctx.advance(T, P, Y, dt, st, None, opts=chemk.default_opts(max_steps=max_steps))
+
+
+def generate_pairs(ctx, mech, dt, n_pairs, seed=3001, frac_traj=0.6, frac_mix=0.1,
+                   n_rec=200, t_end=2.5, log=print):
+    """Returns host arrays (T, p, Y, Y_next, kind) of n_pairs DI-labelled pairs."""
+    import torch
+
+    from synth import workload as sw
+
+    dev = "cuda:0"
+    rng = np.random.default_rng(seed)
+    n_traj_states = int(n_pairs * frac_traj)
+    n_mix = int(n_pairs * frac_mix)
+    n_blk = n_pairs - n_traj_states - n_mix
+    n_traj = max(1, int(math.ceil(n_traj_states / n_rec)))
+    t0 = time.time()
+    # --- ignition trajectories (DI on the GPU) ---
+    T0, p0, Y0, phi = sw.ignition_initial_states(mech, n_traj, seed + 1)
+    T = torch.from_numpy(T0).to(dev)
+    Y = torch.from_numpy(Y0).to(dev)
+    P = torch.from_numpy(p0).to(dev)
+    st = torch.zeros(n_traj, dtype=torch.int32, device=dev)
+    times = np.geomspace(1e-6, t_end, n_rec)
+    recT, recY = [], []
+    t_prev = 0.0
+    for t in times:
+        _advance(ctx, T, P, Y, t - t_prev, st)
+        t_prev = t
+        recT.append(T.clone())
+        recY.append(Y.clone())
+    torch.cuda.synchronize()
+    TT = torch.stack(recT, 1).reshape(-1).cpu().numpy()
+    YY = torch.stack(recY, 1).reshape(-1, mech.K).cpu().numpy()
+    ok = np.repeat(st.cpu().numpy() == 0, n_rec)
+    sel = rng.choice(np.nonzero(ok)[0], n_traj_states, replace=n_traj_states > ok.sum())
+    Tt, Yt = sw.perturb_states(TT[sel], YY[sel], seed + 2)
+    log(f"train data: {n_traj} trajectories x {n_rec} records in {time.time() - t0:.1f} s")
+    # --- mixing lines: cold fuel/air <-> burnt trajectory end states ---
+    burnt_T = recT[-1].cpu().numpy()
+    burnt_Y = recY[-1].cpu().numpy()
+    j = rng.integers(0, n_traj, n_mix)
+    Tc, _, Yc, _ = sw.ignition_initial_states(mech, n_mix, seed + 3, T0_range=(300.0, 600.0))
+    c = rng.uniform(0.0, 1.0, n_mix)
+    Tm = (1 - c) * Tc + c * burnt_T[j]
+    Ym = (1 - c)[:, None] * Yc + c[:, None] * burnt_Y[j]
+    # --- flame-block states with disjoint seeds ---
+    Tb_l, Yb_l = [], []
+    got, s_ = 0, seed + 100
+    while got < n_blk:
+        Tb, _, Yb, _ = sw.flame_block(mech, 32, s_)
+        Tb_l.append(Tb)
+        Yb_l.append(Yb)
+        got += Tb.size
+        s_ += 1
+    Tb = np.concatenate(Tb_l)[:n_blk]
+    Yb = np.concatenate(Yb_l)[:n_blk]
+    Tin = np.concatenate([Tt, Tm, Tb])
+    Yin = np.concatenate([Yt, Ym, Yb])
+    kind = np.concatenate([np.zeros(len(Tt), np.int8), np.ones(n_mix, np.int8),
+                           np.full(n_blk, 2, np.int8)])
+    pin = np.full(Tin.size, p0[0])
+    # --- labels: DI over dt ---
+    t1 = time.time()
+    Tg = torch.from_numpy(Tin).to(dev)
+    Yg = torch.from_numpy(np.ascontiguousarray(Yin)).to(dev)
+    Pg = torch.from_numpy(pin).to(dev)
+    stg = torch.zeros(Tin.size, dtype=torch.int32, device=dev)
+    _advance(ctx, Tg, Pg, Yg, dt, stg)
+    torch.cuda.synchronize()
+    good = stg.cpu().numpy() == 0
+    log(f"train data: {Tin.size} DI labels in {time.time() - t1:.1f} s "
+        f"({(~good).sum()} failed, dropped)")
+    return (Tin[good], pin[good], np.ascontiguousarray(Yin[good]), Yg.cpu().numpy()[good],
+            kind[good])
+
+
+def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001,
+                  holdout=0.1, log=print):
+    """Fits the network on the DI pairs; returns a history dict."""
+    import torch
+
+    dev = "cuda:0"
+    T, p, Y, Yn, kind = data
+    n = T.size
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    n_hold = int(n * holdout)
+    hold, tr = np.sort(perm[:n_hold]), np.sort(perm[n_hold:])
+    K = Y.shape[1]
+    dims = default_dims(K)
+    ctx.ann_create(dims)
+    ctx.ann_set_weights(init_params(dims, seed))
+    ctx.ann_reset_optimizer()
+    Td = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
+          (("T", T[tr]), ("p", p[tr]), ("Y", Y[tr]), ("Yn", Yn[tr]))}
+    ctx.ann_fit_norm(Td["T"], Td["p"], Td["Y"], Td["Yn"], dt)
+    ntr = tr.size
+    X = torch.empty((ntr, 64), dtype=torch.int16, device=dev)
+    Z = torch.empty((ntr, K), dtype=torch.float32, device=dev)
+    ctx.ann_pack(Td["T"], Td["p"], Td["Y"], Td["Yn"], X, Z)
+    steps_per_epoch = ntr // batch
+    total = steps_per_epoch * epochs
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    hist = {"loss": [], "epochs": epochs, "batch": batch, "n_train": int(ntr),
+            "n_holdout": int(n_hold)}
+    t0 = time.time()
+    step = 0
+    for ep in range(epochs):
+        order = torch.from_numpy(rng.permutation(ntr).astype(np.int32)).to(dev)
+        for b in range(steps_per_epoch):
+            lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * step / max(total, 1)))
+            idx = order[b * batch:(b + 1) * batch]
+            ctx.ann_train_step(idx, X, Z, lr, update=True, loss=loss if b == steps_per_epoch - 1
+                               else None)
+            step += 1
+        torch.cuda.synchronize()
+        hist["loss"].append(float(loss.item()))
+        if ep % 10 == 0 or ep == epochs - 1:
+            log(f"train: epoch {ep + 1}/{epochs} loss {hist['loss'][-1]:.4e} "
+                f"({time.time() - t0:.1f} s)")
+    hist["train_s"] = time.time() - t0
+    hist["steps"] = step
+    hist["holdout_index"] = hold
+    return hist
+
+
+def evaluate(ctx, T, p, Y, Yn_ref):
+    """Per-species RMS and max of the normalised dY error of the network
+    (no projection, no fallback) against reference dY, plus the frozen-
+    chemistry (dY = 0) error, on host arrays."""
+    import torch
+
+    dev = "cuda:0"
+    K = Y.shape[1]
+    n = T.size
+    mx, sx, my, sy, dt = ctx.ann_get_norm()
+    Td = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (T, p, Y, Yn_ref)]
+    X = torch.empty((n, 64), dtype=torch.int16, device=dev)
+    out = torch.empty((n, K), dtype=torch.float32, device=dev)
+    ctx.ann_pack(Td[0], Td[1], Td[2], None, X, None)
+    ctx.ann_forward_packed(X, out)
+    pred = my + sy * out.cpu().numpy().astype(np.float64)
+    ref = Yn_ref - Y
+    e = (pred - ref) / sy
+    e0 = (0.0 - ref) / sy
+    return {"rms_norm": np.sqrt(np.mean(e * e, 0)), "max_norm": np.abs(e).max(0),
+            "rms_abs": np.sqrt(np.mean((pred - ref) ** 2, 0)),
+            "frozen_rms_norm": np.sqrt(np.mean(e0 * e0, 0)),
+            "rms_norm_all": float(np.sqrt(np.mean(e * e))),
+            "frozen_rms_norm_all": float(np.sqrt(np.mean(e0 * e0)))}
+
+
+WEIGHTS = os.path.join(HERE, "weights", "mlp_medium.npz")
+
+
+def save(ctx, path=WEIGHTS, extra=None):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    mx, sx, my, sy, dt = ctx.ann_get_norm()
+    lo, hi, neg_tol = ctx.ann_get_envelope()
+    np.savez(path, params=ctx.ann_get_weights(), dims=np.array(ctx.dims), mu_x=mx, sd_x=sx,
+             mu_y=my, sd_y=sy, dt=dt, env_lo=lo, env_hi=hi, neg_tol=neg_tol, **(extra or {}))
+
+
+def load(ctx, path=WEIGHTS, neg_tol=None):
+    d = np.load(path, allow_pickle=False)
+    ctx.ann_create([int(v) for v in d["dims"]])
+    ctx.ann_set_weights(d["params"])
+    ctx.ann_set_norm(d["mu_x"], d["sd_x"], d["mu_y"], d["sd_y"], float(d["dt"]))
+    if "env_lo" in d.files:
+        nt = float(d["neg_tol"]) if neg_tol is None else neg_tol
+        ctx.ann_set_envelope(d["env_lo"], d["env_hi"], nt)
+    return d
+
+
+def load_or_train(ctx, mech, dt, log=print, n_pairs=None, epochs=None, path=WEIGHTS):
+    """Loads trained weights if present (with matching dt and dims), else runs
+    the full pipeline (data generation, training) and saves the result."""
+    if os.path.exists(path):
+        d = np.load(path, allow_pickle=False)
+        if abs(float(d["dt"]) - dt) <= 1e-12 * dt and int(d["dims"][0]) == mech.K + 2:
+            load(ctx, path)
+            log(f"ann: loaded {path}")
+            return True
+    n_pairs = n_pairs or int(os.environ.get("CHEMK_TRAIN_PAIRS", 2_000_000))
+    epochs = epochs or int(os.environ.get("CHEMK_TRAIN_EPOCHS", 50))
+    data = generate_pairs(ctx, mech, dt, n_pairs, log=log)
+    hist = train_network(ctx, data, dt, epochs=epochs, log=log)
+    mx, sx, my, sy, _ = ctx.ann_get_norm()
+    save(ctx, path, extra={"loss": np.array(hist["loss"])})
+    return True

@@ -1,0 +1,101 @@
+"""Pins of the oracle's learned-part reference (Box-Cox, GELU, MLP gradients,
+Adam, bfloat16 rounding, element projection).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ann
+from synth import mechanism as sm
+
+
+def test_box_cox_maps_unit_interval_as_stated():
+    """Sec. II.B: mass fractions in [0, 1] map onto [-1/lambda, 0]."""
+    assert ann.box_cox(0.0) == pytest.approx(-10.0, abs=0)
+    assert ann.box_cox(1.0) == pytest.approx(0.0, abs=0)
+    x = np.linspace(0, 1, 1001)
+    f = ann.box_cox(x)
+    assert np.all(np.diff(f) > 0) and f.min() >= -10.0 and f.max() <= 0.0
+    # lambda -> 0 limit is the log branch of Eq. 7
+    assert ann.box_cox(0.3, lam=1e-8) == pytest.approx(math.log(0.3), rel=1e-7)
+    assert ann.box_cox(0.3, lam=0.0) == pytest.approx(math.log(0.3), rel=1e-15)
+    assert ann.box_cox(-1e-12) == -10.0          # round-off negatives clamp to 0
+
+
+def test_gelu_values():
+    assert ann.gelu(0.0) == 0.0
+    assert ann.gelu(1.0) == pytest.approx(0.8413447460685429, rel=1e-15)   # Phi(1)
+    assert ann.gelu(-1.0) == pytest.approx(-0.15865525393145707, rel=1e-14)
+    assert ann.gelu(10.0) == pytest.approx(10.0, rel=1e-15)
+    assert abs(ann.gelu(-10.0)) < 1e-20
+    x = np.linspace(-5, 5, 41)
+    d = 1e-6
+    fd = (ann.gelu(x + d) - ann.gelu(x - d)) / (2 * d)
+    assert np.allclose(ann.gelu_grad(x), fd, rtol=1e-8, atol=1e-10)
+
+
+def test_bf16_rounding_known_values():
+    e = 2.0 ** -7                      # bfloat16 ulp at 1.0
+    vals = np.array([1.0, 1 + e / 2, 1 + e / 2 + 2**-20, 1 + 3 * e / 2, -2.5, 3.0e38])
+    want = np.array([1.0, 1.0, 1 + e, 1 + 2 * e, -2.5, 2.9942e38])
+    got = ann.bf16(vals)
+    assert got[0] == 1.0 and got[1] == 1.0          # tie to even
+    assert got[2] == 1 + e and got[3] == 1 + 2 * e  # above the tie / tie to even (up)
+    assert got[4] == -2.5
+    assert got[5] == pytest.approx(want[5], rel=4e-3)
+
+
+def test_mlp_backward_matches_finite_differences():
+    dims = [6, 16, 12, 8, 3]
+    Ws, bs = ann.init_params(dims, 1)
+    rng = np.random.default_rng(2)
+    bs = [rng.normal(0, 0.1, b.shape) for b in bs]
+    X = rng.normal(size=(5, 6))
+    tgt = rng.normal(size=(5, 3))
+    out, cache = ann.forward(Ws, bs, X, quantize=False)
+    loss, dout = ann.mse_loss(out, tgt)
+    gW, gb = ann.backward(Ws, bs, cache, dout, quantize=False)
+
+    def L(Ws_, bs_):
+        o, _ = ann.forward(Ws_, bs_, X, quantize=False)
+        return ann.mse_loss(o, tgt)[0]
+
+    h = 1e-6
+    for layer in range(len(Ws)):
+        for (i, j) in [(0, 0), (1, 2), (Ws[layer].shape[0] - 1, Ws[layer].shape[1] - 1)]:
+            Wp = [w.copy() for w in Ws]
+            Wm = [w.copy() for w in Ws]
+            Wp[layer][i, j] += h
+            Wm[layer][i, j] -= h
+            fd = (L(Wp, bs) - L(Wm, bs)) / (2 * h)
+            assert gW[layer][i, j] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+        bp = [b.copy() for b in bs]
+        bm = [b.copy() for b in bs]
+        bp[layer][1] += h
+        bm[layer][1] -= h
+        fd = (L(Ws, bp) - L(Ws, bm)) / (2 * h)
+        assert gb[layer][1] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+
+
+def test_adam_first_step_by_hand():
+    """On f(x) = (x-3)^2 from x=0: g = -6, m1 = 0.1 g, v1 = 0.001 g^2; after
+    bias correction the step is lr * g / (|g| + eps)."""
+    lr = 0.01
+    p, m, v = ann.adam_step(np.array([0.0]), np.array([-6.0]), np.zeros(1), np.zeros(1), 1, lr)
+    assert m[0] == pytest.approx(-0.6, rel=1e-15)
+    assert v[0] == pytest.approx(0.036, rel=1e-13)
+    assert p[0] == pytest.approx(lr * 6.0 / (6.0 + 1e-8), rel=1e-13)
+
+
+def test_projection_conserves_elements():
+    mech = sm.mech_medium()
+    E = ann.element_matrix(mech.composition, mech.element_mass)
+    # every column of E sums to 1: a species' mass is carried by its elements
+    assert np.allclose(E.sum(0), 1.0, rtol=1e-14)
+    rng = np.random.default_rng(4)
+    Y = rng.dirichlet(np.ones(mech.K), 8)
+    dY = 1e-4 * rng.standard_normal(Y.shape)
+    out = ann.project_delta(E, Y, dY)
+    assert np.abs(out @ E.T).max() < 1e-18
+    again = ann.project_delta(E, Y, out)
+    assert np.abs(again - out).max() < 1e-19
