@@ -81,6 +81,12 @@ _SIGS = {
     "chemk_ann_reset_optimizer": (C.c_int, [_vp]),
 }
 
+# torch ships its own HIP runtime (libamdhip64.so.7).  Importing torch first
+# makes the library's libamdhip64.so.7 dependency resolve to that same copy, so
+# the process has one HIP/HSA runtime shared by torch tensors, streams and the
+# library's kernels (a second runtime would hide the GPU from one of them).
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                       "(hipcc, gfx950); there is no fallback path")

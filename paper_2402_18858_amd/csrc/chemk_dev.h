@@ -40,6 +40,16 @@ struct DevMech {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// The lane index as an opaque value: per-lane table addresses derived from it
+// are recomputed where they are used instead of being hoisted out of the
+// integration loop as long-lived 64-bit register pairs (cheap to rebuild,
+// expensive to keep: they push the DI kernel into scratch spills).
+__device__ __forceinline__ int lane_fresh() {
+    int l = threadIdx.x & (WAVE - 1);
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // Orders LDS traffic of this wave around the call (compiler and memory model).
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -200,7 +210,7 @@ __device__ __forceinline__ RxnEval rxn_eval(const DevMech &m, const Lds &L, int 
 // >= N).  Lane k < K holds Y_k in y, lane K holds T.
 __device__ __forceinline__ double wave_rhs(const DevMech &m, const Lds &L, double p_cgs,
                                            double y) {
-    const int lane = lane_id();
+    const int lane = lane_fresh();
     const int K = m.K;
     const bool sp = lane < K;
     const double Yk = sp ? y : 0.0;
@@ -248,7 +258,7 @@ __device__ __forceinline__ double wave_rhs(const DevMech &m, const Lds &L, doubl
 // with hs_j = sum_r dH_r dq_r/dC_j, Hu = sum_k (h_k/RT) u_k, Q' = dQ/dT, chat' = dchat/dT.
 __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, double p_cgs,
                                              double y) {
-    const int lane = lane_id();
+    const int lane = lane_fresh();
     const int K = m.K, ld = L.ld;
     const bool sp = lane < K;
     const double Yk = sp ? y : 0.0;

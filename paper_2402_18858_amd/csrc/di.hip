@@ -2,11 +2,11 @@
 // flow step (Eq. 2) on gfx950.
 //
 // Design: one wavefront per cell.  Lane i < N holds component i of
-// y = (Y_1..Y_K, T) and row i of the iteration matrix (1/(h gamma)) I - J in
-// registers (N is a template parameter so the row is a register array).  The
-// Jacobian is assembled in the wave's LDS slice, LU with partial pivoting
-// broadcasts each pivot row through LDS and keeps the permutation implicit,
-// and the triangular solves broadcast one solution component per step.
+// y = (Y_1..Y_K, T) and owns row i of the Jacobian / iteration matrix
+// (1/(h gamma)) I - J in the wave's LDS slice.  LU with partial pivoting reads
+// each pivot row from LDS and keeps the permutation implicit; the triangular
+// solves gather the right-hand side in pivot order and broadcast one solution
+// component per step.  All loop control is wave-uniform by construction.
 // Integrator: RODAS (Hairer & Wanner, Solving ODEs II, Sec. VI.4), the
 // stiffly accurate Rosenbrock method of order 4 with an embedded order-3
 // estimate, in its transformed form; weighted-RMS error control.
@@ -37,77 +37,71 @@ __constant__ double kC[6][5] = {
 constexpr double kGamma = 0.25;
 
 // ---------------------------------------------------------------------------
-// dense LU of the iteration matrix, one row per lane, implicit pivoting.
-// On return a[] of the lane that was chosen at step k holds U row k (columns
-// >= k) and its L multipliers (columns < k); piv[k] = that lane; mystep = k.
-// Returns false if a pivot is exactly zero.
+// dense LU of the iteration matrix in LDS, one row per lane, implicit
+// partial pivoting (the pivot row is broadcast from LDS; rows are not moved).
+// On return: L.piv[k] = row chosen at step k; that row holds its L
+// multipliers in columns < k and U in columns >= k; mystep = the step at
+// which this lane's row was chosen.  Returns false on an exactly zero pivot.
 // ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ bool wave_lu(double (&a)[N], int &mystep, const Lds &L) {
+__device__ __forceinline__ bool wave_lu(const Lds &L, int n, int &mystep) {
     const int lane = lane_id();
-    mystep = lane < N ? N : -1;
+    double *row = L.J + lane * L.ld;
+    mystep = lane < n ? n : -1;
     bool ok = true;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const bool open = mystep == N;
-        const int p = wave_argmax(fabs(a[k]), open);
+#pragma unroll 1
+    for (int k = 0; k < n; ++k) {
+        const bool open = mystep == n;
+        const double ak = lane < n ? row[k] : 0.0;
+        const int p = wave_argmax(fabs(ak), open);
         if (lane == p) {
             mystep = k;
             L.piv[k] = p;
         }
-        const double pv = bcast(a[k], p);
+        wave_sync();
+        const double *prow = L.J + p * L.ld;
+        const double pv = prow[k];
         if (pv == 0.0) ok = false;
-        // rows not yet chosen eliminate column k; chosen rows see l = 0
-        const double l = open ? a[k] / pv : 0.0;
-        a[k] = open ? l : a[k];
-#pragma unroll
-        for (int j = k + 1; j < N; ++j) a[j] = fma(-l, bcast(a[j], p), a[j]);
-        __builtin_amdgcn_sched_barrier(0);
+        if (mystep == n) {   // rows still open (the pivot row itself is now closed)
+            const double l = ak / pv;
+            row[k] = l;
+#pragma unroll 1
+            for (int j = k + 1; j < n; ++j) row[j] -= l * prow[j];
+        }
+        wave_sync();
     }
-    wave_sync();
     return ok;
 }
 
-// Store the factors to LDS (row of lane i at L.J[i*ld], overwriting the
-// Jacobian) and return 1/U_kk for the lane that pivoted at step k.
-template <int N>
-__device__ __forceinline__ double wave_store_lu(const double (&a)[N], int mystep, const Lds &L) {
-    const int lane = lane_id();
-    double rd = 0.0;
-    if (lane < N) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            L.J[lane * L.ld + j] = a[j];
-            if (j == mystep) rd = 1.0 / a[j];
-        }
-    }
-    wave_sync();
-    return rd;
-}
-
-// Solve (LU) x = b with the factors in LDS; b is this lane's component and the
-// solution component of lane i is returned in lane i.
-__device__ __forceinline__ double wave_solve(const Lds &L, int n, int mystep, double rdiag,
+// Solve (LU) x = b; b is this lane's component (equation `lane`), the
+// solution component of variable i is returned in lane i.  Lane k works on
+// the row chosen at step k (LDS row src = piv[k]); rdiag = 1/U_kk.
+__device__ __forceinline__ double wave_solve(const Lds &L, int n, int src, double rdiag,
                                              double b) {
     const int lane = lane_id();
-    const double *row = L.J + lane * L.ld;
-    // forward: the lane that pivoted at step k holds z_k; later rows subtract l z_k
+    const double *row = L.J + src * L.ld;
+    // right-hand side in pivot order
+    double z = __shfl(b, src, WAVE);
+    // forward: L y = Pb (unit lower triangle)
 #pragma unroll 1
-    for (int k = 0; k < n; ++k) {
-        const int p = uniform(L.piv[k]);
-        const double z = bcast(b, p);
-        if (mystep > k) b -= row[k] * z;
+    for (int k = 0; k < n - 1; ++k) {
+        const double zk = bcast(z, k);
+        if (lane > k && lane < n) z -= row[k] * zk;
     }
-    // backward: x_k = z_k / U_kk in the pivot lane; earlier pivot rows subtract
-    double x = 0.0;
+    // backward: U x = y
 #pragma unroll 1
     for (int k = n - 1; k >= 0; --k) {
-        const int p = uniform(L.piv[k]);
-        const double xk = bcast(b * rdiag, p);
-        if (mystep >= 0 && mystep < k) b -= row[k] * xk;
-        if (lane == k) x = xk;
+        const double xk = bcast(z * rdiag, k);
+        if (lane < k) z -= row[k] * xk;
+        if (lane == k) z = xk;
     }
-    return x;
+    return lane < n ? z : 0.0;
+}
+
+// wave-uniform copy of a double (the value of lane 0)
+__device__ __forceinline__ double uniform_d(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
 }
 
 struct DIParams {
@@ -237,7 +231,9 @@ __device__ __forceinline__ int wave_T_from_h(const DevMech &m, double h0R, doubl
 
 // Integrate one cell over dt.  y: this lane's component (in/out).  Returns the
 // cell status; nsteps receives the number of attempted steps.
-template <int N>
+// Integrate one cell over dt.  y: this lane's component (in/out).  Returns the
+// cell status; nsteps receives the number of attempted steps.  All loop
+// control (t, h, error, counters) is wave-uniform by construction.
 __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, double dt,
                        const DIParams &o, int &nsteps) {
     const int lane = lane_id();
@@ -249,14 +245,15 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
     double h0R, cdummy;
     wave_h_cp(m, bcast(y, K), lane < K ? y : 0.0, h0R, cdummy);
 
-    double a[N];
     double u0, u1, u2, u3, u4, u5;
     double f0 = 0.0;
     double t = 0.0, h = o.h0_frac * dt;
     bool need_jac = true, rejected = false;
     int nst = 0, status = 0;
     int mystep = -1;
-    while (t < dt) {
+#pragma unroll 1
+    for (int guard = 0; guard <= o.max_steps; ++guard) {
+        if (!(t < dt)) break;
         if (nst >= o.max_steps) {
             status = CHEMK_CELL_MAX_STEPS;
             break;
@@ -275,66 +272,68 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
             need_jac = false;
         }
         ++nst;
+        // iteration matrix fac I - J in place of J (a rejected step re-evaluates J)
         const double fac = 1.0 / (h * kGamma);
-        // iteration matrix row: fac I - J (identity on padded rows)
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double jv = (lane < Na && j < Na) ? L.J[lane * L.ld + j] : 0.0;
-            a[j] = (j == lane ? fac : 0.0) - jv;
+        if (act) {
+            double *row = L.J + lane * L.ld;
+            row[lane] = fac - row[lane];
+#pragma unroll 1
+            for (int j = 0; j < Na; ++j)
+                if (j != lane) row[j] = -row[j];
         }
-        if (!wave_lu<N>(a, mystep, L)) {
+        wave_sync();
+        need_jac = true;
+        if (!wave_lu(L, Na, mystep)) {
             status = CHEMK_CELL_SINGULAR;
             break;
         }
-        // the factors replace the Jacobian in LDS: a rejected step re-evaluates J
-        const double rdiag = wave_store_lu<N>(a, mystep, L);
-        need_jac = true;
+        const int src = act ? L.piv[lane] : lane;
+        const double rdiag = act ? 1.0 / L.J[src * L.ld + lane] : 0.0;
         const double ih = 1.0 / h;
-        // stage 1
-        u0 = wave_solve(L, N, mystep, rdiag, f0);
+        u0 = wave_solve(L, Na, src, rdiag, f0);
         double yt = y + kA[1][0] * u0;
         double fs = wave_rhs(m, L, p_cgs, yt);
-        u1 = wave_solve(L, N, mystep, rdiag, fs + kC[1][0] * ih * u0);
+        u1 = wave_solve(L, Na, src, rdiag, fs + kC[1][0] * ih * u0);
         yt = y + kA[2][0] * u0 + kA[2][1] * u1;
         fs = wave_rhs(m, L, p_cgs, yt);
-        u2 = wave_solve(L, N, mystep, rdiag, fs + ih * (kC[2][0] * u0 + kC[2][1] * u1));
+        u2 = wave_solve(L, Na, src, rdiag, fs + ih * (kC[2][0] * u0 + kC[2][1] * u1));
         yt = y + kA[3][0] * u0 + kA[3][1] * u1 + kA[3][2] * u2;
         fs = wave_rhs(m, L, p_cgs, yt);
-        u3 = wave_solve(L, N, mystep, rdiag,
-                           fs + ih * (kC[3][0] * u0 + kC[3][1] * u1 + kC[3][2] * u2));
+        u3 = wave_solve(L, Na, src, rdiag,
+                        fs + ih * (kC[3][0] * u0 + kC[3][1] * u1 + kC[3][2] * u2));
         yt = y + kA[4][0] * u0 + kA[4][1] * u1 + kA[4][2] * u2 + kA[4][3] * u3;
         fs = wave_rhs(m, L, p_cgs, yt);
         u4 = wave_solve(
-            L, N, mystep, rdiag,
+            L, Na, src, rdiag,
             fs + ih * (kC[4][0] * u0 + kC[4][1] * u1 + kC[4][2] * u2 + kC[4][3] * u3));
         yt = yt + u4;   // embedded (order 3) solution
         fs = wave_rhs(m, L, p_cgs, yt);
-        u5 = wave_solve(L, N, mystep, rdiag,
-                           fs + ih * (kC[5][0] * u0 + kC[5][1] * u1 + kC[5][2] * u2 +
-                                      kC[5][3] * u3 + kC[5][4] * u4));
+        u5 = wave_solve(L, Na, src, rdiag,
+                        fs + ih * (kC[5][0] * u0 + kC[5][1] * u1 + kC[5][2] * u2 +
+                                   kC[5][3] * u3 + kC[5][4] * u4));
         const double ynew = yt + u5;
         const double sc = atol + o.rtol * fmax(fabs(y), fabs(ynew));
         const double e = act ? u5 / sc : 0.0;
-        double err = sqrt(wave_sum(e * e) / Na);
-        const bool finite = isfinite(err);
-        if (!finite) {
-            h *= 0.2;
+        const double err = uniform_d(sqrt(wave_sum(e * e) / Na));
+        if (!isfinite(err)) {
+            h = uniform_d(h * 0.2);
             rejected = true;
             continue;
         }
         if (err <= 1.0) {
-            t = last ? dt : t + h;
+            t = uniform_d(last ? dt : t + h);
             y = act ? ynew : 0.0;
             double fc = err > 0.0 ? 0.9 / sqrt(sqrt(err)) : 5.0;
             fc = fmin(5.0, fmax(0.2, fc));
             if (rejected) fc = fmin(fc, 1.0);
-            h *= fc;
+            h = uniform_d(h * fc);
             rejected = false;
         } else {
-            h *= fmax(0.2, 0.9 / sqrt(sqrt(err)));
+            h = uniform_d(h * fmax(0.2, 0.9 / sqrt(sqrt(err))));
             rejected = true;
         }
     }
+    if (status == 0 && t < dt) status = CHEMK_CELL_MAX_STEPS;
     nsteps = nst;
     if (status == 0) {
         // non-finite state anywhere -> status 3
@@ -358,23 +357,14 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
 }
 
 // Persistent DI kernel: waves pull items from the queue until it is drained.
-// Register budget per template: the iteration-matrix row (2N VGPRs) plus the
-// stage vectors and scalars; the minimum waves per SIMD is set so the
-// compiler keeps everything in registers at the highest residency it allows.
-template <int N>
-struct DIOcc {
-    static constexpr int waves = N <= 24 ? 4 : (N <= 40 ? 3 : 2);
-};
-
-template <int N>
-__global__ void __launch_bounds__(64, DIOcc<N>::waves) di_kernel(DevMech m, const int *__restrict__ n_items_p,
+__global__ void __launch_bounds__(64) di_kernel(DevMech m, const int *__restrict__ n_items_p,
                                                 const int *__restrict__ queue, int *counter,
                                                 double *T, const double *p, double *Y,
                                                 double dt, DIParams o, int *status,
                                                 int *nsteps, unsigned long long *stats,
                                                 int status_or) {
     extern __shared__ double lds[];
-    const Lds L = carve_lds(lds, m.K, m.R, N);
+    const Lds L = carve_lds(lds, m.K, m.R, m.K + 1);
     const int lane = lane_id();
     const int K = m.K;
     const int n_items = *n_items_p;
@@ -388,7 +378,7 @@ __global__ void __launch_bounds__(64, DIOcc<N>::waves) di_kernel(DevMech m, cons
         if (lane < K) y = Y[(size_t)c * K + lane];
         else if (lane == K) y = T[c];
         int ns = 0;
-        const int st = di_cell<N>(m, L, p[c] * PA_TO_CGS, y, dt, o, ns);
+        const int st = di_cell(m, L, p[c] * PA_TO_CGS, y, dt, o, ns);
         if (lane < K) Y[(size_t)c * K + lane] = y;
         else if (lane == K) T[c] = y;
         if (lane == 0) {
@@ -473,29 +463,10 @@ __global__ void scatter_kernel(const int *bin, int n, int *offs, int *queue) {
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-int di_template_N(int Nreal) {
-    static const int exact[] = {10, 33, 54};
-    for (int e : exact)
-        if (e == Nreal) return e;
-    static const int buckets[] = {16, 24, 32, 40, 48, 56, 64};
-    for (int b : buckets)
-        if (Nreal <= b) return b;
-    return -1;
-}
+int di_template_N(int Nreal) { return Nreal >= 2 && Nreal <= 64 ? Nreal : -1; }
 
 size_t di_lds_bytes(int K, int R, int N) {
     return sizeof(double) * (size_t)lds_doubles_per_wave(K, R, N);
-}
-
-template <int N>
-static hipError_t launch_di_N(const DevMech &m, int grid, const int *n_items, const int *queue,
-                              int *counter, double *T, const double *p, double *Y, double dt,
-                              const DIParams &o, int *status, int *nsteps,
-                              unsigned long long *stats, int status_or, hipStream_t s) {
-    const size_t lds = di_lds_bytes(m.K, m.R, N);
-    hipLaunchKernelGGL(di_kernel<N>, dim3(grid), dim3(64), lds, s, m, n_items, queue, counter, T,
-                       p, Y, dt, o, status, nsteps, stats, status_or);
-    return hipGetLastError();
 }
 
 hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *queue,
@@ -504,24 +475,10 @@ hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *
                      int project, int *status, int *nsteps, unsigned long long *stats,
                      int status_or, hipStream_t s) {
     DIParams o{rtol, atolY, atolT, h0_frac, max_steps, project};
-    switch (di_template_N(m.N)) {
-#define CASE_N(NN) \
-    case NN:       \
-        return launch_di_N<NN>(m, grid, n_items, queue, counter, T, p, Y, dt, o, status, nsteps, stats, status_or, s);
-        CASE_N(10)
-        CASE_N(16)
-        CASE_N(24)
-        CASE_N(32)
-        CASE_N(33)
-        CASE_N(40)
-        CASE_N(48)
-        CASE_N(54)
-        CASE_N(56)
-        CASE_N(64)
-#undef CASE_N
-        default:
-            return hipErrorInvalidValue;
-    }
+    const size_t lds = di_lds_bytes(m.K, m.R, m.K + 1);
+    hipLaunchKernelGGL(di_kernel, dim3(grid), dim3(64), lds, s, m, n_items, queue, counter, T, p,
+                       Y, dt, o, status, nsteps, stats, status_or);
+    return hipGetLastError();
 }
 
 hipError_t launch_binning(const DevMech &m, int n, const double *T, const double *p,
