@@ -477,7 +477,7 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->tOut);
     (void)hipFree(a->tLoss);
     for (auto p : a->tZ) (void)hipFree(p);
-    for (auto p : a->tA) (void)hipFree(p);
+    for (size_t i = 1; i < a->tA.size(); ++i) (void)hipFree(a->tA[i]);   // tA[0] aliases tX
     delete a;
 }
 
@@ -988,7 +988,7 @@ static hipError_t ensure_train(AnnState *a, int B) {
     (void)hipFree(a->tOut);
     (void)hipFree(a->tLoss);
     for (auto p : a->tZ) (void)hipFree(p);
-    for (auto p : a->tA) (void)hipFree(p);
+    for (size_t i = 1; i < a->tA.size(); ++i) (void)hipFree(a->tA[i]);   // tA[0] aliases tX
     a->tZ.clear();
     a->tA.clear();
     a->tB = 0;
