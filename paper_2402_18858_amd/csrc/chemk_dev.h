@@ -57,13 +57,26 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// wave-uniform copy of a double (the value of the first active lane)
+__device__ __forceinline__ double uniform_d(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, returned as one wave-uniform value.  The butterfly alone
+// does not give identical bits in every lane: the compiler fuses a lane's own
+// product into the first exchange step (an FMA against the partner's rounded
+// product), so partners can differ in the last bit.  Branches taken on such a
+// value would split the wave around later collectives; the broadcast of the
+// first lane's result rules that out.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;   // identical bits in every lane: each butterfly step adds the same pair
+    return uniform_d(v);
 }
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // value of v in lane src (src wave-uniform)
 __device__ __forceinline__ double bcast(double v, int src) {

@@ -97,13 +97,6 @@ __device__ __forceinline__ double wave_solve(const Lds &L, int n, int src, doubl
     return lane < n ? z : 0.0;
 }
 
-// wave-uniform copy of a double (the value of lane 0)
-__device__ __forceinline__ double uniform_d(double v) {
-    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
-    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
-    return __hiloint2double(hi, lo);
-}
-
 struct DIParams {
     double rtol, atolY, atolT, h0_frac;
     int max_steps, project;
@@ -369,9 +362,14 @@ __global__ void __launch_bounds__(64) di_kernel(DevMech m, const int *__restrict
     const int K = m.K;
     const int n_items = *n_items_p;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(counter, 1);
-        item = uniform(item);
+        // The claim is issued by every lane (lane 0 adds 1, the others 0) so
+        // that no branch on the lane index precedes the broadcast of the
+        // claimed index.  With a lane-0 branch here the compiler may thread
+        // the previous iteration's lane-0 block straight into this one; lanes
+        // 1..63 then reach the broadcast without lane 0, read their own zero
+        // and never see the queue drain.
+        const int got = atomicAdd(counter, lane == 0 ? 1 : 0);
+        const int item = uniform(got);
         if (item >= n_items) break;
         const int c = queue ? queue[item] : item;
         double y = 0.0;
@@ -384,9 +382,10 @@ __global__ void __launch_bounds__(64) di_kernel(DevMech m, const int *__restrict
         if (lane == 0) {
             status[c] = st | status_or;
             if (nsteps) nsteps[c] = ns;
-            atomicAdd(&stats[1], (unsigned long long)ns);
-            if (st) atomicAdd(&stats[2], 1ull);
         }
+        // statistics: wave-level atomics with zero contributions off lane 0
+        atomicAdd(&stats[1], lane == 0 ? (unsigned long long)ns : 0ull);
+        atomicAdd(&stats[2], (lane == 0 && st != 0) ? 1ull : 0ull);
     }
 }
 
