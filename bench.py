@@ -42,6 +42,30 @@ def di_flops_per_step(K, R, nnz):
     return 5 * rhs + jac + lu + 6 * solve + 6 * stage
 
 
+def element_mass(mech, Y):
+    comp = mech.composition.astype(np.float64)
+    Em = comp * mech.element_mass[None, :] / (comp @ mech.element_mass)[:, None]
+    return Y @ Em
+
+
+def ann_vs_di(ctx, mech, Y0, T_a, Y_a, st_a, T_d, Y_d, routed_bit):
+    """Error of the ANN advance against the FP64 DI advance of the same
+    cells: per-species RMS and max of (Y_ann - Y_di) / sd(dY) over the cells
+    the network advanced (routed cells are DI by construction), |dT|, and the
+    element-mass drift of the network's cells."""
+    _, _, _, sd_y, _ = ctx.ann_get_norm()
+    net = (st_a & routed_bit) == 0
+    e = (Y_a[net] - Y_d[net]) / sd_y[None, :]
+    m0, m1 = element_mass(mech, Y0[net]), element_mass(mech, Y_a[net])
+    drift = np.abs(m1 - m0) / np.maximum(m0, 1e-300)
+    return {"cells": int(net.sum()), "rms_norm_all": float(np.sqrt(np.mean(e * e))),
+            "rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(e * e, 0))],
+            "max_norm": [round(float(v), 4) for v in np.abs(e).max(0)],
+            "max_abs_T_K": float(np.abs(T_a[net] - T_d[net]).max()),
+            "rms_abs_T_K": float(np.sqrt(np.mean((T_a[net] - T_d[net]) ** 2))),
+            "element_drift_max": float(drift[m0 > 1e-12].max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +146,7 @@ def main():
     wall_di, ph_di = timed(o_di, args.steps, args.warmup)
     ns_h = ns.cpu().numpy()
     st_h = st.cpu().numpy()
+    T_di, Y_di = T.cpu().numpy(), Y.cpu().numpy()
     steps_total = float(ns_h.sum())
     di_cups = n * args.steps / wall_di
     nnz = int(sum(1 for j in range(mech.R) for s in list(mech.reactants[j]) + list(mech.products[j])
@@ -163,11 +188,13 @@ def main():
                 "frac": mlp_tf / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "mlp GEMMs",
                 "flops_per_cell": train.mlp_flops_per_cell(ctx.dims)}
         phases = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]} for k, v in ph_a.items()}
+        acc_ann = ann_vs_di(ctx, mech, Y0, T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(),
+                            T_di, Y_di, chemk.CELL_ROUTED_DI)
         result.update({"value": ann_cups, "ms_per_step": 1e3 * wall_a / args.steps,
                        "dtype": "bf16+f64", "config": dict(cfg, path="ANN (BF16 MFMA) + DI fallback"),
                        "roofline": roof, "di": di_info, "di_roofline": roof_di,
                        "ann": {"phases": phases, "routed_cells": cnt["routed"],
-                               "speedup_over_di": ann_cups / di_cups}})
+                               "speedup_over_di": ann_cups / di_cups, "error_vs_di": acc_ann}})
 
     # ---- CPU baseline: the oracle on a bounded sample ---------------------------
     if not args.no_cpu_baseline:
@@ -178,9 +205,14 @@ def main():
         om = oracle.OracleMech(mech)
         cores = oracle.default_threads()
         t0 = time.perf_counter()
-        om.advance(T0[idx], p0[idx], Y0[idx], dt, rtol=o_di.rtol, atol_Y=o_di.atol_Y,
-                   atol_T=o_di.atol_T, nthreads=cores)
+        To, Yo = om.advance(T0[idx], p0[idx], Y0[idx], dt, rtol=o_di.rtol, atol_Y=o_di.atol_Y,
+                            atol_T=o_di.atol_T, nthreads=cores)[:2]
         tc = time.perf_counter() - t0
+        big = Yo > 1e-8
+        result["di_error_vs_oracle"] = {
+            "cells": int(len(idx)), "oracle_rtol": o_di.rtol,
+            "max_rel_Y_above_1e-8": float((np.abs(Y_di[idx] - Yo)[big] / Yo[big]).max()),
+            "max_abs_T_K": float(np.abs(T_di[idx] - To).max())}
         result["cpu_baseline"] = {"value": len(idx) / tc, "unit": "cell-updates/s", "cores": cores,
                                   "kind": "oracle",
                                   "sample": f"{len(idx)} cells stratified over the 3 regions of the "

@@ -240,3 +240,54 @@ def load_or_train(ctx, mech, dt, log=print, n_pairs=None, epochs=None, path=WEIG
     mx, sx, my, sy, _ = ctx.ann_get_norm()
     save(ctx, path, extra={"loss": np.array(hist["loss"])})
     return True
+
+
+def main(argv=None):
+    """Command line: the full pipeline (DI pairs, training, held-out check),
+    the weights saved to --out and a JSON report on stdout."""
+    import argparse
+    import json
+    import sys
+
+    import torch
+
+    from synth import mechanism as sm
+
+    from . import chemk
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--pairs", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=50)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--dt", type=float, default=5e-7)
+    ap.add_argument("--out", default=WEIGHTS)
+    a = ap.parse_args(argv)
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    mech = sm.mech_medium()
+    ctx = chemk.Context(mech)
+    t0 = time.time()
+    data = generate_pairs(ctx, mech, a.dt, a.pairs, log=log)
+    t_data = time.time() - t0
+    hist = train_network(ctx, data, a.dt, epochs=a.epochs, batch=a.batch, log=log)
+    save(ctx, a.out, extra={"loss": np.array(hist["loss"])})
+    T, p, Y, Yn, _ = data
+    hold = hist["holdout_index"]
+    ev = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold])
+    torch.cuda.synchronize()
+    fl = 3 * mlp_flops_per_cell(ctx.dims) * a.batch * hist["steps"]
+    rep = {"pairs": int(T.size), "n_train": hist["n_train"], "n_holdout": hist["n_holdout"],
+           "epochs": a.epochs, "batch": a.batch, "data_s": t_data, "train_s": hist["train_s"],
+           "train_tflops_wall": fl / hist["train_s"] / 1e12,
+           "loss_first": hist["loss"][0], "loss_last": hist["loss"][-1],
+           "holdout_rms_norm_all": ev["rms_norm_all"],
+           "holdout_frozen_rms_norm_all": ev["frozen_rms_norm_all"],
+           "holdout_rms_norm": [float(v) for v in ev["rms_norm"]],
+           "holdout_max_norm": [float(v) for v in ev["max_norm"]], "weights": a.out}
+    print(json.dumps(rep))
+
+
+if __name__ == "__main__":
+    main()

@@ -153,7 +153,7 @@ def test_training_reduces_loss_and_beats_frozen_chemistry():
     ctx = chemk.Context(mech)
     announce("training: small mechanism pipeline")
     data = train.generate_pairs(ctx, mech, 1e-6, 60000, n_rec=60, t_end=0.5, log=announce)
-    hist = train.train_network(ctx, data, 1e-6, epochs=25, batch=1024, log=announce)
+    hist = train.train_network(ctx, data, 1e-6, epochs=80, batch=1024, log=announce)
     assert hist["loss"][-1] < 0.5 * hist["loss"][0]
     hold = hist["holdout_index"]
     T, p, Y, Yn, _ = data
