@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--nx", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--bins", type=int, default=0, help="fixed stiffness bins (skips the autotuner)")
+    ap.add_argument("--wpc", type=int, default=0, help="fixed DI waves per CU (with --bins)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the chemistry advance has no "
@@ -114,7 +116,10 @@ def main():
 
     # DI tuning on the workload (untimed): bins x waves-per-CU grid on copies
     o_di = chemk.default_opts()
-    best_bins, best_wpc, tune_ms = ctx.autotune(Tin, P, Yin, dt, o_di)
+    if args.bins > 0:
+        best_bins, best_wpc, tune_ms = args.bins, args.wpc or 8, 0.0
+    else:
+        best_bins, best_wpc, tune_ms = ctx.autotune(Tin, P, Yin, dt, o_di)
     o_di = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc)
     print(f"bench.py: DI autotune -> bins={best_bins} waves/CU={best_wpc} ({tune_ms:.1f} ms)",
           file=sys.stderr)

@@ -165,3 +165,12 @@ def project_delta(Emat, Y, dY, floor=1e-30):
         lam = np.linalg.solve(A, Emat @ dY[c])
         out[c] = dY[c] - w * (Emat.T @ lam)
     return out
+
+
+def post_state(Emat, Y, dY, floor=1e-30):
+    """State after the network's step (the post-processing of the chemistry
+    advance with the learned source term): Y + dY with negative entries set
+    to zero, then the element-conserving projection onto Y's element masses
+    with weights max(., floor).  Returns the new mass fractions."""
+    Yc = np.maximum(Y + dY, 0.0)
+    return Y + project_delta(Emat, Y, Yc - Y, floor)

@@ -143,6 +143,43 @@ def test_adam_step_matches_oracle():
     assert d.max() < 1e-2 * lr + 1e-7
 
 
+def test_ann_advance_matches_oracle_post_step():
+    """ANN mode of chemk_advance against the oracle: the oracle network (same
+    BF16 rounding points), the oracle's post step (negative entries zeroed,
+    element projection) and T from the conserved enthalpy.  Random weights
+    with a 1e-3 output scale drive many species negative, so the clipping is
+    exercised on most cells."""
+    import oracle
+    import torch
+    from paper_2402_18858_amd import chemk
+    mech = sm.mech_medium()
+    ctx, dims, params = _ctx_small_net(mech, seed=11)
+    n = 1000
+    T, p, Y = _states(mech, n, 44)
+    mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
+    Tt, Yt = dev(T), dev(Y)
+    st = torch.full((n,), -1, dtype=torch.int32, device="cuda:0")
+    ctx.advance(Tt, dev(p), Yt, 5e-7, st, None, opts=chemk.default_opts(mode=chemk.MODE_ANN))
+    s, Yg, Tg = host(st), host(Yt), host(Tt)
+    Ws, bs = _unpack(params, dims)
+    o, _ = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
+    E = oann.element_matrix(mech.composition, mech.element_mass)
+    assert (Y + 1e-3 * o < 0).any(1).mean() > 0.5
+    Yo = oann.post_state(E, Y, 1e-3 * o)
+    om = oracle.OracleMech(mech)
+    _, h0 = om.thermo_batch(T, Y)
+    To, sto = om.T_from_h_batch(h0, Yo, T)
+    net = (s == 0) & (sto == 0)
+    err = np.abs(Yg[net] - Yo[net])
+    announce(f"ann advance: {net.sum()} network cells, max |dY| vs oracle {err.max():.2e}, "
+             f"max |dT| {np.abs(Tg[net] - To[net]).max():.2e} K, routed {(s != 0).sum()}")
+    assert net.mean() > 0.9
+    # forward agreement ~1e-4 of the output scale (1e-3) -> 1e-7 in Y
+    assert err.max() < 2e-7
+    assert np.abs(Tg[net] - To[net]).max() < 1e-2
+    assert Yg[net].min() >= -1e-20
+
+
 def test_training_reduces_loss_and_beats_frozen_chemistry():
     """Small end-to-end run of the pipeline on the 9-species mechanism: DI
     labels on the GPU, training by the library's kernels, held-out error

@@ -99,3 +99,28 @@ def test_projection_conserves_elements():
     assert np.abs(out @ E.T).max() < 1e-18
     again = ann.project_delta(E, Y, out)
     assert np.abs(again - out).max() < 1e-19
+
+
+def test_post_state_clips_then_conserves():
+    """Negative predictions are zeroed and the projection restores the element
+    masses exactly, without making a clipped or a positive species negative
+    again; a prediction that needs no clipping is only projected."""
+    mech = sm.mech_medium()
+    E = ann.element_matrix(mech.composition, mech.element_mass)
+    rng = np.random.default_rng(5)
+    Y = rng.dirichlet(0.3 * np.ones(mech.K), 16)
+    Y[:, :6] = 0.0                                   # absent species, as in cold cells
+    Y /= Y.sum(1, keepdims=True)
+    dY = 1e-5 * rng.standard_normal(Y.shape)          # network noise, drives zeros negative
+    out = ann.post_state(E, Y, dY)
+    assert (Y + dY < 0).any()
+    assert out.min() >= -1e-25
+    m0 = Y @ E.T
+    assert (np.abs((out - Y) @ E.T) / np.maximum(m0, 1e-300))[m0 > 1e-12].max() < 1e-14
+    # where nothing is clipped the step equals the plain projection
+    dY2 = np.abs(dY) * 1e-3
+    ref = Y + ann.project_delta(E, Y, dY2)
+    assert np.abs(ann.post_state(E, Y, dY2) - ref).max() < 1e-16   # rounding of Y + dY - Y
+    # clipped species stay at (numerically) zero after the projection
+    clipped = Y + dY < 0
+    assert np.abs(out[clipped]).max() < 1e-25
