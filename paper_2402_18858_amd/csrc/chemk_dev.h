@@ -66,16 +66,20 @@ __device__ __forceinline__ double uniform_d(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the wave, returned as one wave-uniform value.  The butterfly alone
-// does not give identical bits in every lane: the compiler fuses a lane's own
-// product into the first exchange step (an FMA against the partner's rounded
-// product), so partners can differ in the last bit.  Branches taken on such a
-// value would split the wave around later collectives; the broadcast of the
-// first lane's result rules that out.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return uniform_d(v);
+// DPP lane exchanges inside a row of 16 lanes: a VALU operand modifier, so no
+// LDS round trip (ds_bpermute) per step.  quad_perm [1,0,3,2] and [2,3,0,1]
+// swap neighbours at distance 1 and 2, the mirrors pair the two quads of a
+// half row and the two half rows of a row.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL> __device__ __forceinline__ unsigned dpp_u(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
 // value of v in lane src (src wave-uniform)
@@ -83,6 +87,19 @@ __device__ __forceinline__ double bcast(double v, int src) {
     int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
     int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
     return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave as one wave-uniform value: four DPP steps leave every
+// lane with its 16-lane row sum, the four row sums are read as scalars and
+// added in a fixed order.  Uniform by construction (the per-lane partial
+// sums may differ in the last bit: the compiler can fuse a lane's own
+// product into the first step, and branches must never see such values).
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<kDppHalfMirror>(v);
+    v += dpp_d<kDppMirror>(v);
+    return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
 }
 
 // Pivot search: lane of the largest v >= 0 among lanes with cand set (ties ->
@@ -96,14 +113,27 @@ __device__ __forceinline__ int wave_argmax(double v, bool cand) {
         key = (1ull << 63) | ((unsigned long long)__double_as_longlong(v) & ~63ull) |
               (unsigned long long)(63 - lane);
     unsigned lo = (unsigned)key, hi = (unsigned)(key >> 32);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned olo = __shfl_xor(lo, off, WAVE), ohi = __shfl_xor(hi, off, WAVE);
+    auto step = [&](unsigned olo, unsigned ohi) {
         const bool gt = (ohi > hi) | ((ohi == hi) & (olo > lo));
         lo = gt ? olo : lo;
         hi = gt ? ohi : hi;
+    };
+    step(dpp_u<kDppXor1>(lo), dpp_u<kDppXor1>(hi));
+    step(dpp_u<kDppXor2>(lo), dpp_u<kDppXor2>(hi));
+    step(dpp_u<kDppHalfMirror>(lo), dpp_u<kDppHalfMirror>(hi));
+    step(dpp_u<kDppMirror>(lo), dpp_u<kDppMirror>(hi));
+    // the four row maxima as scalars, then the wave maximum
+    unsigned blo = (unsigned)__builtin_amdgcn_readlane((int)lo, 0);
+    unsigned bhi = (unsigned)__builtin_amdgcn_readlane((int)hi, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) {
+        const unsigned rlo = (unsigned)__builtin_amdgcn_readlane((int)lo, r);
+        const unsigned rhi = (unsigned)__builtin_amdgcn_readlane((int)hi, r);
+        const bool gt = (rhi > bhi) | ((rhi == bhi) & (rlo > blo));
+        blo = gt ? rlo : blo;
+        bhi = gt ? rhi : bhi;
     }
-    return 63 - (int)(uniform((int)lo) & 63);
+    return 63 - (int)(blo & 63);
 }
 
 // ---------------------------------------------------------------------------

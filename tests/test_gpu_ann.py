@@ -168,16 +168,24 @@ def test_ann_advance_matches_oracle_post_step():
     Yo = oann.post_state(E, Y, 1e-3 * o)
     om = oracle.OracleMech(mech)
     _, h0 = om.thermo_batch(T, Y)
-    To, sto = om.T_from_h_batch(h0, Yo, T)
+    # T: the oracle's Newton on the GPU's own Y (pure FP64, no network in it)
+    To, sto = om.T_from_h_batch(h0, Yg, T)
     net = (s == 0) & (sto == 0)
-    err = np.abs(Yg[net] - Yo[net])
-    announce(f"ann advance: {net.sum()} network cells, max |dY| vs oracle {err.max():.2e}, "
-             f"max |dT| {np.abs(Tg[net] - To[net]).max():.2e} K, routed {(s != 0).sum()}")
+    d = Yg[net] - Yo[net]
+    dy = 1e-3 * o[net]
+    rel_rms = np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(dy * dy))
+    announce(f"ann advance: {net.sum()} network cells, rel rms dY vs oracle {rel_rms:.2e}, "
+             f"max |dY| {np.abs(d).max():.2e}, max |T - T(h0, Y)| "
+             f"{np.abs(Tg[net] - To[net]).max():.2e} K, routed {(s != 0).sum()}")
     assert net.mean() > 0.9
-    # forward agreement ~1e-4 of the output scale (1e-3) -> 1e-7 in Y
-    assert err.max() < 2e-7
-    assert np.abs(Tg[net] - To[net]).max() < 1e-2
+    # the bar of the forward test: BF16 rounding of activations can flip
+    # between FP32 (MFMA) and FP64 accumulation, one BF16 ulp at a time
+    assert rel_rms < 2e-3
+    assert np.abs(d).max() < 2e-2 * np.abs(dy).max()
+    assert np.abs(Tg[net] - To[net]).max() < 1e-8 * T.max()
     assert Yg[net].min() >= -1e-20
+    m0, m1 = element_mass(mech, Y[net]), element_mass(mech, Yg[net])
+    assert (np.abs(m1 - m0) / np.maximum(m0, 1e-300))[m0 > 1e-12].max() < 1e-12
 
 
 def test_training_reduces_loss_and_beats_frozen_chemistry():
