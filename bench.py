@@ -61,6 +61,8 @@ def ann_vs_di(ctx, mech, Y0, T_a, Y_a, st_a, T_d, Y_d, routed_bit):
     return {"cells": int(net.sum()), "rms_norm_all": float(np.sqrt(np.mean(e * e))),
             "rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(e * e, 0))],
             "max_norm": [round(float(v), 4) for v in np.abs(e).max(0)],
+            "rms_abs": [float(f"{v:.3e}") for v in np.sqrt(np.mean((Y_a[net] - Y_d[net]) ** 2, 0))],
+            "sd_dY_train": [float(f"{v:.3e}") for v in sd_y],
             "max_abs_T_K": float(np.abs(T_a[net] - T_d[net]).max()),
             "rms_abs_T_K": float(np.sqrt(np.mean((T_a[net] - T_d[net]) ** 2))),
             "element_drift_max": float(drift[m0 > 1e-12].max())}

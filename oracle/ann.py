@@ -167,10 +167,14 @@ def project_delta(Emat, Y, dY, floor=1e-30):
     return out
 
 
-def post_state(Emat, Y, dY, floor=1e-30):
+def post_state(Emat, Y, dY, floor=1e-30, rounds=2):
     """State after the network's step (the post-processing of the chemistry
-    advance with the learned source term): Y + dY with negative entries set
-    to zero, then the element-conserving projection onto Y's element masses
-    with weights max(., floor).  Returns the new mass fractions."""
-    Yc = np.maximum(Y + dY, 0.0)
-    return Y + project_delta(Emat, Y, Yc - Y, floor)
+    advance with the learned source term): `rounds` times, negative entries
+    of the current state set to zero, then the element-conserving projection
+    onto Y's element masses with weights max(., floor).  Returns the new mass
+    fractions."""
+    Yn = Y + dY
+    for _ in range(rounds):
+        Yc = np.maximum(Yn, 0.0)
+        Yn = Y + project_delta(Emat, Y, Yc - Y, floor)
+    return Yn

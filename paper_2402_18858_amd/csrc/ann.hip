@@ -125,11 +125,14 @@ __global__ void __launch_bounds__(POST_CELLS) post_kernel(DevMech m, NormDev nd,
             const int c = base + threadIdx.x;
             double *y = sY + threadIdx.x * ld;   // Y_in + dY
             bool bad = route[c] != 0;
-            if (!bad && project) {
-                // negative predictions are set to zero (NaN is kept for the
-                // finiteness check), then the element-conserving projection
-                // y <- y - w E^T (E w E^T)^-1 (E y - E Y_in), w = max(y, 1e-30),
-                // which moves species held at zero by ~1e-30 only
+            // Two rounds of: negative entries set to zero (NaN is kept for the
+            // finiteness check), then the element-conserving projection
+            // y <- y - w E^T (E w E^T)^-1 (E y - E Y_in), w = max(y, 1e-30),
+            // which moves species held at zero by ~1e-30 only.  The second
+            // round catches the small species the first correction pushed
+            // below zero.
+#pragma unroll 1
+            for (int round = 0; round < 2 && !bad && project; ++round) {
                 for (int k = 0; k < K; ++k)
                     if (y[k] < 0.0) y[k] = 0.0;
                 double A[E][E], r[E];

@@ -215,9 +215,9 @@ extern "C" int chemk_ctx_create(int device, const chemk_mech *m, chemk_ctx **out
     c->N = m->K + 1;
     const int K = m->K, R = m->R, E = m->E;
     if (di_template_N(c->N) < 0) return fail(CHEMK_E_UNSUPPORTED, "K=%d too large", K);
-    if (di_lds_bytes(K, R, di_template_N(c->N)) > 64 * 1024)
-        return fail(CHEMK_E_UNSUPPORTED, "mechanism needs %zu bytes of LDS per wave (> 64 KiB)",
-                    di_lds_bytes(K, R, di_template_N(c->N)));
+    if (di_block_lds_bytes(K, R) > 64 * 1024)
+        return fail(CHEMK_E_UNSUPPORTED, "mechanism needs %zu bytes of LDS per DI workgroup (> 64 KiB)",
+                    di_block_lds_bytes(K, R));
 
     // host-side tables
     std::vector<double> W(K), invW(K);

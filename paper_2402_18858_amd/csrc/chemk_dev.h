@@ -278,7 +278,7 @@ __device__ __forceinline__ double wave_rhs(const DevMech &m, const Lds &L, doubl
     double wk = 0.0;
     if (sp) {
         const int b = m.inc_start[lane], en = m.inc_start[lane + 1];
-#pragma unroll 1
+#pragma unroll 4
         for (int i = b; i < en; ++i) wk += m.inc_nu[i] * L.q[m.inc_r[i]];
     }
     const double chat = wave_sum(Yk * cpR * iw);     // sum_k Y_k (cp_k/R) / W_k
@@ -381,7 +381,7 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
     double wk = 0.0;
     if (sp) {
         const int b = m.inc_start[lane], en = m.inc_start[lane + 1];
-#pragma unroll 1
+#pragma unroll 4
         for (int i = b; i < en; ++i) wk += m.inc_nu[i] * L.q[m.inc_r[i]];
     }
     const double uk = sp ? L.u[lane] : 0.0;

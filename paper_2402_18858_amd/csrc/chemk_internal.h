@@ -62,6 +62,7 @@ struct DevMech;
 // di.hip
 int di_template_N(int Nreal);
 size_t di_lds_bytes(int K, int R, int N);
+size_t di_block_lds_bytes(int K, int R);   // LDS of one DI workgroup
 hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *queue,
                      int *counter, double *T, const double *p, double *Y, double dt,
                      double rtol, double atolY, double atolT, double h0_frac, int max_steps,

@@ -64,8 +64,21 @@ __device__ __forceinline__ bool wave_lu(const Lds &L, int n, int &mystep) {
         if (mystep == n) {   // rows still open (the pivot row itself is now closed)
             const double l = ak / pv;
             row[k] = l;
+            // four columns per pass: all eight LDS reads are issued before the
+            // first use, so one wait covers them (the row update is otherwise a
+            // chain of load latencies)
+            int j = k + 1;
 #pragma unroll 1
-            for (int j = k + 1; j < n; ++j) row[j] -= l * prow[j];
+            for (; j + 4 <= n; j += 4) {
+                const double p0 = prow[j], p1 = prow[j + 1], p2 = prow[j + 2], p3 = prow[j + 3];
+                const double r0 = row[j], r1 = row[j + 1], r2 = row[j + 2], r3 = row[j + 3];
+                row[j] = r0 - l * p0;
+                row[j + 1] = r1 - l * p1;
+                row[j + 2] = r2 - l * p2;
+                row[j + 3] = r3 - l * p3;
+            }
+#pragma unroll 1
+            for (; j < n; ++j) row[j] -= l * prow[j];
         }
         wave_sync();
     }
@@ -81,20 +94,53 @@ __device__ __forceinline__ double wave_solve(const Lds &L, int n, int src, doubl
     const double *row = L.J + src * L.ld;
     // right-hand side in pivot order
     double z = __shfl(b, src, WAVE);
-    // forward: L y = Pb (unit lower triangle)
+    // forward: L y = Pb (unit lower triangle).  The matrix entries of four
+    // steps are read ahead (they do not depend on z); the broadcasts stay in
+    // order.
+    const bool in = lane < n;
+    int k = 0;
 #pragma unroll 1
-    for (int k = 0; k < n - 1; ++k) {
+    for (; k + 4 <= n - 1; k += 4) {
+        const double a0 = row[k], a1 = row[k + 1], a2 = row[k + 2], a3 = row[k + 3];
+        double zk = bcast(z, k);
+        if (in && lane > k) z -= a0 * zk;
+        zk = bcast(z, k + 1);
+        if (in && lane > k + 1) z -= a1 * zk;
+        zk = bcast(z, k + 2);
+        if (in && lane > k + 2) z -= a2 * zk;
+        zk = bcast(z, k + 3);
+        if (in && lane > k + 3) z -= a3 * zk;
+    }
+#pragma unroll 1
+    for (; k < n - 1; ++k) {
         const double zk = bcast(z, k);
-        if (lane > k && lane < n) z -= row[k] * zk;
+        if (in && lane > k) z -= row[k] * zk;
     }
     // backward: U x = y
+    k = n - 1;
 #pragma unroll 1
-    for (int k = n - 1; k >= 0; --k) {
+    for (; k >= 3; k -= 4) {
+        const double a0 = row[k], a1 = row[k - 1], a2 = row[k - 2], a3 = row[k - 3];
+        double xk = bcast(z * rdiag, k);
+        if (lane < k) z -= a0 * xk;
+        if (lane == k) z = xk;
+        xk = bcast(z * rdiag, k - 1);
+        if (lane < k - 1) z -= a1 * xk;
+        if (lane == k - 1) z = xk;
+        xk = bcast(z * rdiag, k - 2);
+        if (lane < k - 2) z -= a2 * xk;
+        if (lane == k - 2) z = xk;
+        xk = bcast(z * rdiag, k - 3);
+        if (lane < k - 3) z -= a3 * xk;
+        if (lane == k - 3) z = xk;
+    }
+#pragma unroll 1
+    for (; k >= 0; --k) {
         const double xk = bcast(z * rdiag, k);
         if (lane < k) z -= row[k] * xk;
         if (lane == k) z = xk;
     }
-    return lane < n ? z : 0.0;
+    return in ? z : 0.0;
 }
 
 struct DIParams {
@@ -280,7 +326,8 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
             status = CHEMK_CELL_SINGULAR;
             break;
         }
-        const int src = act ? L.piv[lane] : lane;
+        // lanes past the system read row 0 (in the slice; their results are unused)
+        const int src = act ? L.piv[lane] : 0;
         const double rdiag = act ? 1.0 / L.J[src * L.ld + lane] : 0.0;
         const double ih = 1.0 / h;
         u0 = wave_solve(L, Na, src, rdiag, f0);
@@ -349,15 +396,27 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
     return status;
 }
 
+// Waves per workgroup of the DI kernel; each wave has its own LDS slice and
+// its own cells (no block-level synchronisation).
+#ifndef CHEMK_DI_WPB
+#define CHEMK_DI_WPB 1
+#endif
+constexpr int kDiWavesPerBlock = CHEMK_DI_WPB;
+
+__host__ __device__ inline int di_slice_doubles(int K, int R) {
+    return (lds_doubles_per_wave(K, R, K + 1) + 1) & ~1;   // 16-byte aligned slices
+}
+
 // Persistent DI kernel: waves pull items from the queue until it is drained.
-__global__ void __launch_bounds__(64) di_kernel(DevMech m, const int *__restrict__ n_items_p,
+__global__ void __launch_bounds__(64 * kDiWavesPerBlock) di_kernel(DevMech m, const int *__restrict__ n_items_p,
                                                 const int *__restrict__ queue, int *counter,
                                                 double *T, const double *p, double *Y,
                                                 double dt, DIParams o, int *status,
                                                 int *nsteps, unsigned long long *stats,
                                                 int status_or) {
     extern __shared__ double lds[];
-    const Lds L = carve_lds(lds, m.K, m.R, m.K + 1);
+    const int wv = uniform((int)(threadIdx.x >> 6));   // wave index in the block, as a scalar
+    const Lds L = carve_lds(lds + wv * di_slice_doubles(m.K, m.R), m.K, m.R, m.K + 1);
     const int lane = lane_id();
     const int K = m.K;
     const int n_items = *n_items_p;
@@ -464,6 +523,10 @@ __global__ void scatter_kernel(const int *bin, int n, int *offs, int *queue) {
 // ---------------------------------------------------------------------------
 int di_template_N(int Nreal) { return Nreal >= 2 && Nreal <= 64 ? Nreal : -1; }
 
+size_t di_block_lds_bytes(int K, int R) {
+    return sizeof(double) * (size_t)di_slice_doubles(K, R) * kDiWavesPerBlock;
+}
+
 size_t di_lds_bytes(int K, int R, int N) {
     return sizeof(double) * (size_t)lds_doubles_per_wave(K, R, N);
 }
@@ -474,9 +537,10 @@ hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *
                      int project, int *status, int *nsteps, unsigned long long *stats,
                      int status_or, hipStream_t s) {
     DIParams o{rtol, atolY, atolT, h0_frac, max_steps, project};
-    const size_t lds = di_lds_bytes(m.K, m.R, m.K + 1);
-    hipLaunchKernelGGL(di_kernel, dim3(grid), dim3(64), lds, s, m, n_items, queue, counter, T, p,
-                       Y, dt, o, status, nsteps, stats, status_or);
+    const size_t lds = di_block_lds_bytes(m.K, m.R);
+    const int blocks = (grid + kDiWavesPerBlock - 1) / kDiWavesPerBlock;
+    hipLaunchKernelGGL(di_kernel, dim3(blocks), dim3(64 * kDiWavesPerBlock), lds, s, m, n_items,
+                       queue, counter, T, p, Y, dt, o, status, nsteps, stats, status_or);
     return hipGetLastError();
 }
 
