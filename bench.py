@@ -42,6 +42,25 @@ def di_flops_per_step(K, R, nnz):
     return 5 * rhs + jac + lu + 6 * solve + 6 * stage
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs summarised in profiles/traffic.json (scaled by the copy calibration),
+    or None when the kernel's sources changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(key)
+    if not entry:
+        return None
+    srcs = {"di_kernel": ("di.hip", "chemk_dev.h"), "mlp_forward": ("gemm.hip",)}[key]
+    h = hashlib.sha1()
+    for f in srcs:
+        with open(os.path.join(ROOT, "paper_2402_18858_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return entry["bytes"] if h.hexdigest()[:16] == entry["sources_sha1"] else None
+
+
 def element_mass(mech, Y):
     comp = mech.composition.astype(np.float64)
     Em = comp * mech.element_mass[None, :] / (comp @ mech.element_mass)[:, None]
@@ -90,6 +109,7 @@ def main():
     from synth import mechanism as sm, workload as sw
 
     mech = sm.mech_medium()
+    nx_default = args.nx == 64          # the block the stored counters were taken on
     T0, p0, Y0, region = sw.flame_block(mech, args.nx, 2002)
     n, K = Y0.shape
     dt = 5e-7
@@ -169,8 +189,9 @@ def main():
                "tuning": {"bins": best_bins, "waves_per_cu": best_wpc},
                "rtol": o_di.rtol, "atol_Y": o_di.atol_Y}
     roof_di = {"bound": "alu", "achieved": di_tflops, "peak": PEAK_FP64_TFLOPS,
-               "unit": "TFLOP/s", "frac": di_tflops / PEAK_FP64_TFLOPS, "traffic": None,
-               "kernel": f"di_kernel<{K + 1}>",
+               "unit": "TFLOP/s", "frac": di_tflops / PEAK_FP64_TFLOPS,
+               "traffic": measured_traffic("di_kernel") if nx_default else None,
+               "kernel": f"di_kernel (N = {K + 1})",
                "flops_per_step_per_cell": fl_step, "rodas_steps": steps_total}
 
     result = {"metric": "chem cell-updates/s (BF16 ANN vs FP64 DI), 262k cells x 32 sp; err vs oracle",
@@ -192,7 +213,10 @@ def main():
         mlp_flops = train.mlp_flops_per_cell(ctx.dims) * n * args.steps
         mlp_tf = mlp_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else 0.0
         roof = {"bound": "mfma", "achieved": mlp_tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": mlp_tf / PEAK_BF16_TFLOPS, "traffic": None, "kernel": "mlp GEMMs",
+                "frac": mlp_tf / PEAK_BF16_TFLOPS,
+                "traffic": measured_traffic("mlp_forward") if nx_default else None,
+                "traffic_unit": "bytes per MLP forward of the block (16 GEMM launches)",
+                "kernel": "mlp GEMMs",
                 "flops_per_cell": train.mlp_flops_per_cell(ctx.dims)}
         phases = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]} for k, v in ph_a.items()}
         acc_ann = ann_vs_di(ctx, mech, Y0, T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(),

@@ -38,7 +38,8 @@ constexpr double kGamma = 0.25;
 
 // ---------------------------------------------------------------------------
 // dense LU of the iteration matrix in LDS, one row per lane, implicit
-// partial pivoting (the pivot row is broadcast from LDS; rows are not moved).
+// partial pivoting (the pivot row is read from LDS by every lane; rows are not
+// moved).
 // On return: L.piv[k] = row chosen at step k; that row holds its L
 // multipliers in columns < k and U in columns >= k; mystep = the step at
 // which this lane's row was chosen.  Returns false on an exactly zero pivot.
@@ -48,26 +49,33 @@ __device__ __forceinline__ bool wave_lu(const Lds &L, int n, int &mystep) {
     double *row = L.J + lane * L.ld;
     mystep = lane < n ? n : -1;
     bool ok = true;
+    // ak: this lane's entry in the current pivot column, carried in a register
+    // from one step to the next (the update of column k+1 is done first)
+    double ak = lane < n ? row[0] : 0.0;
 #pragma unroll 1
     for (int k = 0; k < n; ++k) {
         const bool open = mystep == n;
-        const double ak = lane < n ? row[k] : 0.0;
         const int p = wave_argmax(fabs(ak), open);
+        const double pv = bcast(ak, p);   // the pivot, from the pivot lane's register
         if (lane == p) {
             mystep = k;
             L.piv[k] = p;
         }
-        wave_sync();
-        const double *prow = L.J + p * L.ld;
-        const double pv = prow[k];
         if (pv == 0.0) ok = false;
+        const double *prow = L.J + p * L.ld;
+        double next = 0.0;
         if (mystep == n) {   // rows still open (the pivot row itself is now closed)
             const double l = ak / pv;
             row[k] = l;
+            int j = k + 1;
+            if (j < n) {
+                next = row[j] - l * prow[j];
+                row[j] = next;
+                ++j;
+            }
             // four columns per pass: all eight LDS reads are issued before the
             // first use, so one wait covers them (the row update is otherwise a
             // chain of load latencies)
-            int j = k + 1;
 #pragma unroll 1
             for (; j + 4 <= n; j += 4) {
                 const double p0 = prow[j], p1 = prow[j + 1], p2 = prow[j + 2], p3 = prow[j + 3];
@@ -80,6 +88,7 @@ __device__ __forceinline__ bool wave_lu(const Lds &L, int n, int &mystep) {
 #pragma unroll 1
             for (; j < n; ++j) row[j] -= l * prow[j];
         }
+        ak = next;
         wave_sync();
     }
     return ok;
