@@ -40,9 +40,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Box-Cox of a mass fraction (negative round-off clamped to 0), in FP64:
+// x^lambda as exp(lambda ln x), a third of the work of the library pow, with
+// a relative error of a few ulp (far below the BF16 rounding that follows).
 __device__ __forceinline__ double box_cox(double y) {
-    const double x = y > 0.0 ? y : 0.0;
-    return (pow(x, BCT_LAMBDA) - 1.0) / BCT_LAMBDA;
+    const double p = y > 0.0 ? exp(BCT_LAMBDA * log(y)) : 0.0;
+    return (p - 1.0) / BCT_LAMBDA;
 }
 
 struct NormDev {
@@ -214,19 +217,26 @@ __global__ void __launch_bounds__(POST_CELLS) post_kernel(DevMech m, NormDev nd,
             }
             double Tn = T[c];
             if (!bad) {
-                // Newton on h(T) = h0 (then bisection), as in the property update
+                // Newton on h(T) = h0, as in the property update.  The mixture
+                // enthalpy is itself a NASA-7 polynomial in T with coefficients
+                // B_j = sum_k (Y_k / W_k) a_jk, built once: each iteration then
+                // costs one polynomial instead of one per species.
                 const double h0 = h0R[c];
+                double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                for (int k = 0; k < K; ++k) {
+                    const double w = y[k] * m.invW[k];
+                    const double *a = m.nasa + 7 * k;
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) B[j] += w * a[j];
+                }
                 int st = 1;
                 for (int it = 0; it < 50; ++it) {
-                    const double invT = 1.0 / Tn;
-                    double c_ = 0.0, hh = 0.0;
-                    for (int k = 0; k < K; ++k) {
-                        double cpR, hRT;
-                        sp_cp_h(m.nasa + 7 * k, Tn, invT, cpR, hRT);
-                        c_ += y[k] * m.invW[k] * cpR;
-                        hh += y[k] * m.invW[k] * hRT;
-                    }
-                    const double dT = (hh * Tn - h0) / c_;
+                    const double t = Tn;
+                    // cp/R and h/R of the mixture (per unit mass)
+                    const double c_ = B[0] + t * (B[1] + t * (B[2] + t * (B[3] + t * B[4])));
+                    const double hT = t * (B[0] + t * (B[1] * 0.5 + t * (B[2] * (1.0 / 3.0) +
+                                      t * (B[3] * 0.25 + t * B[4] * 0.2)))) + B[5];
+                    const double dT = (hT - h0) / c_;
                     Tn -= dT;
                     if (!isfinite(Tn)) break;
                     if (fabs(dT) <= 1e-12 * fabs(Tn)) {

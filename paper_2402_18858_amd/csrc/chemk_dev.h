@@ -102,38 +102,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
 }
 
-// Pivot search: lane of the largest v >= 0 among lanes with cand set (ties ->
-// lowest lane), wave-uniform.  The key packs the bits of v (non-negative
-// doubles order like unsigned integers) with the lane in the 6 low mantissa
-// bits, so candidates closer than ~1e-14 relative are tie-broken by lane.
+// Pivot search: the lane of (about) the largest v >= 0 among lanes with cand
+// set, wave-uniform.  The 32-bit key holds a candidate bit, the exponent and
+// the top 14 mantissa bits of v (non-negative doubles order like unsigned
+// integers) and the lane in the 6 low bits: candidates within a relative 6e-5
+// of each other are tie-broken to the lowest lane (partial pivoting needs a
+// large pivot, not the largest to the last bit: |l| <= 1 + 6e-5).  One DPP
+// max per step, then the four row maxima as scalars.
 __device__ __forceinline__ int wave_argmax(double v, bool cand) {
     const int lane = lane_id();
-    unsigned long long key = 0ull;
-    if (cand)
-        key = (1ull << 63) | ((unsigned long long)__double_as_longlong(v) & ~63ull) |
-              (unsigned long long)(63 - lane);
-    unsigned lo = (unsigned)key, hi = (unsigned)(key >> 32);
-    auto step = [&](unsigned olo, unsigned ohi) {
-        const bool gt = (ohi > hi) | ((ohi == hi) & (olo > lo));
-        lo = gt ? olo : lo;
-        hi = gt ? ohi : hi;
-    };
-    step(dpp_u<kDppXor1>(lo), dpp_u<kDppXor1>(hi));
-    step(dpp_u<kDppXor2>(lo), dpp_u<kDppXor2>(hi));
-    step(dpp_u<kDppHalfMirror>(lo), dpp_u<kDppHalfMirror>(hi));
-    step(dpp_u<kDppMirror>(lo), dpp_u<kDppMirror>(hi));
-    // the four row maxima as scalars, then the wave maximum
-    unsigned blo = (unsigned)__builtin_amdgcn_readlane((int)lo, 0);
-    unsigned bhi = (unsigned)__builtin_amdgcn_readlane((int)hi, 0);
-#pragma unroll
-    for (int r = 16; r < 64; r += 16) {
-        const unsigned rlo = (unsigned)__builtin_amdgcn_readlane((int)lo, r);
-        const unsigned rhi = (unsigned)__builtin_amdgcn_readlane((int)hi, r);
-        const bool gt = (rhi > bhi) | ((rhi == bhi) & (rlo > blo));
-        blo = gt ? rlo : blo;
-        bhi = gt ? rhi : bhi;
-    }
-    return 63 - (int)(blo & 63);
+    const unsigned hi = (unsigned)__double2hiint(v);
+    unsigned key = cand ? (0x80000000u | (hi & 0x7fffffc0u) | (unsigned)(63 - lane)) : 0u;
+    key = max(key, dpp_u<kDppXor1>(key));
+    key = max(key, dpp_u<kDppXor2>(key));
+    key = max(key, dpp_u<kDppHalfMirror>(key));
+    key = max(key, dpp_u<kDppMirror>(key));
+    const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
+    const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)key, 16);
+    const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)key, 32);
+    const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)key, 48);
+    const unsigned best = max(max(r0, r1), max(r2, r3));
+    return 63 - (int)(best & 63u);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,6 +208,7 @@ __device__ __forceinline__ CellScalars cell_scalars(const DevMech &m, double p_c
 // Rate constants and fluxes of reaction r (the law of the header comment).
 struct RxnEval {
     double lnkf, qf, qr, dlnKc_T, dHr;   // dlnKc_T = d ln Kc / dT, dHr = sum nu h/RT
+    double kfM, krM;                     // k_f [M] and k_r [M] ([M] = 1 without third body)
 };
 
 __device__ __forceinline__ RxnEval rxn_eval(const DevMech &m, const Lds &L, int r,
@@ -228,7 +218,9 @@ __device__ __forceinline__ RxnEval rxn_eval(const DevMech &m, const Lds &L, int 
     e.lnkf = pr.x + pr.y * c.lnT - pr.z * c.invT;
     const double kf = exp(e.lnkf);
     const double Ma = fl.x ? c.M : 1.0;
-    e.qf = kf * Ma * L.C[s4.x] * (s4.y >= 0 ? L.C[s4.y] : 1.0);
+    e.kfM = kf * Ma;
+    e.krM = 0.0;
+    e.qf = e.kfM * L.C[s4.x] * (s4.y >= 0 ? L.C[s4.y] : 1.0);
     e.qr = 0.0;
     e.dlnKc_T = 0.0;
     e.dHr = 0.0;
@@ -236,7 +228,8 @@ __device__ __forceinline__ RxnEval rxn_eval(const DevMech &m, const Lds &L, int 
         const double dg = L.gRT[s4.z] + (s4.w >= 0 ? L.gRT[s4.w] : 0.0) - L.gRT[s4.x] -
                           (s4.y >= 0 ? L.gRT[s4.y] : 0.0);
         const double lnKc = -dg + fl.z * lnPref;
-        e.qr = exp(e.lnkf - lnKc) * Ma * L.C[s4.z] * (s4.w >= 0 ? L.C[s4.w] : 1.0);
+        e.krM = exp(e.lnkf - lnKc) * Ma;
+        e.qr = e.krM * L.C[s4.z] * (s4.w >= 0 ? L.C[s4.w] : 1.0);
         if (want_T) {
             e.dHr = L.hRT[s4.z] + (s4.w >= 0 ? L.hRT[s4.w] : 0.0) - L.hRT[s4.x] -
                     (s4.y >= 0 ? L.hRT[s4.y] : 0.0);
@@ -338,25 +331,11 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
         const int sp_[4] = {s4.x, s4.y, s4.z, s4.w};
         const double nu_[4] = {-1.0, -1.0, 1.0, 1.0};
         // dq/dC of each slot (product rule, so a doubled species gets both terms)
-        const double kfM = e.qf, krM = e.qr;
         double dq_[4];
-        {
-            const double cf = exp(e.lnkf) * (fl.x ? c.M : 1.0);
-            dq_[0] = cf * (s4.y >= 0 ? L.C[s4.y] : 1.0);
-            dq_[1] = s4.y >= 0 ? cf * L.C[s4.x] : 0.0;
-            double cr = 0.0;
-            if (fl.y) {
-                // k_r [M] from q_r when the concentrations are non-zero would divide;
-                // recompute it instead
-                const double dg = L.gRT[s4.z] + (s4.w >= 0 ? L.gRT[s4.w] : 0.0) - L.gRT[s4.x] -
-                                  (s4.y >= 0 ? L.gRT[s4.y] : 0.0);
-                cr = exp(e.lnkf + dg - fl.z * lnPref) * (fl.x ? c.M : 1.0);
-            }
-            dq_[2] = -cr * (s4.w >= 0 ? L.C[s4.w] : 1.0);
-            dq_[3] = s4.w >= 0 ? -cr * L.C[s4.z] : 0.0;
-            (void)kfM;
-            (void)krM;
-        }
+        dq_[0] = e.kfM * (s4.y >= 0 ? L.C[s4.y] : 1.0);
+        dq_[1] = s4.y >= 0 ? e.kfM * L.C[s4.x] : 0.0;
+        dq_[2] = -e.krM * (s4.w >= 0 ? L.C[s4.w] : 1.0);
+        dq_[3] = s4.w >= 0 ? -e.krM * L.C[s4.z] : 0.0;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int k = sp_[a];

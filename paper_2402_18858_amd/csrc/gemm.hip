@@ -9,8 +9,10 @@
 // the tile loader transposes through LDS.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves, each
-// 64 x 64 = 4 x 4 MFMA tiles of 16 x 16), K step 64 (two MFMA k-steps),
-// double-buffered LDS with a padded row stride.  Workgroups are mapped to
+// 64 x 64 in MFMA tiles of 16 x 16), K step 64 (two MFMA k-steps),
+// double-buffered LDS with a padded row stride.  (The kernel is templated on
+// the tile; a 256 x 256 tile with one workgroup per CU measured slower: the
+// K loop is bound by the latency of the next slab's global loads.)  Workgroups are mapped to
 // tiles so that each of the 8 XCDs walks a contiguous range of row blocks
 // (the A rows it streams stay in that XCD's L2).
 #include <hip/hip_runtime.h>
@@ -23,14 +25,19 @@ namespace chemk {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(4))) float floatx4_t;
 
-constexpr int BM = 128, BN = 128, BK = 64;
-constexpr int LDS_LD = BK + 8;   // bf16 elements per LDS row (16-byte pad)
 constexpr int NTHREADS = 256;
+// bf16 elements per LDS row for a K step of BK (16-byte pad)
+template <int BK> constexpr int lds_ld() { return BK + 8; }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+typedef __attribute__((ext_vector_type(2))) float floatx2_t;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
+
+// two FP32 -> packed BF16 (round to nearest even), one v_cvt_pk_bf16_f32
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const bf16x2_t r = __builtin_convertvector((floatx2_t){lo, hi}, bf16x2_t);
+    uint32_t u;
+    __builtin_memcpy(&u, &r, 4);
+    return u;
 }
 
 // erf by Abramowitz & Stegun 7.1.26 (Hastings' rational form): absolute
@@ -57,22 +64,25 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
            x * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x) * 0.39894228040143268f;
 }
 
-// load the (rows x BK) slab of an operand into LDS [rows][LDS_LD]
-template <bool KCONT>
+// load the (ROWS x BK) slab of an operand into registers, then LDS [ROWS][LDS_LD]
+template <int ROWS, int BK, bool KCONT>
 __device__ __forceinline__ void load_tile(const uint16_t *__restrict__ G, int ld, int row0,
-                                          int rows_total, int k0, int K, uint4 (&reg)[4]) {
+                                          int rows_total, int k0, int K,
+                                          uint4 (&reg)[ROWS * BK / 8 / NTHREADS]) {
+    constexpr int KC = BK / 8;            // chunks of 8 bf16 per row
     const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = t + q * NTHREADS;   // 0..1023 chunks of 8 bf16
+    for (int q = 0; q < ROWS * BK / 8 / NTHREADS; ++q) {
+        const int c = t + q * NTHREADS;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (KCONT) {
-            const int r = c >> 3, kc = c & 7;   // 128 rows x 8 chunks
+            const int r = c / KC, kc = c % KC;   // ROWS rows x KC chunks
             const int gr = row0 + r, gk = k0 + kc * 8;
             if (gr < rows_total && gk < K)
                 v = *reinterpret_cast<const uint4 *>(G + (size_t)gr * ld + gk);
         } else {
-            const int k = c >> 4, mc = c & 15;  // 64 k x 16 chunks of 8 rows
+            constexpr int RC = ROWS / 8;        // chunks of 8 rows per k
+            const int k = c / RC, mc = c % RC;  // BK k x RC chunks
             const int gk = k0 + k, gr = row0 + mc * 8;
             if (gk < K && gr < rows_total)
                 v = *reinterpret_cast<const uint4 *>(G + (size_t)gk * ld + gr);
@@ -81,26 +91,31 @@ __device__ __forceinline__ void load_tile(const uint16_t *__restrict__ G, int ld
     }
 }
 
-template <bool KCONT>
-__device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[4]) {
+template <int ROWS, int BK, bool KCONT>
+__device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[ROWS * BK / 8 / NTHREADS]) {
+    constexpr int KC = BK / 8, LD = lds_ld<BK>();
     const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ROWS * BK / 8 / NTHREADS; ++q) {
         const int c = t + q * NTHREADS;
         if (KCONT) {
-            const int r = c >> 3, kc = c & 7;
-            *reinterpret_cast<uint4 *>(S + r * LDS_LD + kc * 8) = reg[q];
+            const int r = c / KC, kc = c % KC;
+            *reinterpret_cast<uint4 *>(S + r * LD + kc * 8) = reg[q];
         } else {
-            const int k = c >> 4, mc = c & 15;
+            constexpr int RC = ROWS / 8;
+            const int k = c / RC, mc = c % RC;
             const uint16_t *e = reinterpret_cast<const uint16_t *>(&reg[q]);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) S[(mc * 8 + i) * LDS_LD + k] = e[i];
+            for (int i = 0; i < 8; ++i) S[(mc * 8 + i) * LD + k] = e[i];
         }
     }
 }
 
-template <bool AK, bool BKc, int EPI>
+// BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each with a
+// (BM/2) x (BN/2) tile of TM x TN MFMA tiles of 16 x 16.
+template <int BM, int BN, int BK, bool AK, bool BKc, int EPI>
 __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
+    constexpr int TM = BM / 32, TN = BN / 32, LDS_LD = lds_ld<BK>();
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_LD];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDS_LD];
 
@@ -116,50 +131,50 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
     const int m0 = tm * BM, n0 = tn * BN;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
 
-    floatx4_t acc[4][4];
+    floatx4_t acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
 
-    uint4 ra[4], rb[4];
+    uint4 ra[BM * BK / 8 / NTHREADS], rb[BN * BK / 8 / NTHREADS];
     const int KT = (g.K + BK - 1) / BK;
-    load_tile<AK>(g.A, g.lda, m0, g.M, 0, g.K, ra);
-    load_tile<BKc>(g.B, g.ldb, n0, g.N, 0, g.K, rb);
-    store_tile<AK>(sA[0], ra);
-    store_tile<BKc>(sB[0], rb);
+    load_tile<BM, BK, AK>(g.A, g.lda, m0, g.M, 0, g.K, ra);
+    load_tile<BN, BK, BKc>(g.B, g.ldb, n0, g.N, 0, g.K, rb);
+    store_tile<BM, BK, AK>(sA[0], ra);
+    store_tile<BN, BK, BKc>(sB[0], rb);
     __syncthreads();
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int kt = 0; kt < KT; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < KT) {
-            load_tile<AK>(g.A, g.lda, m0, g.M, (kt + 1) * BK, g.K, ra);
-            load_tile<BKc>(g.B, g.ldb, n0, g.N, (kt + 1) * BK, g.K, rb);
+            load_tile<BM, BK, AK>(g.A, g.lda, m0, g.M, (kt + 1) * BK, g.K, ra);
+            load_tile<BN, BK, BKc>(g.B, g.ldb, n0, g.N, (kt + 1) * BK, g.K, rb);
         }
         const uint16_t *A_ = sA[cur];
         const uint16_t *B_ = sB[cur];
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 32) {
-            bf16x8_t af[4], bfr[4];
+            bf16x8_t af[TM], bfr[TN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
                 af[i] = *reinterpret_cast<const bf16x8_t *>(A_ + (wm + i * 16 + fr) * LDS_LD + ks + fk);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < TN; ++j)
                 bfr[j] = *reinterpret_cast<const bf16x8_t *>(B_ + (wn + j * 16 + fr) * LDS_LD + ks + fk);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j],
                                                                         0, 0, 0);
         }
         if (kt + 1 < KT) {
-            store_tile<AK>(sA[cur ^ 1], ra);
-            store_tile<BKc>(sB[cur ^ 1], rb);
+            store_tile<BM, BK, AK>(sA[cur ^ 1], ra);
+            store_tile<BN, BK, BKc>(sB[cur ^ 1], rb);
         }
         __syncthreads();
     }
@@ -172,20 +187,29 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
     const bool vcf = g.Cf && g.ldc % 4 == 0 && ((uintptr_t)g.Cf & 15) == 0;
     const bool vcb = g.Cb && g.ldcb % 4 == 0 && ((uintptr_t)g.Cb & 7) == 0;
     const bool vz = g.Zin && g.ldz % 4 == 0 && ((uintptr_t)g.Zin & 15) == 0;
+    const bool vbias = g.bias && ((uintptr_t)g.bias & 15) == 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TM; ++i) {
         const int row = m0 + wm + i * 16 + (lane & 15);
         if (row >= g.M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TN; ++j) {
             const int col = n0 + wn + j * 16 + (lane >> 4) * 4;
             if (col >= g.N) continue;
             const floatx4_t v = acc[i][j];
             const bool full = col + 4 <= g.N;
             float z[4];
             if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS) {
+                if (full && vbias) {
+                    const float4 b = *reinterpret_cast<const float4 *>(g.bias + col);
+                    z[0] = v[0] + b.x;
+                    z[1] = v[1] + b.y;
+                    z[2] = v[2] + b.z;
+                    z[3] = v[3] + b.w;
+                } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) z[r] = v[r] + (col + r < g.N ? g.bias[col + r] : 0.f);
+                    for (int r = 0; r < 4; ++r) z[r] = v[r] + (col + r < g.N ? g.bias[col + r] : 0.f);
+                }
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) z[r] = v[r];
@@ -209,16 +233,17 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
                         for (int r = 0; r < 4 && col + r < g.N; ++r) zin[r] = zp[r];
                     }
                 }
-                uint16_t o[4];
+                float a[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    o[r] = f2bf(EPI == EPI_BIAS_GELU ? gelu_f(z[r]) : z[r] * gelu_grad_f(zin[r]));
+                    a[r] = EPI == EPI_BIAS_GELU ? gelu_f(z[r]) : z[r] * gelu_grad_f(zin[r]);
+                const uint2 pk = make_uint2(pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]));
                 uint16_t *dst = g.Cb + (size_t)row * g.ldcb + col;
                 if (full && vcb) {
-                    const uint2 pk = make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16),
-                                                (uint32_t)o[2] | ((uint32_t)o[3] << 16));
                     *reinterpret_cast<uint2 *>(dst) = pk;
                 } else {
+                    const uint16_t o[4] = {(uint16_t)pk.x, (uint16_t)(pk.x >> 16), (uint16_t)pk.y,
+                                           (uint16_t)(pk.y >> 16)};
                     for (int r = 0; r < 4 && col + r < g.N; ++r) dst[r] = o[r];
                 }
             }
@@ -228,18 +253,19 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
 
 hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-    const int grid = ((tiles + 7) / 8) * 8;
-#define GEMM_CASE(AKV, BKV, EP)                                                         \
+#define GEMM_CASE(TB, TK, AKV, BKV, EP)                                                 \
     if (a_kcont == AKV && b_kcont == BKV && epi == EP) {                                \
-        hipLaunchKernelGGL((gemm_bf16_kernel<AKV, BKV, EP>), dim3(grid), dim3(NTHREADS), 0, s, g); \
+        const int tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);                \
+        const int grid = ((tiles + 7) / 8) * 8;                                         \
+        hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP>), dim3(grid),     \
+                           dim3(NTHREADS), 0, s, g);                                    \
         return hipGetLastError();                                                       \
     }
-    GEMM_CASE(true, true, EPI_BIAS_GELU)
-    GEMM_CASE(true, true, EPI_BIAS)
-    GEMM_CASE(true, true, EPI_GELU_GRAD)
-    GEMM_CASE(true, true, EPI_STORE_F32)
-    GEMM_CASE(false, false, EPI_STORE_F32)
+    GEMM_CASE(128, 64, true, true, EPI_BIAS_GELU)
+    GEMM_CASE(128, 64, true, true, EPI_BIAS)
+    GEMM_CASE(128, 64, true, true, EPI_GELU_GRAD)
+    GEMM_CASE(128, 64, true, true, EPI_STORE_F32)
+    GEMM_CASE(128, 64, false, false, EPI_STORE_F32)
 #undef GEMM_CASE
     return hipErrorInvalidValue;
 }

@@ -80,6 +80,39 @@ def test_forward_matches_oracle():
     assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
 
 
+def test_forward_full_network_matches_oracle():
+    """The production network (34-1024-512-256-32) against the oracle network,
+    on a row count ragged against the GEMM tile."""
+    import torch
+    from paper_2402_18858_amd import chemk, train
+    mech = sm.mech_medium()
+    ctx = chemk.Context(mech)
+    dims = train.default_dims(mech.K)
+    ctx.ann_create(dims)
+    params = train.init_params(dims, 21)
+    rng = np.random.default_rng(21)
+    off = 0
+    for i in range(len(dims) - 1):
+        off += dims[i] * dims[i + 1]
+        params[off:off + dims[i + 1]] = rng.normal(0, 0.1, dims[i + 1]).astype(np.float32)
+        off += dims[i + 1]
+    ctx.ann_set_weights(params)
+    n = 777                                   # ragged against both tiles
+    T, p, Y = _states(mech, n, 45)
+    mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
+    X = torch.empty((n, 64), dtype=torch.int16, device="cuda:0")
+    ctx.ann_pack(dev(T), dev(p), dev(Y), None, X, None)
+    out = torch.empty((n, mech.K), dtype=torch.float32, device="cuda:0")
+    ctx.ann_forward_packed(X, out)
+    g = host(out).astype(np.float64)
+    Ws, bs = _unpack(params, dims)
+    o, _ = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
+    rel_rms = np.sqrt(np.mean((g - o) ** 2)) / np.sqrt(np.mean(o ** 2))
+    announce(f"forward (full network): rel rms {rel_rms:.2e}, max abs {np.abs(g - o).max():.2e}")
+    assert rel_rms < 2e-3
+    assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
+
+
 def test_gradients_match_oracle():
     import torch
     mech = sm.mech_medium()
