@@ -10,7 +10,9 @@
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves, each
 // 64 x 64 in MFMA tiles of 16 x 16), K step 64 (two MFMA k-steps),
-// double-buffered LDS with a padded row stride.  (The kernel is templated on
+// double-buffered LDS with a padded row stride, K slabs in flight in a ring
+// of registers ahead of the one being multiplied (buffer loads, which read
+// zeros past an operand's edge, so no load sits behind a branch).  (The kernel is templated on
 // the tile; a 256 x 256 tile with one workgroup per CU measured slower: the
 // K loop is bound by the latency of the next slab's global loads.)  Workgroups are mapped to
 // tiles so that each of the 8 XCDs walks a contiguous range of row blocks
@@ -26,6 +28,12 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(4))) float floatx4_t;
 
 constexpr int NTHREADS = 256;
+// K slabs in flight in registers ahead of the one being multiplied (2 or 3)
+#ifndef CHEMK_GEMM_PREFETCH
+#define CHEMK_GEMM_PREFETCH 2
+#endif
+constexpr int kGemmPrefetch = CHEMK_GEMM_PREFETCH;
+static_assert(kGemmPrefetch == 2 || kGemmPrefetch == 3, "ring depth 2 or 3");
 // bf16 elements per LDS row for a K step of BK (16-byte pad)
 template <int BK> constexpr int lds_ld() { return BK + 8; }
 
@@ -64,30 +72,73 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
            x * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x) * 0.39894228040143268f;
 }
 
-// load the (ROWS x BK) slab of an operand into registers, then LDS [ROWS][LDS_LD]
-template <int ROWS, int BK, bool KCONT>
-__device__ __forceinline__ void load_tile(const uint16_t *__restrict__ G, int ld, int row0,
-                                          int rows_total, int k0, int K,
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
+// wait for outstanding global loads, which are the slabs in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
+
+// Buffer resource over one operand: raw buffer loads return zero for offsets
+// past num_records, which is how the tile loader handles the edges.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const uint16_t *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, (int)bytes, 0x00020000);
+}
+
+// Up to 8 consecutive elements of G from element offset `at` (nvalid of
+// them, zeros after), element by element: for operands whose chunks are not
+// 16-byte aligned or run past the operand's edge.
+__device__ __forceinline__ uint4 load_chunk_slow(const uint16_t *G, size_t at, int nvalid) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (e < nvalid) w[e >> 1] |= (uint32_t)G[at + e] << (16 * (e & 1));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// load the (ROWS x BK) slab of an operand into registers (then LDS
+// [ROWS][LDS_LD]).  Where the operands are stored in whole 16-byte chunks
+// (VEC, chosen by the host), every chunk is one buffer load, and a chunk outside the
+// operand gets an offset past the buffer's end and so reads as zeros: no
+// branch surrounds a load, so the compiler can wait for one slab while later
+// slabs stay in flight.  Other shapes (small training layers) load element by
+// element.  (The host guarantees operands below 2 GiB.)
+template <int ROWS, int BK, bool KCONT, bool VEC>
+__device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const uint16_t *G,
+                                          int ld, int row0, int rows_total, int k0, int K,
                                           uint4 (&reg)[ROWS * BK / 8 / NTHREADS]) {
     constexpr int KC = BK / 8;            // chunks of 8 bf16 per row
     const int t = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < ROWS * BK / 8 / NTHREADS; ++q) {
         const int c = t + q * NTHREADS;
-        uint4 v = make_uint4(0, 0, 0, 0);
+        int gr, gk;
+        size_t at;
+        int nvalid;
         if (KCONT) {
             const int r = c / KC, kc = c % KC;   // ROWS rows x KC chunks
-            const int gr = row0 + r, gk = k0 + kc * 8;
-            if (gr < rows_total && gk < K)
-                v = *reinterpret_cast<const uint4 *>(G + (size_t)gr * ld + gk);
+            gr = row0 + r;
+            gk = k0 + kc * 8;
+            at = (size_t)gr * ld + gk;
+            nvalid = gr < rows_total ? min(8, K - gk) : 0;
         } else {
             constexpr int RC = ROWS / 8;        // chunks of 8 rows per k
             const int k = c / RC, mc = c % RC;  // BK k x RC chunks
-            const int gk = k0 + k, gr = row0 + mc * 8;
-            if (gk < K && gr < rows_total)
-                v = *reinterpret_cast<const uint4 *>(G + (size_t)gk * ld + gr);
+            gk = k0 + k;
+            gr = row0 + mc * 8;
+            at = (size_t)gk * ld + gr;
+            nvalid = gk < K ? min(8, rows_total - gr) : 0;
         }
-        reg[q] = v;
+        if constexpr (VEC) {
+            const int off = nvalid > 0 ? (int)(2 * at) : 0x7fffffff;
+            const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+            reg[q] = make_uint4(v.x, v.y, v.z, v.w);
+        } else {
+            reg[q] = load_chunk_slow(G, at, nvalid);
+        }
     }
 }
 
@@ -113,8 +164,11 @@ __device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[ROWS 
 
 // BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each with a
 // (BM/2) x (BN/2) tile of TM x TN MFMA tiles of 16 x 16.
-template <int BM, int BN, int BK, bool AK, bool BKc, int EPI>
-__global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
+// KTC > 0: the number of K slabs, fixed at compile time, so the K loop is
+// unrolled completely (the compiler's waits can then keep later slabs in
+// flight, which it does not do across a loop back-edge); 0: runtime loop.
+template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC, int KTC>
+__global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     constexpr int TM = BM / 32, TN = BN / 32, LDS_LD = lds_ld<BK>();
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_LD];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDS_LD];
@@ -139,21 +193,31 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
 
-    uint4 ra[BM * BK / 8 / NTHREADS], rb[BN * BK / 8 / NTHREADS];
-    const int KT = (g.K + BK - 1) / BK;
-    load_tile<BM, BK, AK>(g.A, g.lda, m0, g.M, 0, g.K, ra);
-    load_tile<BN, BK, BKc>(g.B, g.ldb, n0, g.N, 0, g.K, rb);
-    store_tile<BM, BK, AK>(sA[0], ra);
-    store_tile<BN, BK, BKc>(sB[0], rb);
+    // Global -> LDS pipeline: slab kt is in LDS buffer kt & 1 while the next
+    // PD slabs are in flight in a ring of register sets.  Each step computes
+    // from LDS, stores slab kt+1 into the other buffer and reuses its
+    // registers for the load of slab kt+PD+1, so a load has PD steps of MFMA
+    // work to arrive.  The ring index is a compile-time constant (the K loop
+    // is unrolled by PD).
+    constexpr int QA = BM * BK / 8 / NTHREADS, QB = BN * BK / 8 / NTHREADS;
+    constexpr int PD = kGemmPrefetch;
+    uint4 ra[PD][QA], rb[PD][QB];
+    const int KT = KTC > 0 ? KTC : (g.K + BK - 1) / BK;
+    const __amdgpu_buffer_rsrc_t rsA =
+        operand_rsrc(g.A, 2ll * g.lda * (AK ? g.M : g.K));
+    const __amdgpu_buffer_rsrc_t rsB =
+        operand_rsrc(g.B, 2ll * g.ldb * (BKc ? g.N : g.K));
+    auto load_slab = [&](uint4 (&a)[QA], uint4 (&b)[QB], int kt) {
+        load_tile<BM, BK, AK, VEC>(rsA, g.A, g.lda, m0, g.M, kt * BK, g.K, a);
+        load_tile<BN, BK, BKc, VEC>(rsB, g.B, g.ldb, n0, g.N, kt * BK, g.K, b);
+    };
+    load_slab(ra[0], rb[0], 0);
+    store_tile<BM, BK, AK>(sA[0], ra[0]);
+    store_tile<BN, BK, BKc>(sB[0], rb[0]);
     __syncthreads();
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    for (int kt = 0; kt < KT; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < KT) {
-            load_tile<BM, BK, AK>(g.A, g.lda, m0, g.M, (kt + 1) * BK, g.K, ra);
-            load_tile<BN, BK, BKc>(g.B, g.ldb, n0, g.N, (kt + 1) * BK, g.K, rb);
-        }
+    auto compute = [&](int cur) {
         const uint16_t *A_ = sA[cur];
         const uint16_t *B_ = sB[cur];
 #pragma unroll
@@ -172,11 +236,40 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j],
                                                                         0, 0, 0);
         }
-        if (kt + 1 < KT) {
-            store_tile<BM, BK, AK>(sA[cur ^ 1], ra);
-            store_tile<BN, BK, BKc>(sB[cur ^ 1], rb);
+    };
+    if (KT == 1) {
+        compute(0);
+    } else {
+        // KT rounded up to whole ring turns; the extra slabs load as zeros
+        const int KTR = (KT + PD - 1) / PD * PD;
+#pragma unroll
+        for (int q = 1; q <= PD; ++q) load_slab(ra[q % PD], rb[q % PD], q);
+        // one step; N = (kt + 1) % PD holds slab kt+1 and then takes slab kt+PD+1
+#define GEMM_STEP(KTV, N)                                                                 \
+        compute((KTV) & 1);                                                               \
+        store_tile<BM, BK, AK>(sA[((KTV) + 1) & 1], ra[N]);                               \
+        store_tile<BN, BK, BKc>(sB[((KTV) + 1) & 1], rb[N]);                              \
+        lds_barrier();                                                                    \
+        load_slab(ra[N], rb[N], (KTV) + PD + 1);
+        auto turn = [&](int kt) {
+            if constexpr (PD == 2) {
+                GEMM_STEP(kt, 1)
+                GEMM_STEP(kt + 1, 0)
+            } else {
+                GEMM_STEP(kt, 1)
+                GEMM_STEP(kt + 1, 2)
+                GEMM_STEP(kt + 2, 0)
+            }
+        };
+        if constexpr (KTC > 0) {
+            constexpr int KTRC = (KTC + PD - 1) / PD * PD;
+#pragma unroll
+            for (int kt = 0; kt < KTRC; kt += PD) turn(kt);
+        } else {
+#pragma unroll 1
+            for (int kt = 0; kt < KTR; kt += PD) turn(kt);
         }
-        __syncthreads();
+#undef GEMM_STEP
     }
 
     // epilogue.  The MFMA computes the 16 x 16 tile transposed (B operand
@@ -251,22 +344,53 @@ __global__ void __launch_bounds__(NTHREADS) gemm_bf16_kernel(GemmArgs g) {
     }
 }
 
+template <bool AKV, bool BKV, int EP>
+static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
+    constexpr int TB = 128, TK = 64;
+    const int tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);
+    const int grid = ((tiles + 7) / 8) * 8;
+    const int kt = (g.K + TK - 1) / TK;
+    // forward layers of the MLP get a K loop unrolled for their slab count
+    constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS);
+#define GEMM_LAUNCH(VECV, KTV)                                                          \
+    hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV, KTV>), dim3(grid), \
+                       dim3(NTHREADS), 0, s, g)
+    if (!vec) {
+        GEMM_LAUNCH(false, 0);
+    } else if constexpr (fwd) {
+        if (kt == 16) GEMM_LAUNCH(true, 16);
+        else if (kt == 8) GEMM_LAUNCH(true, 8);
+        else if (kt == 4) GEMM_LAUNCH(true, 4);
+        else GEMM_LAUNCH(true, 0);
+    } else {
+        GEMM_LAUNCH(true, 0);
+    }
+#undef GEMM_LAUNCH
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-#define GEMM_CASE(TB, TK, AKV, BKV, EP)                                                 \
-    if (a_kcont == AKV && b_kcont == BKV && epi == EP) {                                \
-        const int tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);                \
-        const int grid = ((tiles + 7) / 8) * 8;                                         \
-        hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP>), dim3(grid),     \
-                           dim3(NTHREADS), 0, s, g);                                    \
-        return hipGetLastError();                                                       \
+    if (g.K <= 0) return hipErrorInvalidValue;
+    // byte offsets of the buffer loads are 31-bit
+    const int64_t bytesA = 2ll * g.lda * (a_kcont ? g.M : g.K);
+    const int64_t bytesB = 2ll * g.ldb * (b_kcont ? g.N : g.K);
+    if (bytesA >= (1ll << 31) || bytesB >= (1ll << 31)) return hipErrorInvalidValue;
+    // whole 16-byte chunks in both operands: leading dimensions and chunked
+    // extents multiples of 8 (then the branch-free buffer-load path)
+    const bool vec = g.lda % 8 == 0 && (a_kcont ? g.K : g.M) % 8 == 0 && g.ldb % 8 == 0 &&
+                     (b_kcont ? g.K : g.N) % 8 == 0;
+    if (a_kcont && b_kcont) {
+        switch (epi) {
+            case EPI_BIAS_GELU: return launch_case<true, true, EPI_BIAS_GELU>(g, vec, s);
+            case EPI_BIAS: return launch_case<true, true, EPI_BIAS>(g, vec, s);
+            case EPI_GELU_GRAD: return launch_case<true, true, EPI_GELU_GRAD>(g, vec, s);
+            case EPI_STORE_F32: return launch_case<true, true, EPI_STORE_F32>(g, vec, s);
+            default: return hipErrorInvalidValue;
+        }
     }
-    GEMM_CASE(128, 64, true, true, EPI_BIAS_GELU)
-    GEMM_CASE(128, 64, true, true, EPI_BIAS)
-    GEMM_CASE(128, 64, true, true, EPI_GELU_GRAD)
-    GEMM_CASE(128, 64, true, true, EPI_STORE_F32)
-    GEMM_CASE(128, 64, false, false, EPI_STORE_F32)
-#undef GEMM_CASE
+    if (!a_kcont && !b_kcont && epi == EPI_STORE_F32)
+        return launch_case<false, false, EPI_STORE_F32>(g, vec, s);
     return hipErrorInvalidValue;
 }
 
