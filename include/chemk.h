@@ -229,14 +229,15 @@ int chemk_ann_fit_norm(chemk_ctx *ctx, int64_t n, const double *T, const double 
                        const double *Y, const double *Y_next, double dt, double widen,
                        double neg_tol, void *stream);
 
-/* Device: pack training pairs into network space: X [n, F] BF16 (F = dims[0]
- * rounded up to 32, zero padded, stored as uint16 bit patterns) and the
- * z-scored targets Z [n, K] FP32.                                             */
+/* Device: pack training pairs into network space: X [n, 64] BF16 (the
+ * dims[0] = K + 2 features zero padded to 64 columns, stored as uint16 bit
+ * patterns; X 16-byte aligned, else CHEMK_E_ARG) and, when Y_next is given,
+ * the z-scored targets Z [n, K] FP32.                                         */
 int chemk_ann_pack(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
                    const double *Y, const double *Y_next, uint16_t *X, float *Z,
                    void *stream);
 
-/* Network forward on packed inputs X [n, F] (BF16 bits): out [n, K] FP32, the
+/* Network forward on packed inputs X [n, 64] (BF16 bits): out [n, K] FP32, the
  * z-scored prediction.  Test hook and batch inference.                        */
 int chemk_ann_forward_packed(chemk_ctx *ctx, int64_t n, const uint16_t *X, float *out,
                              void *stream);

@@ -40,12 +40,36 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Box-Cox of a mass fraction (negative round-off clamped to 0), in FP64:
-// x^lambda as exp(lambda ln x), a third of the work of the library pow, with
-// a relative error of a few ulp (far below the BF16 rounding that follows).
+// x^(1/10) for x > 0 (any finite positive double, denormals included), in
+// FP64 without log or exp: x = m 2^(10 q + r) with m in [0.5, 1), r in 0..9,
+// so x^(1/10) = 2^q u^(1/10) with u = m 2^r in [0.5, 512).  A single-precision
+// estimate of u^(1/10) from the hardware log2 and exp2 (relative error below
+// 1e-6) is refined by two Newton steps on t^10 = u, t <- t (0.9 + 0.1 u / t^10)
+// (quadratic: ~1e-12, then the rounding of the last step), which leaves the
+// result within about 2 ulp of the exact root.
+__device__ __forceinline__ double root10(double x) {
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const int q = (((e + 1100) * 6554) >> 16) - 110;   // floor(e / 10), exact for |e| < 1100
+    const double u = __builtin_ldexp(m, e - 10 * q);
+    double t = (double)__builtin_amdgcn_exp2f(0.1f * __builtin_amdgcn_logf((float)u));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double t2 = t * t, t4 = t2 * t2, t10 = t4 * t4 * t2;
+        double r = __builtin_amdgcn_rcp(t10);
+        r = fma(r, fma(-t10, r, 1.0), r);
+        t *= fma(0.1, u * r, 0.9);
+    }
+    return __builtin_ldexp(t, q);
+}
+
+// Box-Cox of a mass fraction (Eq. 7 with lambda = 0.1; negative round-off
+// clamped to 0, NaN kept), in FP64.
+static_assert(BCT_LAMBDA == 0.1, "root10 is the lambda = 0.1 power");
 __device__ __forceinline__ double box_cox(double y) {
-    const double p = y > 0.0 ? exp(BCT_LAMBDA * log(y)) : 0.0;
-    return (p - 1.0) / BCT_LAMBDA;
+    const double r = root10(y);   // on every lane (no branch); unused for y <= 0 or NaN
+    const double p = y > 0.0 ? r : (y == y ? 0.0 : y);
+    return (p - 1.0) * (1.0 / BCT_LAMBDA);
 }
 
 struct NormDev {
@@ -53,213 +77,394 @@ struct NormDev {
 };
 
 // ---------------------------------------------------------------------------
-// ingest: features, envelope flag, conserved enthalpy
+// ingest and post: one lane per cell, the cell's row in registers
 // ---------------------------------------------------------------------------
-constexpr int ING_CELLS = 64;
+// Both kernels are templated on KM >= K (16, 32 or 64: K + 2 <= FPAD bounds K
+// by 62), so every loop over species is unrolled at compile time and the row
+// of a cell lives in registers.  A workgroup is one wave of 64 cells; the
+// rows enter and leave through LDS with coalesced global accesses.  The
+// per-species constants come from a table built once per normalisation
+// (zero-padded to KM), read at compile-time offsets through a restrict
+// pointer: uniform scalar loads into SGPRs, which leaves the vector registers
+// to the rows.
+// ingest table: lo, hi, mu_x, 1/sd_x [FPAD each], nasa [7 KM], 1/W [KM]
+constexpr int ti_lo = 0, ti_hi = FPAD, ti_mu = 2 * FPAD, ti_sd = 3 * FPAD, ti_nasa = 4 * FPAD;
+__host__ __device__ constexpr int ti_invW(int KM) { return 4 * FPAD + 7 * KM; }
+__host__ __device__ constexpr int ti_size(int KM) { return 4 * FPAD + 8 * KM; }
+// post table: E [E KM], 1/W [KM], a_j (j < 6) [6 KM], mu_y [KM], sd_y [KM]
+__host__ __device__ constexpr int tp_invW(int E, int KM) { return E * KM; }
+__host__ __device__ constexpr int tp_a(int E, int KM) { return (E + 1) * KM; }
+__host__ __device__ constexpr int tp_mu(int E, int KM) { return (E + 7) * KM; }
+__host__ __device__ constexpr int tp_sd(int E, int KM) { return (E + 8) * KM; }
+__host__ __device__ constexpr int tp_size(int E, int KM) { return (E + 9) * KM; }
+constexpr int ROW_TAB_DOUBLES = 4 * FPAD + 8 * 64 + (8 + 9) * 64;
 
-__global__ void __launch_bounds__(ING_CELLS) ingest_kernel(DevMech m, NormDev nd, int n,
-                                                           const double *__restrict__ T,
-                                                           const double *__restrict__ p,
-                                                           const double *__restrict__ Y,
-                                                           uint16_t *X, int ldx, int *route,
-                                                           double *h0R) {
-    extern __shared__ double sY[];
-    const int K = m.K, ld = K + 1, F = K + 2;
-    for (int base = blockIdx.x * ING_CELLS; base < n; base += gridDim.x * ING_CELLS) {
-        const int cnt = n - base < ING_CELLS ? n - base : ING_CELLS;
-        const double *src = Y + (size_t)base * K;
-        for (int i = threadIdx.x; i < cnt * K; i += blockDim.x) {
-            const int c = i / K, k = i - c * K;
-            sY[c * ld + k] = src[i];
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const int c = base + threadIdx.x;
-            const double *y = sY + threadIdx.x * ld;
-            const double Tc = T[c], pc = p[c];
-            bool out = false;
-            uint16_t *xr = X + (size_t)c * ldx;
-            double hs = 0.0;
-            const double invT = 1.0 / Tc;
-            for (int k = 0; k < F; ++k) {
-                const double raw = k < K ? box_cox(y[k]) : (k == K ? Tc : pc);
-                if (!(raw >= nd.lo[k] && raw <= nd.hi[k])) out = true;   // NaN -> out
-                xr[k] = f2bf((float)((raw - nd.mu_x[k]) / nd.sd_x[k]));
-                if (k < K) {
-                    double cpR, hRT;
-                    sp_cp_h(m.nasa + 7 * k, Tc, invT, cpR, hRT);
-                    hs += y[k] * m.invW[k] * hRT;
-                }
-            }
-            for (int k = F; k < ldx; ++k) xr[k] = 0;
-            route[c] = out ? 1 : 0;
-            h0R[c] = hs * Tc;
-        }
-        __syncthreads();
+__global__ void row_tables_kernel(DevMech m, NormDev nd, int KM, double *ti, double *tp) {
+    const int K = m.K, F = K + 2, E = m.E;
+    for (int i = threadIdx.x; i < FPAD; i += blockDim.x) {
+        const bool f = i < F;
+        ti[ti_lo + i] = f ? nd.lo[i] : 0.0;
+        ti[ti_hi + i] = f ? nd.hi[i] : 0.0;
+        ti[ti_mu + i] = f ? nd.mu_x[i] : 0.0;
+        ti[ti_sd + i] = f ? 1.0 / nd.sd_x[i] : 1.0;
+    }
+    for (int i = threadIdx.x; i < 7 * KM; i += blockDim.x) ti[ti_nasa + i] = i < 7 * K ? m.nasa[i] : 0.0;
+    for (int i = threadIdx.x; i < KM; i += blockDim.x) {
+        const bool s = i < K;
+        ti[ti_invW(KM) + i] = s ? m.invW[i] : 0.0;
+        tp[tp_invW(E, KM) + i] = s ? m.invW[i] : 0.0;
+        tp[tp_mu(E, KM) + i] = s ? nd.mu_y[i] : 0.0;
+        tp[tp_sd(E, KM) + i] = s ? nd.sd_y[i] : 0.0;
+        for (int j = 0; j < 6; ++j) tp[tp_a(E, KM) + j * KM + i] = s ? m.nasa[7 * i + j] : 0.0;
+        for (int e = 0; e < E; ++e) tp[e * KM + i] = s ? m.Emat[e * K + i] : 0.0;
     }
 }
 
-// ---------------------------------------------------------------------------
-// post: dY = mu + sd * out, element projection, checks, T from h0
-// ---------------------------------------------------------------------------
-constexpr int POST_CELLS = 64;
+constexpr int POST_CELLS = 64;   // ingest and post: one wave per workgroup
 
-template <int E>
-__global__ void __launch_bounds__(POST_CELLS) post_kernel(DevMech m, NormDev nd, int n,
-                                                          double *T, double *Y,
-                                                          const float *__restrict__ out,
-                                                          const int *__restrict__ route,
-                                                          const double *__restrict__ h0R,
-                                                          double neg_tol, int project,
-                                                          int *status, int *nsteps, int *queue,
-                                                          int *n_routed,
-                                                          unsigned long long *stats) {
-    extern __shared__ double sY[];
-    const int K = m.K, ld = K + 1;
-    for (int base = blockIdx.x * POST_CELLS; base < n; base += gridDim.x * POST_CELLS) {
-        const int cnt = n - base < POST_CELLS ? n - base : POST_CELLS;
-        const double *src = Y + (size_t)base * K;
-        for (int i = threadIdx.x; i < cnt * K; i += blockDim.x) {
-            const int c = i / K, k = i - c * K;
-            sY[c * ld + k] = src[i] + (nd.mu_y[k] + nd.sd_y[k] * (double)out[(size_t)base * K + i]);
+// Block copy of the rows of cells [0, cnt) from a row-major global span (K
+// values per cell, contiguous) into an LDS tile of row stride ld, in
+// consecutive global elements per lane; all of a lane's loads are issued
+// before its first LDS store.  Element i is cell i / K, computed with a float
+// reciprocal: exact here, since i < 4096 and the fractional part of
+// (i + 0.5) / K is at least 1 / 128 away from an integer.
+template <int KM, typename Tv>
+__device__ __forceinline__ void rows_to_lds(const Tv *__restrict__ g, int cnt, int K, float invK,
+                                            Tv *s, int ld) {
+    const int total = cnt * K;
+    Tv v[KM];
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+        const int i = r * POST_CELLS + (int)threadIdx.x;
+        v[r] = i < total ? g[i] : Tv(0);
+    }
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+        const int i = r * POST_CELLS + (int)threadIdx.x;
+        if (i < total) {
+            const int c = (int)(((float)i + 0.5f) * invK);
+            s[c * ld + (i - c * K)] = v[r];
         }
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            const int c = base + threadIdx.x;
-            double *y = sY + threadIdx.x * ld;   // Y_in + dY
-            bool bad = route[c] != 0;
-            // Two rounds of: negative entries set to zero (NaN is kept for the
-            // finiteness check), then the element-conserving projection
-            // y <- y - w E^T (E w E^T)^-1 (E y - E Y_in), w = max(y, 1e-30),
-            // which moves species held at zero by ~1e-30 only.  The second
-            // round catches the small species the first correction pushed
-            // below zero.
+    }
+}
+
+// Features (Box-Cox of the K mass fractions, then T and p), z-scored and
+// rounded to BF16 into a row of FPAD inputs; the envelope flag (a raw feature
+// outside [lo, hi] of the training data, or NaN); the enthalpy h(T, Y) / R
+// that the post step conserves.
+template <int KM>
+__global__ void __launch_bounds__(POST_CELLS, 2) ingest_kernel(int K, int n,
+                                                               const double *__restrict__ tab,
+                                                               const double *__restrict__ T,
+                                                               const double *__restrict__ p,
+                                                               const double *__restrict__ Y,
+                                                               uint16_t *__restrict__ X,
+                                                               int *__restrict__ route,
+                                                               double *__restrict__ h0R) {
+    // Rows of Y come in, and rows of X go out, through LDS so that the global
+    // accesses are coalesced.  X rows are FPAD BF16 = 8 chunks of 16 bytes,
+    // staged at a stride of 9 chunks.
+    constexpr int ld = KM + 1, XLD = FPAD / 8 + 1;
+    constexpr int LDS_D = POST_CELLS * (ld > 2 * XLD ? ld : 2 * XLD);
+    __shared__ double s_row[LDS_D];
+    const int base = blockIdx.x * POST_CELLS;
+    const int cnt = n - base < POST_CELLS ? n - base : POST_CELLS;
+    const int lane = threadIdx.x;
+    const bool valid = lane < cnt;
+    const int c = valid ? base + lane : base;
+    rows_to_lds<KM>(Y + (size_t)base * K, cnt, K, 1.0f / (float)K, s_row, ld);
+    __syncthreads();
+    double y[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) y[k] = k < K ? s_row[lane * ld + k] : 0.0;
+    const double Tc = T[c], pc = p[c];
+    const double invT = 1.0 / Tc;
+    // species features; beyond K the row and the tables are zero, which adds
+    // nothing to h and is masked out of the envelope test and the row
+    bool out = false;
+    double hs = 0.0;
+    float fs[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const double raw = box_cox(y[k]);
+        double cpR, hRT;
+        sp_cp_h(tab + ti_nasa + 7 * k, Tc, invT, cpR, hRT);
+        hs += y[k] * tab[ti_invW(KM) + k] * hRT;
+        const bool inside = (raw >= tab[ti_lo + k]) & (raw <= tab[ti_hi + k]);   // NaN -> outside
+        out |= (k < K) & !inside;
+        fs[k] = (float)((raw - tab[ti_mu + k]) * tab[ti_sd + k]);
+    }
+    // T and p: features K and K + 1
+    out |= !((Tc >= tab[ti_lo + K]) & (Tc <= tab[ti_hi + K]));
+    out |= !((pc >= tab[ti_lo + K + 1]) & (pc <= tab[ti_hi + K + 1]));
+    const float fT = (float)((Tc - tab[ti_mu + K]) * tab[ti_sd + K]);
+    const float fp = (float)((pc - tab[ti_mu + K + 1]) * tab[ti_sd + K + 1]);
+    float f[FPAD];
+#pragma unroll
+    for (int j = 0; j < FPAD; ++j) {
+        const float sp = j < KM ? fs[j < KM ? j : 0] : 0.0f;
+        f[j] = j < K ? sp : (j == K ? fT : (j == K + 1 ? fp : 0.0f));
+    }
+    __syncthreads();
+    uint4 *sx = reinterpret_cast<uint4 *>(s_row);
+#pragma unroll
+    for (int q = 0; q < FPAD / 8; ++q) {
+        uint4 v;
+        v.x = (uint32_t)f2bf(f[8 * q + 0]) | ((uint32_t)f2bf(f[8 * q + 1]) << 16);
+        v.y = (uint32_t)f2bf(f[8 * q + 2]) | ((uint32_t)f2bf(f[8 * q + 3]) << 16);
+        v.z = (uint32_t)f2bf(f[8 * q + 4]) | ((uint32_t)f2bf(f[8 * q + 5]) << 16);
+        v.w = (uint32_t)f2bf(f[8 * q + 6]) | ((uint32_t)f2bf(f[8 * q + 7]) << 16);
+        sx[lane * XLD + q] = v;
+    }
+    __syncthreads();
+    uint4 *gx = reinterpret_cast<uint4 *>(X + (size_t)base * FPAD);
+#pragma unroll
+    for (int r = 0; r < FPAD / 8; ++r) {
+        const int j = r * POST_CELLS + lane;   // chunk j: row j / 8, chunk j % 8
+        if (j < cnt * (FPAD / 8)) gx[j] = sx[(j >> 3) * XLD + (j & 7)];
+    }
+    if (valid) {
+        route[c] = out ? 1 : 0;
+        h0R[c] = hs * Tc;
+    }
+}
+
+// post: y = Y_in + dY (dY = mu + sd * out), two rounds of clipping and the
+// element-conserving projection, the admissibility checks, T from h0 by
+// Newton; cells that fail any of it are queued for DI and left unchanged.
+// The table base plus an opaque uniform zero: loads through it are issued in
+// the loop that uses them rather than hoisted out of the round loop, where
+// E * KM doubles would not fit in SGPRs.
+__device__ __forceinline__ const double *fresh_base(const double *__restrict__ t) {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return t + z;
+}
+
+template <int E, int KM>
+__global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
+                                                             const double *__restrict__ tab,
+                                                             double *__restrict__ T,
+                                                             double *__restrict__ Y,
+                                                             const float *__restrict__ out,
+                                                             const int *__restrict__ route,
+                                                             const double *__restrict__ h0R,
+                                                             double neg_tol, int project,
+                                                             int *__restrict__ status,
+                                                             int *__restrict__ nsteps,
+                                                             int *__restrict__ queue,
+                                                             int *__restrict__ n_routed,
+                                                             unsigned long long *__restrict__ stats) {
+    // Rows go through LDS (stride KM + 1: two-way bank conflicts at most) so
+    // that the global reads and writes are coalesced; each lane then holds
+    // its cell's row in registers.
+    constexpr int ld = KM + 1;
+    __shared__ double s_row[POST_CELLS * ld];
+    __shared__ int s_keep[POST_CELLS];
+    const int base = blockIdx.x * POST_CELLS;
+    const int cnt = n - base < POST_CELLS ? n - base : POST_CELLS;
+    const int lane = threadIdx.x;
+    const bool valid = lane < cnt;
+    const int c = valid ? base + lane : base;
+    const float invK = 1.0f / (float)K;
+    const double *__restrict__ tE = tab;
+    rows_to_lds<KM>(Y + (size_t)base * K, cnt, K, invK, s_row, ld);
+    __syncthreads();
+    double y[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) y[k] = k < K ? s_row[lane * ld + k] : 0.0;
+    __syncthreads();
+    float *s_out = reinterpret_cast<float *>(s_row);
+    rows_to_lds<KM>(out + (size_t)base * K, cnt, K, invK, s_out, ld);
+    __syncthreads();
+    // element totals of the input state: the projection's target
+    double eyin[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) acc += tE[a * KM + k] * y[k];
+        eyin[a] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < K) y[k] += tab[tp_mu(E, KM) + k] + tab[tp_sd(E, KM) + k] * (double)s_out[lane * ld + k];
+    bool bad = !valid || route[c] != 0;
+    // Two rounds of: negative entries set to zero (NaN is kept for the
+    // finiteness check), then the projection y <- y - w E^T (E w E^T)^-1
+    // (E y - E Y_in), w = max(y, 1e-30), which moves species held at zero by
+    // ~1e-30 only.  The second round catches the small species the first
+    // correction pushed below zero.  The rounds run on every lane (uniform
+    // control flow keeps one copy of the row live); a routed cell's result
+    // is discarded, and a singular system leaves y unchanged.
+    if (project) {
 #pragma unroll 1
-            for (int round = 0; round < 2 && !bad && project; ++round) {
-                for (int k = 0; k < K; ++k)
-                    if (y[k] < 0.0) y[k] = 0.0;
-                double A[E][E], r[E];
+        for (int round = 0; round < 2; ++round) {
+            double A[E][E], r[E];
+#pragma unroll
+            for (int a = 0; a < E; ++a) {
+                r[a] = -eyin[a];
+#pragma unroll
+                for (int b = 0; b < E; ++b) A[a][b] = 0.0;
+            }
+            const double *__restrict__ tE = fresh_base(tab);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (y[k] < 0.0) y[k] = 0.0;
+                const double w = y[k] > 1e-30 ? y[k] : 1e-30;
 #pragma unroll
                 for (int a = 0; a < E; ++a) {
-                    r[a] = 0.0;
+                    const double ew = tE[a * KM + k] * w;
+                    r[a] += tE[a * KM + k] * y[k];
 #pragma unroll
-                    for (int b = 0; b < E; ++b) A[a][b] = 0.0;
-                }
-                const double *Yin = Y + (size_t)c * K;
-                for (int k = 0; k < K; ++k) {
-                    const double w = y[k] > 1e-30 ? y[k] : 1e-30;
-                    const double d = y[k] - Yin[k];
-                    double Ek[E];
-#pragma unroll
-                    for (int a = 0; a < E; ++a) Ek[a] = m.Emat[a * K + k];
-#pragma unroll
-                    for (int a = 0; a < E; ++a) {
-                        r[a] += Ek[a] * d;
-#pragma unroll
-                        for (int b = 0; b < E; ++b) A[a][b] += Ek[a] * w * Ek[b];
-                    }
-                }
-                // Gaussian elimination with partial pivoting
-                bool ok = true;
-#pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    int piv = k;
-                    double best = fabs(A[k][k]);
-#pragma unroll
-                    for (int i = k + 1; i < E; ++i)
-                        if (fabs(A[i][k]) > best) {
-                            best = fabs(A[i][k]);
-                            piv = i;
-                        }
-                    if (best == 0.0) ok = false;
-#pragma unroll
-                    for (int i = k + 1; i < E; ++i)
-                        if (i == piv) {
-#pragma unroll
-                            for (int j = 0; j < E; ++j) {
-                                const double t = A[k][j];
-                                A[k][j] = A[i][j];
-                                A[i][j] = t;
-                            }
-                            const double t = r[k];
-                            r[k] = r[i];
-                            r[i] = t;
-                        }
-                    if (ok) {
-#pragma unroll
-                        for (int i = k + 1; i < E; ++i) {
-                            const double l = A[i][k] / A[k][k];
-#pragma unroll
-                            for (int j = k; j < E; ++j) A[i][j] -= l * A[k][j];
-                            r[i] -= l * r[k];
-                        }
-                    }
-                }
-                if (ok) {
-#pragma unroll
-                    for (int i = E - 1; i >= 0; --i) {
-#pragma unroll
-                        for (int j = i + 1; j < E; ++j) r[i] -= A[i][j] * r[j];
-                        r[i] /= A[i][i];
-                    }
-                    for (int k = 0; k < K; ++k) {
-                        const double w = y[k] > 1e-30 ? y[k] : 1e-30;
-                        double acc = 0.0;
-#pragma unroll
-                        for (int a = 0; a < E; ++a) acc += m.Emat[a * K + k] * r[a];
-                        y[k] -= w * acc;
-                    }
+                    for (int b = 0; b <= a; ++b) A[a][b] += ew * tE[b * KM + k];
                 }
             }
-            if (!bad) {
-                for (int k = 0; k < K; ++k)
-                    if (!(y[k] >= -neg_tol) || !isfinite(y[k])) bad = true;
-            }
-            double Tn = T[c];
-            if (!bad) {
-                // Newton on h(T) = h0, as in the property update.  The mixture
-                // enthalpy is itself a NASA-7 polynomial in T with coefficients
-                // B_j = sum_k (Y_k / W_k) a_jk, built once: each iteration then
-                // costs one polynomial instead of one per species.
-                const double h0 = h0R[c];
-                double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                for (int k = 0; k < K; ++k) {
-                    const double w = y[k] * m.invW[k];
-                    const double *a = m.nasa + 7 * k;
 #pragma unroll
-                    for (int j = 0; j < 6; ++j) B[j] += w * a[j];
-                }
-                int st = 1;
-                for (int it = 0; it < 50; ++it) {
-                    const double t = Tn;
-                    // cp/R and h/R of the mixture (per unit mass)
-                    const double c_ = B[0] + t * (B[1] + t * (B[2] + t * (B[3] + t * B[4])));
-                    const double hT = t * (B[0] + t * (B[1] * 0.5 + t * (B[2] * (1.0 / 3.0) +
-                                      t * (B[3] * 0.25 + t * B[4] * 0.2)))) + B[5];
-                    const double dT = (hT - h0) / c_;
-                    Tn -= dT;
-                    if (!isfinite(Tn)) break;
-                    if (fabs(dT) <= 1e-12 * fabs(Tn)) {
-                        if (Tn >= 200.0 && Tn <= 4000.0) st = 0;
-                        break;
+            for (int a = 0; a < E; ++a)
+#pragma unroll
+                for (int b = a + 1; b < E; ++b) A[a][b] = A[b][a];
+            // Gaussian elimination with partial pivoting
+            bool ok = true;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                int piv = k;
+                double best = fabs(A[k][k]);
+#pragma unroll
+                for (int i = k + 1; i < E; ++i)
+                    if (fabs(A[i][k]) > best) {
+                        best = fabs(A[i][k]);
+                        piv = i;
                     }
+                ok = ok && best != 0.0;
+#pragma unroll
+                for (int i = k + 1; i < E; ++i) {
+                    const bool sw = i == piv;
+#pragma unroll
+                    for (int j = 0; j < E; ++j) {
+                        const double t = A[k][j];
+                        A[k][j] = sw ? A[i][j] : t;
+                        A[i][j] = sw ? t : A[i][j];
+                    }
+                    const double t = r[k];
+                    r[k] = sw ? r[i] : t;
+                    r[i] = sw ? t : r[i];
                 }
-                if (st) bad = true;
+#pragma unroll
+                for (int i = k + 1; i < E; ++i) {
+                    const double l = A[i][k] / A[k][k];
+#pragma unroll
+                    for (int j = k; j < E; ++j) A[i][j] -= l * A[k][j];
+                    r[i] -= l * r[k];
+                }
             }
-            if (bad) {
-                const int slot = atomicAdd(n_routed, 1);
-                queue[slot] = c;
-                atomicAdd(&stats[0], 1ull);
-            } else {
-                double *dst = Y + (size_t)c * K;
-                for (int k = 0; k < K; ++k) dst[k] = y[k];
-                T[c] = Tn;
-                status[c] = 0;
-                if (nsteps) nsteps[c] = 0;
+#pragma unroll
+            for (int i = E - 1; i >= 0; --i) {
+#pragma unroll
+                for (int j = i + 1; j < E; ++j) r[i] -= A[i][j] * r[j];
+                r[i] /= A[i][i];
+            }
+#pragma unroll
+            for (int a = 0; a < E; ++a) r[a] = ok ? r[a] : 0.0;
+            const double *__restrict__ tE2 = fresh_base(tab);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const double w = y[k] > 1e-30 ? y[k] : 1e-30;
+                double acc = 0.0;
+#pragma unroll
+                for (int a = 0; a < E; ++a) acc += tE2[a * KM + k] * r[a];
+                y[k] -= w * acc;   // zero for the padding (E = 0 there)
             }
         }
-        __syncthreads();
     }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (!(y[k] >= -neg_tol) || !isfinite(y[k])) bad = true;
+    // Newton on h(T) = h0, as in the property update.  The mixture enthalpy
+    // is itself a NASA-7 polynomial in T with coefficients
+    // B_j = sum_k (Y_k / W_k) a_jk, built once: each iteration then costs one
+    // polynomial instead of one per species.
+    double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const double w = y[k] * tab[tp_invW(E, KM) + k];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) B[j] += w * tab[tp_a(E, KM) + j * KM + k];
+    }
+    double Tn = T[c];
+    if (!bad) {
+        const double h0 = h0R[c];
+        int st = 1;
+        for (int it = 0; it < 50; ++it) {
+            const double t = Tn;
+            // cp/R and h/R of the mixture (per unit mass)
+            const double c_ = B[0] + t * (B[1] + t * (B[2] + t * (B[3] + t * B[4])));
+            const double hT = t * (B[0] + t * (B[1] * 0.5 + t * (B[2] * (1.0 / 3.0) +
+                              t * (B[3] * 0.25 + t * B[4] * 0.2)))) + B[5];
+            const double dT = (hT - h0) / c_;
+            Tn -= dT;
+            if (!isfinite(Tn)) break;
+            if (fabs(dT) <= 1e-12 * fabs(Tn)) {
+                if (Tn >= 200.0 && Tn <= 4000.0) st = 0;
+                break;
+            }
+        }
+        if (st) bad = true;
+    }
+    if (valid && bad) {
+        const int slot = atomicAdd(n_routed, 1);
+        queue[slot] = c;
+        atomicAdd(&stats[0], 1ull);
+    } else if (valid) {
+        T[c] = Tn;
+        status[c] = 0;
+        if (nsteps) nsteps[c] = 0;
+    }
+    // new rows of the cells that passed; the others keep Y_in
+    const bool keep = valid && !bad;
+    __syncthreads();
+    if (keep) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (k < K) s_row[lane * ld + k] = y[k];
+    }
+    s_keep[lane] = keep ? 1 : 0;
+    __syncthreads();
+    double *dst = Y + (size_t)base * K;
+    const int total = cnt * K;
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+        const int i = r * POST_CELLS + lane;
+        if (i < total) {
+            const int cc = (int)(((float)i + 0.5f) * invK);
+            if (s_keep[cc]) dst[i] = s_row[cc * ld + (i - cc * K)];
+        }
+    }
+}
+
+template <int KM> struct KmOf {
+    static constexpr int v = KM;
+};
+
+// Launch helpers over the species bound KM.
+static int km_of(int K) { return K <= 16 ? 16 : K <= 32 ? 32 : 64; }
+
+template <typename Fn> static hipError_t with_km(int K, Fn &&f) {
+    if (K <= 16) return f(KmOf<16>{});
+    if (K <= 32) return f(KmOf<32>{});
+    if (K <= 64) return f(KmOf<64>{});
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_ingest(int K, const double *tab, int n, const double *T, const double *p,
+                                const double *Y, uint16_t *X, int *route, double *h0, hipStream_t s) {
+    const int grid = (n + POST_CELLS - 1) / POST_CELLS;
+    return with_km(K, [&](auto km) {
+        constexpr int KM = decltype(km)::v;
+        hipLaunchKernelGGL(ingest_kernel<KM>, dim3(grid), dim3(POST_CELLS), 0, s, K, n, tab, T, p, Y, X,
+                           route, h0);
+        return hipGetLastError();
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -440,6 +645,8 @@ struct AnnState {
     std::vector<uint16_t *> Wt, Wb;   // BF16 copies per layer
     // normalisation and envelope (device: mu_x, sd_x, mu_y, sd_y, lo, hi)
     double *normdev = nullptr;
+    double *rowtab = nullptr;    // per-species tables of the ingest and post kernels
+    bool rowtab_stale = true;
     std::vector<double> mu_x, sd_x, mu_y, sd_y, lo, hi;
     double dt = 0.0, neg_tol = 1e-6;
     bool have_w = false, have_norm = false, have_env = false;
@@ -482,6 +689,7 @@ void ann_destroy(AnnState *a) {
     for (auto p : a->Wt) (void)hipFree(p);
     for (auto p : a->Wb) (void)hipFree(p);
     (void)hipFree(a->normdev);
+    (void)hipFree(a->rowtab);
     (void)hipFree(a->X);
     (void)hipFree(a->route);
     (void)hipFree(a->h0);
@@ -532,7 +740,23 @@ static hipError_t upload_norm(AnnState *a) {
     std::memcpy(h.data() + 2 * F + K, a->sd_y.data(), 8 * K);
     std::memcpy(h.data() + 2 * F + 2 * K, a->lo.data(), 8 * F);
     std::memcpy(h.data() + 3 * F + 2 * K, a->hi.data(), 8 * F);
+    a->rowtab_stale = true;
     return hipMemcpy(a->normdev, h.data(), 8 * h.size(), hipMemcpyHostToDevice);
+}
+
+// The ingest/post tables for the current normalisation (rebuilt after a change).
+static hipError_t row_tables(AnnState *a, const DevMech &m, hipStream_t s, const double **ti,
+                             const double **tp) {
+    const int KM = km_of(a->K);
+    if (a->rowtab_stale) {
+        hipLaunchKernelGGL(row_tables_kernel, dim3(1), dim3(256), 0, s, m, norm_dev(a), KM, a->rowtab,
+                           a->rowtab + ti_size(KM));
+        if (hipError_t e = hipGetLastError()) return e;
+        a->rowtab_stale = false;
+    }
+    *ti = a->rowtab;
+    *tp = a->rowtab + ti_size(KM);
+    return hipSuccess;
 }
 
 // forward of `rows` packed inputs X [rows x FPAD] into out [rows x K] (FP32)
@@ -594,32 +818,33 @@ static hipError_t ensure_infer(AnnState *a, int64_t n) {
     return hipSuccess;
 }
 
-static hipError_t launch_post(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
+static hipError_t launch_post(AnnState *a, const AnnStepArgs &x, const double *tab, hipStream_t s) {
     const DevMech &m = *x.dm;
-    const NormDev nd = norm_dev(a);
-    const int n = (int)x.n;
-    const size_t lds = sizeof(double) * POST_CELLS * (m.K + 1);
-    const int grid = std::min(8192, (n + POST_CELLS - 1) / POST_CELLS);
-#define POST_CASE(EE)                                                                         \
-    case EE:                                                                                  \
-        hipLaunchKernelGGL(post_kernel<EE>, dim3(grid), dim3(POST_CELLS), lds, s, m, nd, n, x.T, \
-                           x.Y, a->out, a->route, a->h0, a->neg_tol, x.project, x.status,      \
-                           x.nsteps, x.queue, x.n_routed, x.stats);                           \
+    const int n = (int)x.n, K = m.K;
+    const int grid = (n + POST_CELLS - 1) / POST_CELLS;
+    return with_km(K, [&](auto km) {
+        constexpr int KM = decltype(km)::v;
+#define POST_CASE(EE)                                                                             \
+    case EE:                                                                                      \
+        hipLaunchKernelGGL((post_kernel<EE, KM>), dim3(grid), dim3(POST_CELLS), 0, s, K, n, tab, x.T, \
+                           x.Y, a->out, a->route, a->h0, a->neg_tol, x.project, x.status,         \
+                           x.nsteps, x.queue, x.n_routed, x.stats);                              \
         break;
-    switch (m.E) {
-        POST_CASE(1)
-        POST_CASE(2)
-        POST_CASE(3)
-        POST_CASE(4)
-        POST_CASE(5)
-        POST_CASE(6)
-        POST_CASE(7)
-        POST_CASE(8)
-        default:
-            return hipErrorInvalidValue;
-    }
+        switch (m.E) {
+            POST_CASE(1)
+            POST_CASE(2)
+            POST_CASE(3)
+            POST_CASE(4)
+            POST_CASE(5)
+            POST_CASE(6)
+            POST_CASE(7)
+            POST_CASE(8)
+            default:
+                return hipErrorInvalidValue;
+        }
 #undef POST_CASE
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
@@ -634,13 +859,9 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     if ((e = launch_zero_u64(x.stats, 4, s)) != hipSuccess) return e;
     // ingest
     if (tm) tm->begin(CHEMK_PHASE_INGEST, s);
-    {
-        const size_t lds = sizeof(double) * ING_CELLS * (m.K + 1);
-        const int grid = std::min(8192, (n + ING_CELLS - 1) / ING_CELLS);
-        hipLaunchKernelGGL(ingest_kernel, dim3(grid), dim3(ING_CELLS), lds, s, m, norm_dev(a), n, x.T,
-                           x.p, x.Y, a->X, FPAD, a->route, a->h0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    const double *ti, *tp;
+    if ((e = row_tables(a, m, s, &ti, &tp)) != hipSuccess) return e;
+    if ((e = launch_ingest(m.K, ti, n, x.T, x.p, x.Y, a->X, a->route, a->h0, s)) != hipSuccess) return e;
     if (tm) tm->end(CHEMK_PHASE_INGEST, s);
     // MLP in chunks
     if (tm) tm->begin(CHEMK_PHASE_MLP, s);
@@ -653,7 +874,7 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     if (tm) tm->end(CHEMK_PHASE_MLP, s);
     // post
     if (tm) tm->begin(CHEMK_PHASE_POST, s);
-    if ((e = launch_post(a, x, s)) != hipSuccess) return e;
+    if ((e = launch_post(a, x, tp, s)) != hipSuccess) return e;
     if (tm) tm->end(CHEMK_PHASE_POST, s);
     // DI on the routed cells
     if (tm) tm->begin(CHEMK_PHASE_FALLBACK, s);
@@ -747,6 +968,7 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
         a->Wb.push_back(wb);
     }
     ANN_TRY(hipMalloc(&a->normdev, 8 * (4 * a->F + 2 * K)));
+    ANN_TRY(hipMalloc(&a->rowtab, 8 * ROW_TAB_DOUBLES));
     a->mu_x.assign(a->F, 0.0);
     a->sd_x.assign(a->F, 1.0);
     a->mu_y.assign(K, 0.0);
@@ -956,6 +1178,7 @@ extern "C" int chemk_ann_pack(chemk_ctx *c, int64_t n, const double *T, const do
     if (n < 0 || n > (1ll << 31) - 1) ANN_FAIL(CHEMK_E_ARG, "bad n");
     if (n == 0) return CHEMK_OK;
     if (!T || !p || !Y || !X || (Z && !Yn)) ANN_FAIL(CHEMK_E_ARG, "null array");
+    if (reinterpret_cast<uintptr_t>(X) % 16) ANN_FAIL(CHEMK_E_ARG, "X must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     // reuse the ingest kernel (its route/h0 outputs go to scratch)
     int *route = nullptr;
@@ -963,10 +1186,9 @@ extern "C" int chemk_ann_pack(chemk_ctx *c, int64_t n, const double *T, const do
     ANN_TRY(hipMalloc(&route, 4 * n));
     ANN_TRY(hipMalloc(&h0, 8 * n));
     const DevMech m = ctx_devmech(c);
-    const size_t lds = sizeof(double) * ING_CELLS * (m.K + 1);
-    const int grid = (int)std::min<int64_t>(8192, (n + ING_CELLS - 1) / ING_CELLS);
-    hipLaunchKernelGGL(ingest_kernel, dim3(grid), dim3(ING_CELLS), lds, s, m, norm_dev(a), (int)n, T, p,
-                       Y, X, FPAD, route, h0);
+    const double *ti, *tp;
+    ANN_TRY(row_tables(a, m, s, &ti, &tp));
+    ANN_TRY(launch_ingest(m.K, ti, (int)n, T, p, Y, X, route, h0, s));
     if (Z) {
         const int g2 = (int)std::min<int64_t>(8192, (n * a->K + 255) / 256);
         hipLaunchKernelGGL(pack_targets_kernel, dim3(g2), dim3(256), 0, s, a->K, (int)n, Y, Yn,
