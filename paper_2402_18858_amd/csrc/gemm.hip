@@ -28,12 +28,13 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(4))) float floatx4_t;
 
 constexpr int NTHREADS = 256;
-// K slabs in flight in registers ahead of the one being multiplied (2 or 3)
+// K slabs in flight in registers ahead of the one being multiplied, for the
+// kernels with a compile-time slab count (2 to 4; the others use 2)
 #ifndef CHEMK_GEMM_PREFETCH
 #define CHEMK_GEMM_PREFETCH 2
 #endif
 constexpr int kGemmPrefetch = CHEMK_GEMM_PREFETCH;
-static_assert(kGemmPrefetch == 2 || kGemmPrefetch == 3, "ring depth 2 or 3");
+
 // bf16 elements per LDS row for a K step of BK (16-byte pad)
 template <int BK> constexpr int lds_ld() { return BK + 8; }
 
@@ -63,8 +64,24 @@ __device__ __forceinline__ float erf_as(float x) {
     return copysignf(fmaf(-t * poly, e, 1.0f), x);
 }
 
+// Forward GELU(x) = x Phi(x).  The upper tail 1 - Phi(u), u = |x|, is
+// (1/2) p(u / sqrt 2)^-16 with p the sixth-degree polynomial of Abramowitz &
+// Stegun 7.1.28 (erf error at most 3e-7); the 1/2 (as 2^(1/16)) and the
+// powers of 1/sqrt 2 are folded into the coefficients, so the tail costs six
+// FMAs, one reciprocal and four squarings, with no exponential.  Absolute
+// error below 1e-6 over the real line; a non-finite input gives NaN.
 __device__ __forceinline__ float gelu_f(float x) {
-    return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f));
+    const float u = fabsf(x);
+    float q = fmaf(u, 5.62129980608006e-06f, 5.105520904180594e-05f);
+    q = fmaf(u, q, 3.9686136005911976e-05f);
+    q = fmaf(u, q, 0.003422739217057824f);
+    q = fmaf(u, q, 0.02207699790596962f);
+    q = fmaf(u, q, 0.052075162529945374f);
+    q = fmaf(u, q, 1.0442737340927124f);
+    const float r = __builtin_amdgcn_rcpf(q);
+    const float r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+    const float t = x * (r8 * r8);   // x (1 - Phi(u))
+    return x >= 0.0f ? x - t : t;
 }
 
 __device__ __forceinline__ float gelu_grad_f(float x) {
@@ -167,7 +184,7 @@ __device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[ROWS 
 // KTC > 0: the number of K slabs, fixed at compile time, so the K loop is
 // unrolled completely (the compiler's waits can then keep later slabs in
 // flight, which it does not do across a loop back-edge); 0: runtime loop.
-template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC, int KTC>
+template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC, int KTC, int PD>
 __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     constexpr int TM = BM / 32, TN = BN / 32, LDS_LD = lds_ld<BK>();
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_LD];
@@ -200,7 +217,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     // work to arrive.  The ring index is a compile-time constant (the K loop
     // is unrolled by PD).
     constexpr int QA = BM * BK / 8 / NTHREADS, QB = BN * BK / 8 / NTHREADS;
-    constexpr int PD = kGemmPrefetch;
+    static_assert(PD >= 2 && PD <= 4, "ring depth 2 to 4");
     uint4 ra[PD][QA], rb[PD][QB];
     const int KT = KTC > 0 ? KTC : (g.K + BK - 1) / BK;
     const __amdgpu_buffer_rsrc_t rsA =
@@ -237,40 +254,57 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
                                                                         0, 0, 0);
         }
     };
-    if (KT == 1) {
+    // one step: compute slab kt, store slab kt+1 (ring slot N) into the other
+    // LDS buffer, then reuse slot N for the load of slab kt+PD+1
+#define GEMM_STEP(KTV, N)                                                                 \
+    compute((KTV) & 1);                                                                   \
+    store_tile<BM, BK, AK>(sA[((KTV) + 1) & 1], ra[N]);                                   \
+    store_tile<BN, BK, BKc>(sB[((KTV) + 1) & 1], rb[N]);                                  \
+    lds_barrier();                                                                        \
+    load_slab(ra[N], rb[N], (KTV) + PD + 1);
+    if constexpr (KTC > 0) {
+        // unrolled slab by slab: the ring slot is a compile-time constant and
+        // nothing is loaded or computed past the last slab
+#pragma unroll
+        for (int q = 1; q <= PD; ++q)
+            if (q < KTC) load_slab(ra[q % PD], rb[q % PD], q);
+#pragma unroll
+        for (int kt = 0; kt < KTC; ++kt) {
+            const int N = (kt + 1) % PD;
+            compute(kt & 1);
+            if (kt + 1 < KTC) {
+                store_tile<BM, BK, AK>(sA[(kt + 1) & 1], ra[N]);
+                store_tile<BN, BK, BKc>(sB[(kt + 1) & 1], rb[N]);
+                lds_barrier();
+                if (kt + PD + 1 < KTC) load_slab(ra[N], rb[N], kt + PD + 1);
+            }
+        }
+    } else if (KT == 1) {
         compute(0);
     } else {
         // KT rounded up to whole ring turns; the extra slabs load as zeros
         const int KTR = (KT + PD - 1) / PD * PD;
 #pragma unroll
         for (int q = 1; q <= PD; ++q) load_slab(ra[q % PD], rb[q % PD], q);
-        // one step; N = (kt + 1) % PD holds slab kt+1 and then takes slab kt+PD+1
-#define GEMM_STEP(KTV, N)                                                                 \
-        compute((KTV) & 1);                                                               \
-        store_tile<BM, BK, AK>(sA[((KTV) + 1) & 1], ra[N]);                               \
-        store_tile<BN, BK, BKc>(sB[((KTV) + 1) & 1], rb[N]);                              \
-        lds_barrier();                                                                    \
-        load_slab(ra[N], rb[N], (KTV) + PD + 1);
         auto turn = [&](int kt) {
             if constexpr (PD == 2) {
                 GEMM_STEP(kt, 1)
                 GEMM_STEP(kt + 1, 0)
-            } else {
+            } else if constexpr (PD == 3) {
                 GEMM_STEP(kt, 1)
                 GEMM_STEP(kt + 1, 2)
                 GEMM_STEP(kt + 2, 0)
+            } else {
+                GEMM_STEP(kt, 1)
+                GEMM_STEP(kt + 1, 2)
+                GEMM_STEP(kt + 2, 3)
+                GEMM_STEP(kt + 3, 0)
             }
         };
-        if constexpr (KTC > 0) {
-            constexpr int KTRC = (KTC + PD - 1) / PD * PD;
-#pragma unroll
-            for (int kt = 0; kt < KTRC; kt += PD) turn(kt);
-        } else {
 #pragma unroll 1
-            for (int kt = 0; kt < KTR; kt += PD) turn(kt);
-        }
-#undef GEMM_STEP
+        for (int kt = 0; kt < KTR; kt += PD) turn(kt);
     }
+#undef GEMM_STEP
 
     // epilogue.  The MFMA computes the 16 x 16 tile transposed (B operand
     // first), so a lane holds row (lane & 15) and the four consecutive
@@ -281,6 +315,32 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     const bool vcb = g.Cb && g.ldcb % 4 == 0 && ((uintptr_t)g.Cb & 7) == 0;
     const bool vz = g.Zin && g.ldz % 4 == 0 && ((uintptr_t)g.Zin & 15) == 0;
     const bool vbias = g.bias && ((uintptr_t)g.bias & 15) == 0;
+    // Forward layers on a tile wholly inside the output with aligned operands
+    // (the usual case; the condition is uniform): no bounds tests, one vector
+    // bias load, store and (BF16) packed store per MFMA tile and lane.
+    if constexpr (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS) {
+        if (m0 + BM <= g.M && n0 + BN <= g.N && vbias && (EPI == EPI_BIAS ? vcf : vcb && (!g.Cf || vcf))) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int col = n0 + wn + j * 16 + (lane >> 4) * 4;
+                const float4 bj = *reinterpret_cast<const float4 *>(g.bias + col);
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int row = m0 + wm + i * 16 + (lane & 15);
+                    const floatx4_t v = acc[i][j];
+                    const float z0 = v[0] + bj.x, z1 = v[1] + bj.y, z2 = v[2] + bj.z, z3 = v[3] + bj.w;
+                    if (EPI == EPI_BIAS || g.Cf)
+                        *reinterpret_cast<float4 *>(g.Cf + (size_t)row * g.ldc + col) =
+                            make_float4(z0, z1, z2, z3);
+                    if constexpr (EPI == EPI_BIAS_GELU)
+                        *reinterpret_cast<uint2 *>(g.Cb + (size_t)row * g.ldcb + col) =
+                            make_uint2(pack_bf16x2(gelu_f(z0), gelu_f(z1)),
+                                       pack_bf16x2(gelu_f(z2), gelu_f(z3)));
+                }
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int row = m0 + wm + i * 16 + (lane & 15);
@@ -352,9 +412,10 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
     const int kt = (g.K + TK - 1) / TK;
     // forward layers of the MLP get a K loop unrolled for their slab count
     constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS);
-#define GEMM_LAUNCH(VECV, KTV)                                                          \
-    hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV, KTV>), dim3(grid), \
-                       dim3(NTHREADS), 0, s, g)
+#define GEMM_LAUNCH(VECV, KTV)                                                               \
+    hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV, KTV,                  \
+                                         ((KTV) > 0 ? kGemmPrefetch : 2)>),                    \
+                       dim3(grid), dim3(NTHREADS), 0, s, g)
     if (!vec) {
         GEMM_LAUNCH(false, 0);
     } else if constexpr (fwd) {
