@@ -234,24 +234,31 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     __syncthreads();
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    auto compute = [&](int cur) {
+    // MFMA fragments of one 32-wide K step: a lane holds 8 consecutive k of
+    // row (lane & 15) of each 16-row tile
+    auto read_frags = [&](int cur, int ks, bf16x8_t (&af)[TM], bf16x8_t (&bfr)[TN]) {
         const uint16_t *A_ = sA[cur];
         const uint16_t *B_ = sB[cur];
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 32) {
-            bf16x8_t af[TM], bfr[TN];
+        for (int i = 0; i < TM; ++i)
+            af[i] = *reinterpret_cast<const bf16x8_t *>(A_ + (wm + i * 16 + fr) * LDS_LD + ks + fk);
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
-                af[i] = *reinterpret_cast<const bf16x8_t *>(A_ + (wm + i * 16 + fr) * LDS_LD + ks + fk);
+        for (int j = 0; j < TN; ++j)
+            bfr[j] = *reinterpret_cast<const bf16x8_t *>(B_ + (wn + j * 16 + fr) * LDS_LD + ks + fk);
+    };
+    auto mfma_frags = [&](const bf16x8_t (&af)[TM], const bf16x8_t (&bfr)[TN]) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                bfr[j] = *reinterpret_cast<const bf16x8_t *>(B_ + (wn + j * 16 + fr) * LDS_LD + ks + fk);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+    };
+    auto compute = [&](int cur) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j],
-                                                                        0, 0, 0);
+        for (int ks = 0; ks < BK; ks += 32) {
+            bf16x8_t af[TM], bfr[TN];
+            read_frags(cur, ks, af, bfr);
+            mfma_frags(af, bfr);
         }
     };
     // one step: compute slab kt, store slab kt+1 (ring slot N) into the other
@@ -263,21 +270,43 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     lds_barrier();                                                                        \
     load_slab(ra[N], rb[N], (KTV) + PD + 1);
     if constexpr (KTC > 0) {
-        // unrolled slab by slab: the ring slot is a compile-time constant and
-        // nothing is loaded or computed past the last slab
+        // Unrolled slab by slab (the ring slot is a compile-time constant and
+        // nothing is loaded or computed past the last slab), in two halves of
+        // 32 k per slab with the fragments double-buffered in registers, so
+        // that LDS traffic overlaps the MFMAs:
+        //   read half 1 of slab kt; store slab kt+1 into the other buffer;
+        //   MFMA half 0 of slab kt; barrier (slab kt+1 visible, every read of
+        //   slab kt done); read half 0 of slab kt+1 and issue the global load
+        //   of slab kt+PD+1; MFMA half 1 of slab kt.
+        static_assert(BK == 64, "two halves of 32 per slab");
 #pragma unroll
         for (int q = 1; q <= PD; ++q)
             if (q < KTC) load_slab(ra[q % PD], rb[q % PD], q);
+        // Each half step issues its memory operations first and its MFMAs
+        // after a scheduling fence (the MFMAs use fragments read one half
+        // step earlier, so nothing waits on the new reads):
+        //   [read half 1 of kt, store slab kt+1] | MFMA half 0 of kt | barrier
+        //   [read half 0 of kt+1, load slab kt+PD+1] | MFMA half 1 of kt
+        bf16x8_t a0[TM], b0[TN], a1[TM], b1[TN];
+        read_frags(0, 0, a0, b0);
 #pragma unroll
         for (int kt = 0; kt < KTC; ++kt) {
             const int N = (kt + 1) % PD;
-            compute(kt & 1);
+            read_frags(kt & 1, 32, a1, b1);
             if (kt + 1 < KTC) {
                 store_tile<BM, BK, AK>(sA[(kt + 1) & 1], ra[N]);
                 store_tile<BN, BK, BKc>(sB[(kt + 1) & 1], rb[N]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_frags(a0, b0);
+            if (kt + 1 < KTC) {
                 lds_barrier();
+                read_frags((kt + 1) & 1, 0, a0, b0);
                 if (kt + PD + 1 < KTC) load_slab(ra[N], rb[N], kt + PD + 1);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_frags(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else if (KT == 1) {
         compute(0);
