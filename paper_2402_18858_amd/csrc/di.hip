@@ -429,7 +429,13 @@ __global__ void __launch_bounds__(64 * kDiWavesPerBlock) di_kernel(DevMech m, co
     const int lane = lane_id();
     const int K = m.K;
     const int n_items = *n_items_p;
+    if (n_items <= 0) return;
     for (;;) {
+        // Same-address atomics serialise in L2: a wave that reads the queue
+        // as drained leaves without a claim (the claim below still decides;
+        // this read only spares the final failing claims of every wave).
+        if (uniform(__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= n_items)
+            break;
         // The claim is issued by every lane (lane 0 adds 1, the others 0) so
         // that no branch on the lane index precedes the broadcast of the
         // claimed index.  With a lane-0 branch here the compiler may thread
