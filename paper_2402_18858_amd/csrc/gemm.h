@@ -27,7 +27,9 @@ struct GemmArgs {
     int ldz;
 };
 
-// Requirements: K, lda, ldb multiples of 8; operands 16-byte aligned.
+// Any K >= 1 and leading dimensions; operands in whole, 16-byte aligned
+// chunks of 8 (K, lda, ldb and the chunked extents multiples of 8) take the
+// buffer-load path, others an element-by-element one.  Operands below 2 GiB.
 hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s);
 
 }  // namespace chemk

@@ -1,4 +1,4 @@
-// gemm.hip -- BF16 GEMM on gfx950 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+// gemm.hip -- BF16 GEMM on gfx950 MFMA (v_mfma_f32_32x32x16_bf16) with FP32
 // accumulation and fused epilogues, for the MLP that stands in for DI
 // (forward pass, and the two backward products of training).
 //
@@ -9,7 +9,7 @@
 // the tile loader transposes through LDS.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves, each
-// 64 x 64 in MFMA tiles of 16 x 16), K step 64 (two MFMA k-steps),
+// 64 x 64 in MFMA tiles of 32 x 32), K step 64 (four MFMA k-steps),
 // double-buffered LDS with a padded row stride, K slabs in flight in a ring
 // of registers ahead of the one being multiplied (buffer loads, which read
 // zeros past an operand's edge, so no load sits behind a branch).  (The kernel is templated on
@@ -26,6 +26,16 @@ namespace chemk {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(4))) float floatx4_t;
+typedef __attribute__((ext_vector_type(16))) float floatx16_t;
+
+// One MFMA: a 32 x 32 x 16 product, B operand first, so that the result is
+// the transposed tile (see the epilogue).  (The 16 x 16 x 32 form does the
+// same work in half the output; measured on gfx950 it needs some 32
+// independent accumulations in flight per SIMD to reach the rate this one
+// reaches with 8.)
+__device__ __forceinline__ floatx16_t mfma32(const bf16x8_t &b, const bf16x8_t &a, const floatx16_t &c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, a, c, 0, 0, 0);
+}
 
 constexpr int NTHREADS = 256;
 // K slabs in flight in registers ahead of the one being multiplied, for the
@@ -34,6 +44,7 @@ constexpr int NTHREADS = 256;
 #define CHEMK_GEMM_PREFETCH 2
 #endif
 constexpr int kGemmPrefetch = CHEMK_GEMM_PREFETCH;
+
 
 // bf16 elements per LDS row for a K step of BK (16-byte pad)
 template <int BK> constexpr int lds_ld() { return BK + 8; }
@@ -117,7 +128,7 @@ __device__ __forceinline__ uint4 load_chunk_slow(const uint16_t *G, size_t at, i
 }
 
 // load the (ROWS x BK) slab of an operand into registers (then LDS
-// [ROWS][LDS_LD]).  Where the operands are stored in whole 16-byte chunks
+// [ROWS][LDS_LD]), shared by the NTHREADS threads t of a loading group.  Where the operands are stored in whole 16-byte chunks
 // (VEC, chosen by the host), every chunk is one buffer load, and a chunk outside the
 // operand gets an offset past the buffer's end and so reads as zeros: no
 // branch surrounds a load, so the compiler can wait for one slab while later
@@ -126,9 +137,8 @@ __device__ __forceinline__ uint4 load_chunk_slow(const uint16_t *G, size_t at, i
 template <int ROWS, int BK, bool KCONT, bool VEC>
 __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const uint16_t *G,
                                           int ld, int row0, int rows_total, int k0, int K,
-                                          uint4 (&reg)[ROWS * BK / 8 / NTHREADS]) {
+                                          uint4 (&reg)[ROWS * BK / 8 / NTHREADS], int t) {
     constexpr int KC = BK / 8;            // chunks of 8 bf16 per row
-    const int t = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < ROWS * BK / 8 / NTHREADS; ++q) {
         const int c = t + q * NTHREADS;
@@ -160,9 +170,9 @@ __device__ __forceinline__ void load_tile(__amdgpu_buffer_rsrc_t rs, const uint1
 }
 
 template <int ROWS, int BK, bool KCONT>
-__device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[ROWS * BK / 8 / NTHREADS]) {
+__device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[ROWS * BK / 8 / NTHREADS],
+                                           int t) {
     constexpr int KC = BK / 8, LD = lds_ld<BK>();
-    const int t = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < ROWS * BK / 8 / NTHREADS; ++q) {
         const int c = t + q * NTHREADS;
@@ -179,14 +189,160 @@ __device__ __forceinline__ void store_tile(uint16_t *S, const uint4 (&reg)[ROWS 
     }
 }
 
+// Epilogue of a BM x BN tile whose wave (wm, wn) holds the TM x TN MFMA
+// tiles acc of 32 x 32.  The MFMA computes each tile transposed (B operand
+// first), so a lane holds row (lane & 31) and, for q = 0..3, the four
+// consecutive columns 8 q + 4 (lane >> 5) + r: one 8-byte (BF16) or 16-byte
+// (FP32) access per quad and lane where the leading dimension and the base
+// pointer allow it (they are uniform), element by element otherwise.
+template <int BM, int BN, int EPI, int TM = BM / 64, int TN = BN / 64>
+__device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16_t (&acc)[TM][TN], int m0,
+                                         int n0, int wm, int wn, int lane, uint16_t *stage) {
+    const bool vcf = g.Cf && g.ldc % 4 == 0 && ((uintptr_t)g.Cf & 15) == 0;
+    const bool vcb = g.Cb && g.ldcb % 4 == 0 && ((uintptr_t)g.Cb & 7) == 0;
+    const bool vz = g.Zin && g.ldz % 4 == 0 && ((uintptr_t)g.Zin & 15) == 0;
+    const bool vbias = g.bias && ((uintptr_t)g.bias & 15) == 0;
+    const int lr = lane & 31, lc = (lane >> 5) * 4;
+    // Forward BF16-only layers on a whole tile: the wave's (BM/2) x (BN/2)
+    // output goes through its LDS staging area (rows of BN/2 + 8 elements) so
+    // that each global store instruction writes whole 128-byte row segments
+    // (eight of them) instead of 16 bytes in each of 32 rows.  The caller has
+    // made the staging area free with a workgroup barrier; the condition is
+    // uniform over the workgroup.
+    if constexpr (EPI == EPI_BIAS_GELU) {
+        constexpr int WR = BM / 2, WC = BN / 2, SLD = WC + 8, CH = WC / 8;
+        if (m0 + BM <= g.M && n0 + BN <= g.N && vbias && !g.Cf && g.Cb && g.ldcb % 8 == 0 &&
+            ((uintptr_t)g.Cb & 15) == 0) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = j * 32 + q * 8 + lc;
+                    const float4 bj = *reinterpret_cast<const float4 *>(g.bias + n0 + wn + c);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        const floatx16_t &v = acc[i][j];
+                        *reinterpret_cast<uint2 *>(stage + (i * 32 + lr) * SLD + c) =
+                            make_uint2(pack_bf16x2(gelu_f(v[4 * q] + bj.x), gelu_f(v[4 * q + 1] + bj.y)),
+                                       pack_bf16x2(gelu_f(v[4 * q + 2] + bj.z), gelu_f(v[4 * q + 3] + bj.w)));
+                    }
+                }
+            // the wave reads back only what it wrote: a wave-scope LDS fence
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+            for (int r = 0; r < WR * CH / 64; ++r) {
+                const int ck = r * 64 + lane;           // chunk of 8 elements: row ck / CH
+                const int row = ck / CH, c8 = (ck % CH) * 8;
+                const uint4 w = *reinterpret_cast<const uint4 *>(stage + row * SLD + c8);
+                *reinterpret_cast<uint4 *>(g.Cb + (size_t)(m0 + wm + row) * g.ldcb + n0 + wn + c8) = w;
+            }
+            return;
+        }
+    }
+    // Forward layers on a tile wholly inside the output with aligned operands
+    // (the usual case; the condition is uniform): no bounds tests, one vector
+    // bias load, store and (BF16) packed store per quad and lane.
+    if constexpr (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS) {
+        if (m0 + BM <= g.M && n0 + BN <= g.N && vbias && (EPI == EPI_BIAS ? vcf : vcb && (!g.Cf || vcf))) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int col = n0 + wn + j * 32 + q * 8 + lc;
+                    const float4 bj = *reinterpret_cast<const float4 *>(g.bias + col);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        const int row = m0 + wm + i * 32 + lr;
+                        const floatx16_t &v = acc[i][j];
+                        const float z0 = v[4 * q] + bj.x, z1 = v[4 * q + 1] + bj.y;
+                        const float z2 = v[4 * q + 2] + bj.z, z3 = v[4 * q + 3] + bj.w;
+                        if (EPI == EPI_BIAS || g.Cf)
+                            *reinterpret_cast<float4 *>(g.Cf + (size_t)row * g.ldc + col) =
+                                make_float4(z0, z1, z2, z3);
+                        if constexpr (EPI == EPI_BIAS_GELU)
+                            *reinterpret_cast<uint2 *>(g.Cb + (size_t)row * g.ldcb + col) =
+                                make_uint2(pack_bf16x2(gelu_f(z0), gelu_f(z1)),
+                                           pack_bf16x2(gelu_f(z2), gelu_f(z3)));
+                    }
+                }
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int row = m0 + wm + i * 32 + lr;
+        if (row >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int col = n0 + wn + j * 32 + q * 8 + lc;
+                if (col >= g.N) continue;
+                const floatx16_t &acv = acc[i][j];
+                const float v[4] = {acv[4 * q], acv[4 * q + 1], acv[4 * q + 2], acv[4 * q + 3]};
+                const bool full = col + 4 <= g.N;
+                float z[4];
+                if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS) {
+                    if (full && vbias) {
+                        const float4 b = *reinterpret_cast<const float4 *>(g.bias + col);
+                        z[0] = v[0] + b.x;
+                        z[1] = v[1] + b.y;
+                        z[2] = v[2] + b.z;
+                        z[3] = v[3] + b.w;
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) z[r] = v[r] + (col + r < g.N ? g.bias[col + r] : 0.f);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) z[r] = v[r];
+                }
+                if (EPI == EPI_BIAS || EPI == EPI_STORE_F32 || (EPI == EPI_BIAS_GELU && g.Cf)) {
+                    float *dst = g.Cf + (size_t)row * g.ldc + col;
+                    if (full && vcf) {
+                        *reinterpret_cast<float4 *>(dst) = make_float4(z[0], z[1], z[2], z[3]);
+                    } else {
+                        for (int r = 0; r < 4 && col + r < g.N; ++r) dst[r] = z[r];
+                    }
+                }
+                if (EPI == EPI_BIAS_GELU || EPI == EPI_GELU_GRAD) {
+                    float zin[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (EPI == EPI_GELU_GRAD) {
+                        const float *zp = g.Zin + (size_t)row * g.ldz + col;
+                        if (full && vz) {
+                            const float4 zq = *reinterpret_cast<const float4 *>(zp);
+                            zin[0] = zq.x; zin[1] = zq.y; zin[2] = zq.z; zin[3] = zq.w;
+                        } else {
+                            for (int r = 0; r < 4 && col + r < g.N; ++r) zin[r] = zp[r];
+                        }
+                    }
+                    float a[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        a[r] = EPI == EPI_BIAS_GELU ? gelu_f(z[r]) : z[r] * gelu_grad_f(zin[r]);
+                    const uint2 pk = make_uint2(pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]));
+                    uint16_t *dst = g.Cb + (size_t)row * g.ldcb + col;
+                    if (full && vcb) {
+                        *reinterpret_cast<uint2 *>(dst) = pk;
+                    } else {
+                        const uint16_t o[4] = {(uint16_t)pk.x, (uint16_t)(pk.x >> 16), (uint16_t)pk.y,
+                                               (uint16_t)(pk.y >> 16)};
+                        for (int r = 0; r < 4 && col + r < g.N; ++r) dst[r] = o[r];
+                    }
+                }
+            }
+    }
+}
+
 // BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each with a
-// (BM/2) x (BN/2) tile of TM x TN MFMA tiles of 16 x 16.
+// (BM/2) x (BN/2) tile of TM x TN MFMA tiles of 32 x 32.
 // KTC > 0: the number of K slabs, fixed at compile time, so the K loop is
 // unrolled completely (the compiler's waits can then keep later slabs in
 // flight, which it does not do across a loop back-edge); 0: runtime loop.
 template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC, int KTC, int PD>
 __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
-    constexpr int TM = BM / 32, TN = BN / 32, LDS_LD = lds_ld<BK>();
+    constexpr int TM = BM / 64, TN = BN / 64, LDS_LD = lds_ld<BK>();
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_LD];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDS_LD];
 
@@ -201,14 +357,17 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     const int tm = tile / nt, tn = tile - tm * nt;
     const int m0 = tm * BM, n0 = tn * BN;
 
+    const int tid = threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
 
-    floatx4_t acc[TM][TN];
+    floatx16_t acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = (floatx4_t){0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     // Global -> LDS pipeline: slab kt is in LDS buffer kt & 1 while the next
     // PD slabs are in flight in a ring of register sets.  Each step computes
@@ -225,39 +384,43 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     const __amdgpu_buffer_rsrc_t rsB =
         operand_rsrc(g.B, 2ll * g.ldb * (BKc ? g.N : g.K));
     auto load_slab = [&](uint4 (&a)[QA], uint4 (&b)[QB], int kt) {
-        load_tile<BM, BK, AK, VEC>(rsA, g.A, g.lda, m0, g.M, kt * BK, g.K, a);
-        load_tile<BN, BK, BKc, VEC>(rsB, g.B, g.ldb, n0, g.N, kt * BK, g.K, b);
+        load_tile<BM, BK, AK, VEC>(rsA, g.A, g.lda, m0, g.M, kt * BK, g.K, a, tid);
+        load_tile<BN, BK, BKc, VEC>(rsB, g.B, g.ldb, n0, g.N, kt * BK, g.K, b, tid);
     };
     load_slab(ra[0], rb[0], 0);
-    store_tile<BM, BK, AK>(sA[0], ra[0]);
-    store_tile<BN, BK, BKc>(sB[0], rb[0]);
+    store_tile<BM, BK, AK>(sA[0], ra[0], tid);
+    store_tile<BN, BK, BKc>(sB[0], rb[0], tid);
     __syncthreads();
 
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    // MFMA fragments of one 32-wide K step: a lane holds 8 consecutive k of
-    // row (lane & 15) of each 16-row tile
-    auto read_frags = [&](int cur, int ks, bf16x8_t (&af)[TM], bf16x8_t (&bfr)[TN]) {
+    const int fr = lane & 31, fk = (lane >> 5) * 8;
+    // MFMA fragments of one half slab (32 k = two MFMA k-steps of 16): a lane
+    // holds 8 consecutive k of row (lane & 31) of each 32-row tile
+    auto read_frags = [&](int cur, int kh, bf16x8_t (&af)[2][TM], bf16x8_t (&bfr)[2][TN]) {
         const uint16_t *A_ = sA[cur];
         const uint16_t *B_ = sB[cur];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-            af[i] = *reinterpret_cast<const bf16x8_t *>(A_ + (wm + i * 16 + fr) * LDS_LD + ks + fk);
+        for (int s = 0; s < 2; ++s) {
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8_t *>(B_ + (wn + j * 16 + fr) * LDS_LD + ks + fk);
-    };
-    auto mfma_frags = [&](const bf16x8_t (&af)[TM], const bf16x8_t (&bfr)[TN]) {
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
+                af[s][i] = *reinterpret_cast<const bf16x8_t *>(A_ + (wm + i * 32 + fr) * LDS_LD + kh + 16 * s + fk);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+                bfr[s][j] = *reinterpret_cast<const bf16x8_t *>(B_ + (wn + j * 32 + fr) * LDS_LD + kh + 16 * s + fk);
+        }
+    };
+    auto mfma_frags = [&](const bf16x8_t (&af)[2][TM], const bf16x8_t (&bfr)[2][TN]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = mfma32(bfr[s][j], af[s][i], acc[i][j]);
     };
     auto compute = [&](int cur) {
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 32) {
-            bf16x8_t af[TM], bfr[TN];
-            read_frags(cur, ks, af, bfr);
+        for (int kh = 0; kh < BK; kh += 32) {
+            bf16x8_t af[2][TM], bfr[2][TN];
+            read_frags(cur, kh, af, bfr);
             mfma_frags(af, bfr);
         }
     };
@@ -265,8 +428,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     // LDS buffer, then reuse slot N for the load of slab kt+PD+1
 #define GEMM_STEP(KTV, N)                                                                 \
     compute((KTV) & 1);                                                                   \
-    store_tile<BM, BK, AK>(sA[((KTV) + 1) & 1], ra[N]);                                   \
-    store_tile<BN, BK, BKc>(sB[((KTV) + 1) & 1], rb[N]);                                  \
+    store_tile<BM, BK, AK>(sA[((KTV) + 1) & 1], ra[N], tid);                                   \
+    store_tile<BN, BK, BKc>(sB[((KTV) + 1) & 1], rb[N], tid);                                  \
     lds_barrier();                                                                        \
     load_slab(ra[N], rb[N], (KTV) + PD + 1);
     if constexpr (KTC > 0) {
@@ -287,15 +450,15 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
         // step earlier, so nothing waits on the new reads):
         //   [read half 1 of kt, store slab kt+1] | MFMA half 0 of kt | barrier
         //   [read half 0 of kt+1, load slab kt+PD+1] | MFMA half 1 of kt
-        bf16x8_t a0[TM], b0[TN], a1[TM], b1[TN];
+        bf16x8_t a0[2][TM], b0[2][TN], a1[2][TM], b1[2][TN];
         read_frags(0, 0, a0, b0);
 #pragma unroll
         for (int kt = 0; kt < KTC; ++kt) {
             const int N = (kt + 1) % PD;
             read_frags(kt & 1, 32, a1, b1);
             if (kt + 1 < KTC) {
-                store_tile<BM, BK, AK>(sA[(kt + 1) & 1], ra[N]);
-                store_tile<BN, BK, BKc>(sB[(kt + 1) & 1], rb[N]);
+                store_tile<BM, BK, AK>(sA[(kt + 1) & 1], ra[N], tid);
+                store_tile<BN, BK, BKc>(sB[(kt + 1) & 1], rb[N], tid);
             }
             __builtin_amdgcn_sched_barrier(0);
             mfma_frags(a0, b0);
@@ -335,102 +498,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     }
 #undef GEMM_STEP
 
-    // epilogue.  The MFMA computes the 16 x 16 tile transposed (B operand
-    // first), so a lane holds row (lane & 15) and the four consecutive
-    // columns 4 (lane >> 4) + r of each tile: one 8-byte (BF16) or 16-byte
-    // (FP32) access per tile and lane where the leading dimension and the
-    // base pointer allow it (they are uniform), element by element otherwise.
-    const bool vcf = g.Cf && g.ldc % 4 == 0 && ((uintptr_t)g.Cf & 15) == 0;
-    const bool vcb = g.Cb && g.ldcb % 4 == 0 && ((uintptr_t)g.Cb & 7) == 0;
-    const bool vz = g.Zin && g.ldz % 4 == 0 && ((uintptr_t)g.Zin & 15) == 0;
-    const bool vbias = g.bias && ((uintptr_t)g.bias & 15) == 0;
-    // Forward layers on a tile wholly inside the output with aligned operands
-    // (the usual case; the condition is uniform): no bounds tests, one vector
-    // bias load, store and (BF16) packed store per MFMA tile and lane.
-    if constexpr (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS) {
-        if (m0 + BM <= g.M && n0 + BN <= g.N && vbias && (EPI == EPI_BIAS ? vcf : vcb && (!g.Cf || vcf))) {
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const int col = n0 + wn + j * 16 + (lane >> 4) * 4;
-                const float4 bj = *reinterpret_cast<const float4 *>(g.bias + col);
-#pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                    const int row = m0 + wm + i * 16 + (lane & 15);
-                    const floatx4_t v = acc[i][j];
-                    const float z0 = v[0] + bj.x, z1 = v[1] + bj.y, z2 = v[2] + bj.z, z3 = v[3] + bj.w;
-                    if (EPI == EPI_BIAS || g.Cf)
-                        *reinterpret_cast<float4 *>(g.Cf + (size_t)row * g.ldc + col) =
-                            make_float4(z0, z1, z2, z3);
-                    if constexpr (EPI == EPI_BIAS_GELU)
-                        *reinterpret_cast<uint2 *>(g.Cb + (size_t)row * g.ldcb + col) =
-                            make_uint2(pack_bf16x2(gelu_f(z0), gelu_f(z1)),
-                                       pack_bf16x2(gelu_f(z2), gelu_f(z3)));
-                }
-            }
-            return;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int row = m0 + wm + i * 16 + (lane & 15);
-        if (row >= g.M) continue;
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int col = n0 + wn + j * 16 + (lane >> 4) * 4;
-            if (col >= g.N) continue;
-            const floatx4_t v = acc[i][j];
-            const bool full = col + 4 <= g.N;
-            float z[4];
-            if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS) {
-                if (full && vbias) {
-                    const float4 b = *reinterpret_cast<const float4 *>(g.bias + col);
-                    z[0] = v[0] + b.x;
-                    z[1] = v[1] + b.y;
-                    z[2] = v[2] + b.z;
-                    z[3] = v[3] + b.w;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) z[r] = v[r] + (col + r < g.N ? g.bias[col + r] : 0.f);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) z[r] = v[r];
-            }
-            if (EPI == EPI_BIAS || EPI == EPI_STORE_F32 || (EPI == EPI_BIAS_GELU && g.Cf)) {
-                float *dst = g.Cf + (size_t)row * g.ldc + col;
-                if (full && vcf) {
-                    *reinterpret_cast<float4 *>(dst) = make_float4(z[0], z[1], z[2], z[3]);
-                } else {
-                    for (int r = 0; r < 4 && col + r < g.N; ++r) dst[r] = z[r];
-                }
-            }
-            if (EPI == EPI_BIAS_GELU || EPI == EPI_GELU_GRAD) {
-                float zin[4] = {0.f, 0.f, 0.f, 0.f};
-                if (EPI == EPI_GELU_GRAD) {
-                    const float *zp = g.Zin + (size_t)row * g.ldz + col;
-                    if (full && vz) {
-                        const float4 q = *reinterpret_cast<const float4 *>(zp);
-                        zin[0] = q.x; zin[1] = q.y; zin[2] = q.z; zin[3] = q.w;
-                    } else {
-                        for (int r = 0; r < 4 && col + r < g.N; ++r) zin[r] = zp[r];
-                    }
-                }
-                float a[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    a[r] = EPI == EPI_BIAS_GELU ? gelu_f(z[r]) : z[r] * gelu_grad_f(zin[r]);
-                const uint2 pk = make_uint2(pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]));
-                uint16_t *dst = g.Cb + (size_t)row * g.ldcb + col;
-                if (full && vcb) {
-                    *reinterpret_cast<uint2 *>(dst) = pk;
-                } else {
-                    const uint16_t o[4] = {(uint16_t)pk.x, (uint16_t)(pk.x >> 16), (uint16_t)pk.y,
-                                           (uint16_t)(pk.y >> 16)};
-                    for (int r = 0; r < 4 && col + r < g.N; ++r) dst[r] = o[r];
-                }
-            }
-        }
-    }
+    // the A operand buffers become the waves' output staging areas
+    static_assert(2 * BM * LDS_LD >= 4 * (BM / 2) * (BN / 2 + 8), "staging fits in sA");
+    __syncthreads();
+    epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, &sA[0][0] + wave * (BM / 2) * (BN / 2 + 8));
 }
 
 template <bool AKV, bool BKV, int EP>

@@ -80,9 +80,12 @@ def test_forward_matches_oracle():
     assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
 
 
-def test_forward_full_network_matches_oracle():
+@pytest.mark.parametrize("n", [777, 1024])
+def test_forward_full_network_matches_oracle(n):
     """The production network (34-1024-512-256-32) against the oracle network,
-    on a row count ragged against the GEMM tile."""
+    on a row count ragged against the GEMM tile (777: the last row block takes
+    the bounds-checked epilogue) and on one the 128-row tiles divide (1,024:
+    every tile takes the epilogue staged through LDS)."""
     import torch
     from paper_2402_18858_amd import chemk, train
     mech = sm.mech_medium()
@@ -97,7 +100,6 @@ def test_forward_full_network_matches_oracle():
         params[off:off + dims[i + 1]] = rng.normal(0, 0.1, dims[i + 1]).astype(np.float32)
         off += dims[i + 1]
     ctx.ann_set_weights(params)
-    n = 777                                   # ragged against both tiles
     T, p, Y = _states(mech, n, 45)
     mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
     X = torch.empty((n, 64), dtype=torch.int16, device="cuda:0")
@@ -108,7 +110,7 @@ def test_forward_full_network_matches_oracle():
     Ws, bs = _unpack(params, dims)
     o, _ = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
     rel_rms = np.sqrt(np.mean((g - o) ** 2)) / np.sqrt(np.mean(o ** 2))
-    announce(f"forward (full network): rel rms {rel_rms:.2e}, max abs {np.abs(g - o).max():.2e}")
+    announce(f"forward (full network, {n} rows): rel rms {rel_rms:.2e}, max abs {np.abs(g - o).max():.2e}")
     assert rel_rms < 2e-3
     assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
 
