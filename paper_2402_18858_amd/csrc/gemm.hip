@@ -9,14 +9,22 @@
 // the tile loader transposes through LDS.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves, each
-// 64 x 64 in MFMA tiles of 32 x 32), K step 64 (four MFMA k-steps),
-// double-buffered LDS with a padded row stride, K slabs in flight in a ring
-// of registers ahead of the one being multiplied (buffer loads, which read
-// zeros past an operand's edge, so no load sits behind a branch).  (The kernel is templated on
-// the tile; a 256 x 256 tile with one workgroup per CU measured slower: the
-// K loop is bound by the latency of the next slab's global loads.)  Workgroups are mapped to
-// tiles so that each of the 8 XCDs walks a contiguous range of row blocks
-// (the A rows it streams stay in that XCD's L2).
+// 64 x 64 in MFMA tiles of 32 x 32), K step 64 (four MFMA k-steps), two LDS
+// stages.  Two kernels:
+//  * forward layers whose slab count is one the MLP has (4, 8, 16): the
+//    slabs go from global memory straight into LDS (buffer loads with an LDS
+//    destination), into unpadded rows with a swizzled chunk order;
+//  * everything else (training products, transposing loads, other K): a
+//    ring of registers holds the next slabs (buffer loads, which read zeros
+//    past an operand's edge, so no load sits behind a branch) and the tile is
+//    stored into LDS rows with a 16-byte pad.
+// Forward BF16 outputs leave through LDS so that each store instruction
+// writes whole 128-byte row segments.  Workgroups are mapped to tiles so that
+// each of the 8 XCDs walks a contiguous range of row blocks (the A rows it
+// streams stay in that XCD's L2).  Measured alternatives that lost: a 256 x
+// 256 tile with one workgroup per CU, a two-group ping-pong schedule, deeper
+// register rings; the 16 x 16 x 32 MFMA needs twice the independent
+// accumulations in flight for the same rate.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,12 +46,6 @@ __device__ __forceinline__ floatx16_t mfma32(const bf16x8_t &b, const bf16x8_t &
 }
 
 constexpr int NTHREADS = 256;
-// K slabs in flight in registers ahead of the one being multiplied, for the
-// kernels with a compile-time slab count (2 to 4; the others use 2)
-#ifndef CHEMK_GEMM_PREFETCH
-#define CHEMK_GEMM_PREFETCH 2
-#endif
-constexpr int kGemmPrefetch = CHEMK_GEMM_PREFETCH;
 
 
 // bf16 elements per LDS row for a K step of BK (16-byte pad)
@@ -109,6 +111,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
+
 
 // Buffer resource over one operand: raw buffer loads return zero for offsets
 // past num_records, which is how the tile loader handles the edges.
@@ -336,12 +339,11 @@ __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16_t (&a
 }
 
 // BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each with a
-// (BM/2) x (BN/2) tile of TM x TN MFMA tiles of 32 x 32.
-// KTC > 0: the number of K slabs, fixed at compile time, so the K loop is
-// unrolled completely (the compiler's waits can then keep later slabs in
-// flight, which it does not do across a loop back-edge); 0: runtime loop.
-template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC, int KTC, int PD>
+// (BM/2) x (BN/2) tile of TM x TN MFMA tiles of 32 x 32.  Runtime K loop,
+// unrolled by the ring depth.
+template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC>
 __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
+    constexpr int PD = 2;   // K slabs in flight in registers ahead of the one multiplied
     constexpr int TM = BM / 64, TN = BN / 64, LDS_LD = lds_ld<BK>();
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_LD];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDS_LD];
@@ -376,9 +378,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     // work to arrive.  The ring index is a compile-time constant (the K loop
     // is unrolled by PD).
     constexpr int QA = BM * BK / 8 / NTHREADS, QB = BN * BK / 8 / NTHREADS;
-    static_assert(PD >= 2 && PD <= 4, "ring depth 2 to 4");
     uint4 ra[PD][QA], rb[PD][QB];
-    const int KT = KTC > 0 ? KTC : (g.K + BK - 1) / BK;
+    const int KT = (g.K + BK - 1) / BK;
     const __amdgpu_buffer_rsrc_t rsA =
         operand_rsrc(g.A, 2ll * g.lda * (AK ? g.M : g.K));
     const __amdgpu_buffer_rsrc_t rsB =
@@ -432,46 +433,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     store_tile<BN, BK, BKc>(sB[((KTV) + 1) & 1], rb[N], tid);                                  \
     lds_barrier();                                                                        \
     load_slab(ra[N], rb[N], (KTV) + PD + 1);
-    if constexpr (KTC > 0) {
-        // Unrolled slab by slab (the ring slot is a compile-time constant and
-        // nothing is loaded or computed past the last slab), in two halves of
-        // 32 k per slab with the fragments double-buffered in registers, so
-        // that LDS traffic overlaps the MFMAs:
-        //   read half 1 of slab kt; store slab kt+1 into the other buffer;
-        //   MFMA half 0 of slab kt; barrier (slab kt+1 visible, every read of
-        //   slab kt done); read half 0 of slab kt+1 and issue the global load
-        //   of slab kt+PD+1; MFMA half 1 of slab kt.
-        static_assert(BK == 64, "two halves of 32 per slab");
-#pragma unroll
-        for (int q = 1; q <= PD; ++q)
-            if (q < KTC) load_slab(ra[q % PD], rb[q % PD], q);
-        // Each half step issues its memory operations first and its MFMAs
-        // after a scheduling fence (the MFMAs use fragments read one half
-        // step earlier, so nothing waits on the new reads):
-        //   [read half 1 of kt, store slab kt+1] | MFMA half 0 of kt | barrier
-        //   [read half 0 of kt+1, load slab kt+PD+1] | MFMA half 1 of kt
-        bf16x8_t a0[2][TM], b0[2][TN], a1[2][TM], b1[2][TN];
-        read_frags(0, 0, a0, b0);
-#pragma unroll
-        for (int kt = 0; kt < KTC; ++kt) {
-            const int N = (kt + 1) % PD;
-            read_frags(kt & 1, 32, a1, b1);
-            if (kt + 1 < KTC) {
-                store_tile<BM, BK, AK>(sA[(kt + 1) & 1], ra[N], tid);
-                store_tile<BN, BK, BKc>(sB[(kt + 1) & 1], rb[N], tid);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            mfma_frags(a0, b0);
-            if (kt + 1 < KTC) {
-                lds_barrier();
-                read_frags((kt + 1) & 1, 0, a0, b0);
-                if (kt + PD + 1 < KTC) load_slab(ra[N], rb[N], kt + PD + 1);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            mfma_frags(a1, b1);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else if (KT == 1) {
+    if (KT == 1) {
         compute(0);
     } else {
         // KT rounded up to whole ring turns; the extra slabs load as zeros
@@ -479,19 +441,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
         for (int q = 1; q <= PD; ++q) load_slab(ra[q % PD], rb[q % PD], q);
         auto turn = [&](int kt) {
-            if constexpr (PD == 2) {
-                GEMM_STEP(kt, 1)
-                GEMM_STEP(kt + 1, 0)
-            } else if constexpr (PD == 3) {
-                GEMM_STEP(kt, 1)
-                GEMM_STEP(kt + 1, 2)
-                GEMM_STEP(kt + 2, 0)
-            } else {
-                GEMM_STEP(kt, 1)
-                GEMM_STEP(kt + 1, 2)
-                GEMM_STEP(kt + 2, 3)
-                GEMM_STEP(kt + 3, 0)
-            }
+            GEMM_STEP(kt, 1)
+            GEMM_STEP(kt + 1, 0)
         };
 #pragma unroll 1
         for (int kt = 0; kt < KTR; kt += PD) turn(kt);
@@ -504,6 +455,119 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, &sA[0][0] + wave * (BM / 2) * (BN / 2 + 8));
 }
 
+// Forward GEMM with the K slabs loaded straight into LDS (buffer loads with
+// an LDS destination: no register staging, no LDS store instructions), for
+// K-contiguous operands in whole 16-byte chunks and a compile-time slab
+// count.  The LDS tiles are unpadded (128-byte rows); a lane's 16 bytes land
+// at the wave's base + 16 lane, so the chunk order within a row is swizzled
+// instead: LDS chunk position p of row r holds the operand's chunk
+// p ^ ((r >> 1) & 7), which keeps the fragment reads of 16 consecutive rows
+// on 16 distinct 4-bank groups.  Two stages, each its own LDS array (so the
+// compiler can tell a load into one stage from reads of the other): slab
+// kt+2 is loaded into the stage slab kt occupied once every wave has read it.
+// The waits and barriers of the K loop are written out: the compiler's own
+// fence would wait for every load into LDS, including the newest slab's.
+template <int EPI, int KTC>
+__global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
+    constexpr int BM = 128, BN = 128, BK = 64, TM = BM / 64, TN = BN / 64;
+    constexpr int SA = BM * BK, SB = BN * BK;          // elements per operand and stage
+    constexpr int NI = (BM + BN) * BK / 8 / NTHREADS;  // 16-byte loads per thread per slab
+    static_assert(NI == 8, "the K loop waits for vmcnt(8)");
+    static_assert(SA >= (BM / 2) * (BN / 2 + 8) && SB >= (BM / 2) * (BN / 2 + 8), "staging fits");
+    __shared__ __attribute__((aligned(16))) uint16_t sA0[SA], sB0[SB], sA1[SA], sB1[SB];
+
+    const int mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
+    const int tiles = mt * nt;
+    const int per = (tiles + 7) / 8;
+    const int w = blockIdx.x;
+    const int tile = (w & 7) * per + (w >> 3);
+    if (tile >= tiles) return;
+    const int tm = tile / nt, tn = tile - tm * nt;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+
+    floatx16_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const __amdgpu_buffer_rsrc_t rsA = operand_rsrc(g.A, 2ll * g.lda * g.M);
+    const __amdgpu_buffer_rsrc_t rsB = operand_rsrc(g.B, 2ll * g.ldb * g.N);
+    // one slab: wave w loads rows [8 (4 w + q), +8) of A and of B, q < 4;
+    // lane l: row 8 (4 w + q) + l / 8, LDS chunk l % 8, operand chunk swizzled
+    auto load_slab = [&](int kt, uint16_t *sa, uint16_t *sb) {
+        const int rl = lane >> 3, p = lane & 7, k0 = kt * BK;
+#pragma unroll
+        for (int q = 0; q < BM / 32; ++q) {
+            const int r = (wave * (BM / 32) + q) * 8 + rl;
+            const int gk = k0 + 8 * (p ^ ((r >> 1) & 7));
+            const int offa = (m0 + r < g.M && gk < g.K) ? 2 * ((m0 + r) * g.lda + gk) : 0x7fffffff;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rsA, (void __attribute__((address_space(3))) *)(sa + (r - rl) * BK), 16, offa, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < BN / 32; ++q) {
+            const int r = (wave * (BN / 32) + q) * 8 + rl;
+            const int gk = k0 + 8 * (p ^ ((r >> 1) & 7));
+            const int offb = (n0 + r < g.N && gk < g.K) ? 2 * ((n0 + r) * g.ldb + gk) : 0x7fffffff;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rsB, (void __attribute__((address_space(3))) *)(sb + (r - rl) * BK), 16, offb, 0, 0, 0);
+        }
+    };
+    const int fr = lane & 31, fc = lane >> 5;   // fragment row in the tile, chunk within a k-step
+    auto compute = [&](const uint16_t *sa, const uint16_t *sb) {
+#pragma unroll
+        for (int s = 0; s < BK / 16; ++s) {
+            const int c = 2 * s + fc;   // logical 16-byte chunk of the row
+            bf16x8_t af[TM], bfr[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int r = wm + i * 32 + fr;
+                af[i] = *reinterpret_cast<const bf16x8_t *>(sa + r * BK + 8 * (c ^ ((r >> 1) & 7)));
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int r = wn + j * 32 + fr;
+                bfr[j] = *reinterpret_cast<const bf16x8_t *>(sb + r * BK + 8 * (c ^ ((r >> 1) & 7)));
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = mfma32(bfr[j], af[i], acc[i][j]);
+        }
+    };
+    load_slab(0, sA0, sB0);
+    if (KTC > 1) {
+        load_slab(1, sA1, sB1);
+        asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    }
+#pragma unroll
+    for (int kt = 0; kt < KTC; ++kt) {
+        uint16_t *sa = (kt & 1) ? sA1 : sA0, *sb = (kt & 1) ? sB1 : sB0;
+        compute(sa, sb);
+        if (kt + 1 < KTC) {
+            // every wave has read this stage: it takes slab kt+2
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            if (kt + 2 < KTC) {
+                load_slab(kt + 2, sa, sb);
+                asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");   // slab kt+1 landed everywhere
+            } else {
+                asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+            }
+        }
+    }
+    // the stages become the waves' output staging areas, one array each
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    uint16_t *stage = wave == 0 ? sA0 : wave == 1 ? sB0 : wave == 2 ? sA1 : sB1;
+    epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, stage);
+}
+
 template <bool AKV, bool BKV, int EP>
 static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
     constexpr int TB = 128, TK = 64;
@@ -512,19 +576,19 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
     const int kt = (g.K + TK - 1) / TK;
     // forward layers of the MLP get a K loop unrolled for their slab count
     constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS);
-#define GEMM_LAUNCH(VECV, KTV)                                                               \
-    hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV, KTV,                  \
-                                         ((KTV) > 0 ? kGemmPrefetch : 2)>),                    \
-                       dim3(grid), dim3(NTHREADS), 0, s, g)
+#define GEMM_LAUNCH(VECV)                                                                    \
+    hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV>), dim3(grid),         \
+                       dim3(NTHREADS), 0, s, g)
     if (!vec) {
-        GEMM_LAUNCH(false, 0);
+        GEMM_LAUNCH(false);
     } else if constexpr (fwd) {
-        if (kt == 16) GEMM_LAUNCH(true, 16);
-        else if (kt == 8) GEMM_LAUNCH(true, 8);
-        else if (kt == 4) GEMM_LAUNCH(true, 4);
-        else GEMM_LAUNCH(true, 0);
+        // forward layers with a slab count the MLP has: slabs loaded straight into LDS
+        if (kt == 16) hipLaunchKernelGGL((gemm_dma_kernel<EP, 16>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 8) hipLaunchKernelGGL((gemm_dma_kernel<EP, 8>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 4) hipLaunchKernelGGL((gemm_dma_kernel<EP, 4>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else GEMM_LAUNCH(true);
     } else {
-        GEMM_LAUNCH(true, 0);
+        GEMM_LAUNCH(true);
     }
 #undef GEMM_LAUNCH
     return hipGetLastError();
