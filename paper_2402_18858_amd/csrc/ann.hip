@@ -151,81 +151,73 @@ __device__ __forceinline__ void rows_to_lds(const Tv *__restrict__ g, int cnt, i
 // Features (Box-Cox of the K mass fractions, then T and p), z-scored and
 // rounded to BF16 into a row of FPAD inputs; the envelope flag (a raw feature
 // outside [lo, hi] of the training data, or NaN); the enthalpy h(T, Y) / R
-// that the post step conserves.
-template <int KM>
-__global__ void __launch_bounds__(POST_CELLS, 2) ingest_kernel(int K, int n,
-                                                               const double *__restrict__ tab,
-                                                               const double *__restrict__ T,
-                                                               const double *__restrict__ p,
-                                                               const double *__restrict__ Y,
-                                                               uint16_t *__restrict__ X,
-                                                               int *__restrict__ route,
-                                                               double *__restrict__ h0R) {
-    // Rows of Y come in, and rows of X go out, through LDS so that the global
-    // accesses are coalesced.  X rows are FPAD BF16 = 8 chunks of 16 bytes,
-    // staged at a stride of 9 chunks.
-    constexpr int ld = KM + 1, XLD = FPAD / 8 + 1;
-    constexpr int LDS_D = POST_CELLS * (ld > 2 * XLD ? ld : 2 * XLD);
-    __shared__ double s_row[LDS_D];
-    const int base = blockIdx.x * POST_CELLS;
-    const int cnt = n - base < POST_CELLS ? n - base : POST_CELLS;
-    const int lane = threadIdx.x;
-    const bool valid = lane < cnt;
-    const int c = valid ? base + lane : base;
-    rows_to_lds<KM>(Y + (size_t)base * K, cnt, K, 1.0f / (float)K, s_row, ld);
-    __syncthreads();
-    double y[KM];
+// that the post step conserves.  A group of KP lanes (the power of two >= K,
+// equal to the table's KM) takes one cell, lane k its species k, so that the
+// species' constants stay in the lane's registers for the whole launch; a
+// wave advances 64 / KP cells per iteration, reading their rows of Y and
+// writing their rows of X coalesced (lane k: the columns k, k + KP, ...).
+constexpr int ING_THREADS = 256;
+
+template <int KP>
+__global__ void __launch_bounds__(ING_THREADS) ingest_kernel(int K, int n,
+                                                             const double *__restrict__ tab,
+                                                             const double *__restrict__ T,
+                                                             const double *__restrict__ p,
+                                                             const double *__restrict__ Y,
+                                                             uint16_t *__restrict__ X,
+                                                             int *__restrict__ route,
+                                                             double *__restrict__ h0R) {
+    static_assert(KP == 16 || KP == 32 || KP == 64, "lane group");
+    constexpr int CPW = 64 / KP, NCOL = FPAD / KP;
+    const int lane = threadIdx.x & 63, k = lane % KP, sub = lane / KP;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int waves = gridDim.x * (ING_THREADS / 64);
+    const bool sp = k < K;
+    // species k's constants (zero past K) and those of the T and p features
+    double lo = 0.0, hi = 0.0, mu = 0.0, isd = 0.0, iw = 0.0, a[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (sp) {
+        lo = tab[ti_lo + k];
+        hi = tab[ti_hi + k];
+        mu = tab[ti_mu + k];
+        isd = tab[ti_sd + k];
+        iw = tab[ti_invW(KP) + k];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) y[k] = k < K ? s_row[lane * ld + k] : 0.0;
-    const double Tc = T[c], pc = p[c];
-    const double invT = 1.0 / Tc;
-    // species features; beyond K the row and the tables are zero, which adds
-    // nothing to h and is masked out of the envelope test and the row
-    bool out = false;
-    double hs = 0.0;
-    float fs[KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const double raw = box_cox(y[k]);
+        for (int j = 0; j < 6; ++j) a[j] = tab[ti_nasa + 7 * k + j];
+    }
+    const double loT = tab[ti_lo + K], hiT = tab[ti_hi + K], muT = tab[ti_mu + K], isdT = tab[ti_sd + K];
+    const double lop = tab[ti_lo + K + 1], hip = tab[ti_hi + K + 1], mup = tab[ti_mu + K + 1],
+                 isdp = tab[ti_sd + K + 1];
+    const unsigned long long gmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
+    for (int g = blockIdx.x * (ING_THREADS / 64) + wave; g * CPW < n; g += waves) {
+        const int c = g * CPW + sub;
+        const bool cv = c < n;
+        const int cc = cv ? c : n - 1;
+        const double y = (cv && sp) ? Y[(size_t)cc * K + k] : 0.0;
+        const double Tc = T[cc], pc = p[cc];
+        const double raw = box_cox(y);
         double cpR, hRT;
-        sp_cp_h(tab + ti_nasa + 7 * k, Tc, invT, cpR, hRT);
-        hs += y[k] * tab[ti_invW(KM) + k] * hRT;
-        const bool inside = (raw >= tab[ti_lo + k]) & (raw <= tab[ti_hi + k]);   // NaN -> outside
-        out |= (k < K) & !inside;
-        fs[k] = (float)((raw - tab[ti_mu + k]) * tab[ti_sd + k]);
-    }
-    // T and p: features K and K + 1
-    out |= !((Tc >= tab[ti_lo + K]) & (Tc <= tab[ti_hi + K]));
-    out |= !((pc >= tab[ti_lo + K + 1]) & (pc <= tab[ti_hi + K + 1]));
-    const float fT = (float)((Tc - tab[ti_mu + K]) * tab[ti_sd + K]);
-    const float fp = (float)((pc - tab[ti_mu + K + 1]) * tab[ti_sd + K + 1]);
-    float f[FPAD];
+        sp_cp_h(a, Tc, 1.0 / Tc, cpR, hRT);
+        double h = y * iw * hRT;   // zero past K
 #pragma unroll
-    for (int j = 0; j < FPAD; ++j) {
-        const float sp = j < KM ? fs[j < KM ? j : 0] : 0.0f;
-        f[j] = j < K ? sp : (j == K ? fT : (j == K + 1 ? fp : 0.0f));
-    }
-    __syncthreads();
-    uint4 *sx = reinterpret_cast<uint4 *>(s_row);
+        for (int o = KP / 2; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+        const bool bad = sp && !((raw >= lo) & (raw <= hi));   // NaN -> outside
+        const unsigned long long m = __ballot(bad);
+        const bool out = ((m >> (sub * KP)) & gmask) != 0 || !((Tc >= loT) & (Tc <= hiT)) ||
+                         !((pc >= lop) & (pc <= hip));
+        const float fs = (float)((raw - mu) * isd);
+        const float fT = (float)((Tc - muT) * isdT), fp = (float)((pc - mup) * isdp);
+        if (cv) {
 #pragma unroll
-    for (int q = 0; q < FPAD / 8; ++q) {
-        uint4 v;
-        v.x = (uint32_t)f2bf(f[8 * q + 0]) | ((uint32_t)f2bf(f[8 * q + 1]) << 16);
-        v.y = (uint32_t)f2bf(f[8 * q + 2]) | ((uint32_t)f2bf(f[8 * q + 3]) << 16);
-        v.z = (uint32_t)f2bf(f[8 * q + 4]) | ((uint32_t)f2bf(f[8 * q + 5]) << 16);
-        v.w = (uint32_t)f2bf(f[8 * q + 6]) | ((uint32_t)f2bf(f[8 * q + 7]) << 16);
-        sx[lane * XLD + q] = v;
-    }
-    __syncthreads();
-    uint4 *gx = reinterpret_cast<uint4 *>(X + (size_t)base * FPAD);
-#pragma unroll
-    for (int r = 0; r < FPAD / 8; ++r) {
-        const int j = r * POST_CELLS + lane;   // chunk j: row j / 8, chunk j % 8
-        if (j < cnt * (FPAD / 8)) gx[j] = sx[(j >> 3) * XLD + (j & 7)];
-    }
-    if (valid) {
-        route[c] = out ? 1 : 0;
-        h0R[c] = hs * Tc;
+            for (int q = 0; q < NCOL; ++q) {
+                const int col = k + q * KP;   // only q = 0 can be a species column (KP >= K)
+                const float v = col < K ? fs : (col == K ? fT : (col == K + 1 ? fp : 0.0f));
+                X[(size_t)c * FPAD + col] = f2bf(v);
+            }
+            if (k == 0) {
+                route[c] = out ? 1 : 0;
+                h0R[c] = h * Tc;
+            }
+        }
     }
 }
 
@@ -432,14 +424,19 @@ __global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
     __syncthreads();
     double *dst = Y + (size_t)base * K;
     const int total = cnt * K;
+    double v[KM];
+    int kp[KM];
 #pragma unroll
-    for (int r = 0; r < KM; ++r) {
+    for (int r = 0; r < KM; ++r) {   // all LDS reads first, then the stores
         const int i = r * POST_CELLS + lane;
-        if (i < total) {
-            const int cc = (int)(((float)i + 0.5f) * invK);
-            if (s_keep[cc]) dst[i] = s_row[cc * ld + (i - cc * K)];
-        }
+        const int ii = i < total ? i : 0;
+        const int cc = (int)(((float)ii + 0.5f) * invK);
+        kp[r] = i < total ? s_keep[cc] : 0;
+        v[r] = s_row[cc * ld + (ii - cc * K)];
     }
+#pragma unroll
+    for (int r = 0; r < KM; ++r)
+        if (kp[r]) dst[r * POST_CELLS + lane] = v[r];
 }
 
 template <int KM> struct KmOf {
@@ -458,10 +455,12 @@ template <typename Fn> static hipError_t with_km(int K, Fn &&f) {
 
 static hipError_t launch_ingest(int K, const double *tab, int n, const double *T, const double *p,
                                 const double *Y, uint16_t *X, int *route, double *h0, hipStream_t s) {
-    const int grid = (n + POST_CELLS - 1) / POST_CELLS;
+    if (n <= 0) return hipSuccess;
     return with_km(K, [&](auto km) {
-        constexpr int KM = decltype(km)::v;
-        hipLaunchKernelGGL(ingest_kernel<KM>, dim3(grid), dim3(POST_CELLS), 0, s, K, n, tab, T, p, Y, X,
+        constexpr int KP = decltype(km)::v;
+        const int64_t groups = ((int64_t)n + 64 / KP - 1) / (64 / KP);
+        const int grid = (int)std::min<int64_t>(2048, (groups + ING_THREADS / 64 - 1) / (ING_THREADS / 64));
+        hipLaunchKernelGGL(ingest_kernel<KP>, dim3(grid), dim3(ING_THREADS), 0, s, K, n, tab, T, p, Y, X,
                            route, h0);
         return hipGetLastError();
     });
