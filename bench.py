@@ -77,13 +77,15 @@ def ann_vs_di(ctx, mech, Y0, T_a, Y_a, st_a, T_d, Y_d, routed_bit):
     e = (Y_a[net] - Y_d[net]) / sd_y[None, :]
     m0, m1 = element_mass(mech, Y0[net]), element_mass(mech, Y_a[net])
     drift = np.abs(m1 - m0) / np.maximum(m0, 1e-300)
-    # species the training data moves (others have a floored sd of dY, where
-    # the normalised error says nothing; their absolute error is listed)
-    act = sd_y >= 1e-6 * sd_y.max()
+    # the species that carry the chemistry's change over dt (sd of dY in the
+    # training data at least 1e-3 of the largest); for the others the
+    # normalised error measures mostly the element projection's corrections,
+    # so their absolute error is listed instead
+    act = sd_y >= 1e-3 * sd_y.max()
     return {"cells": int(net.sum()),
-            "rms_norm_active": float(np.sqrt(np.mean(e[:, act] ** 2))),
-            "active_species": int(act.sum()),
-            "inactive_species_rms_abs": {int(k): float(f"{v:.3e}") for k, v in zip(
+            "rms_norm_major": float(np.sqrt(np.mean(e[:, act] ** 2))),
+            "major_species": int(act.sum()),
+            "minor_species_rms_abs": {int(k): float(f"{v:.3e}") for k, v in zip(
                 np.nonzero(~act)[0], np.sqrt(np.mean((Y_a[net][:, ~act] - Y_d[net][:, ~act]) ** 2, 0)))},
             "rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(e * e, 0))],
             "max_norm": [round(float(v), 4) for v in np.abs(e).max(0)],
