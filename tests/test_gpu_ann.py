@@ -80,17 +80,20 @@ def test_forward_matches_oracle():
     assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
 
 
-@pytest.mark.parametrize("n", [777, 1024])
-def test_forward_full_network_matches_oracle(n):
+@pytest.mark.parametrize("n,hidden", [(777, None), (1024, None), (777, (1024, 512, 192))])
+def test_forward_full_network_matches_oracle(n, hidden):
     """The production network (34-1024-512-256-32) against the oracle network,
     on a row count ragged against the GEMM tile (777: the last row block takes
     the bounds-checked epilogue) and on one the 128-row tiles divide (1,024:
-    every tile takes the epilogue staged through LDS)."""
+    every tile takes the epilogue staged through LDS); and hidden widths
+    1024-512-192, which give the direct-to-LDS kernel a partial column tile
+    (layer 3, N = 192) and the register-ring kernel a K of three slabs
+    (layer 4)."""
     import torch
     from paper_2402_18858_amd import chemk, train
     mech = sm.mech_medium()
     ctx = chemk.Context(mech)
-    dims = train.default_dims(mech.K)
+    dims = train.default_dims(mech.K) if hidden is None else [mech.K + 2, *hidden, mech.K]
     ctx.ann_create(dims)
     params = train.init_params(dims, 21)
     rng = np.random.default_rng(21)
@@ -110,7 +113,7 @@ def test_forward_full_network_matches_oracle(n):
     Ws, bs = _unpack(params, dims)
     o, _ = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
     rel_rms = np.sqrt(np.mean((g - o) ** 2)) / np.sqrt(np.mean(o ** 2))
-    announce(f"forward (full network, {n} rows): rel rms {rel_rms:.2e}, max abs {np.abs(g - o).max():.2e}")
+    announce(f"forward (network {dims}, {n} rows): rel rms {rel_rms:.2e}, max abs {np.abs(g - o).max():.2e}")
     assert rel_rms < 2e-3
     assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
 
