@@ -80,15 +80,17 @@ def test_forward_matches_oracle():
     assert np.abs(g - o).max() < 2e-2 * np.abs(o).max()
 
 
-@pytest.mark.parametrize("n,hidden", [(777, None), (1024, None), (777, (1024, 512, 192))])
+@pytest.mark.parametrize("n,hidden", [(777, None), (1024, None), (777, (1024, 512, 192)),
+                                      (1024, (960, 512, 256))])
 def test_forward_full_network_matches_oracle(n, hidden):
     """The production network (34-1024-512-256-32) against the oracle network,
     on a row count ragged against the GEMM tile (777: the last row block takes
     the bounds-checked epilogue) and on one the 128-row tiles divide (1,024:
-    every tile takes the epilogue staged through LDS); and hidden widths
+    every tile takes the epilogue staged through LDS); hidden widths
     1024-512-192, which give the direct-to-LDS kernel a partial column tile
     (layer 3, N = 192) and the register-ring kernel a K of three slabs
-    (layer 4)."""
+    (layer 4); and 960-512-256, which give the one-slab first layer a partial
+    column tile (N = 960) and the register-ring kernel K = 960 (15 slabs)."""
     import torch
     from paper_2402_18858_amd import chemk, train
     mech = sm.mech_medium()
