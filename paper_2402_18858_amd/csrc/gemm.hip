@@ -9,15 +9,16 @@
 // the tile loader transposes through LDS.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves, each
-// 64 x 64 in MFMA tiles of 32 x 32), K step 64 (four MFMA k-steps), two LDS
-// stages.  Two kernels:
+// 64 x 64 in MFMA tiles of 32 x 32), K step 64 (four MFMA k-steps).  Two
+// kernels:
 //  * forward layers whose slab count is one the MLP has (1, 4, 8, 16): the
 //    slabs go from global memory straight into LDS (buffer loads with an LDS
-//    destination), into unpadded rows with a swizzled chunk order; one slab
-//    (the first layer, K = 64) takes a single stage, shared with the output
-//    staging, so that four workgroups fit on a CU;
-//  * everything else (training products, transposing loads, other K): a
-//    ring of registers holds the next slabs (buffer loads, which read zeros
+//    destination), into unpadded rows with a swizzled chunk order.  1, 8 and
+//    16 slabs use a single LDS stage shared with the output staging (37 KB,
+//    four workgroups per CU, which hide each other's slab loads); 4 slabs
+//    (the last layer) use two stages and prefetch;
+//  * everything else (training products, transposing loads, other K): two
+//    LDS stages, and a ring of registers holds the next slabs (buffer loads, which read zeros
 //    past an operand's edge, so no load sits behind a branch) and the tile is
 //    stored into LDS rows with a 16-byte pad.
 // Forward BF16 outputs leave through LDS so that each store instruction
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
 // kt+2 is loaded into the stage slab kt occupied once every wave has read it.
 // The waits and barriers of the K loop are written out: the compiler's own
 // fence would wait for every load into LDS, including the newest slab's.
-template <int EPI, int KTC>
+template <int EPI, int KTC, int STAGES>
 __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
     constexpr int BM = 128, BN = 128, BK = 64, TM = BM / 64, TN = BN / 64;
     constexpr int SA = BM * BK, SB = BN * BK;          // elements per operand and stage
@@ -484,13 +485,19 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
     static_assert(NI == 8, "the K loop waits for vmcnt(8)");
     constexpr int STG = (BM / 2) * (BN / 2 + 8);       // one wave's output staging area
     static_assert(SA >= STG && SB >= STG, "staging fits");
-    // One slab (K <= 64) needs one stage: operands and the four staging areas
-    // then share one array (37 KB: four workgroups per CU).  Deeper K loops
-    // keep one array per operand and stage, so that the compiler sees that
-    // the LDS-destination loads of one stage do not touch the other.
+    // One LDS stage: operands and the four staging areas share one array
+    // (37 KB), so that four workgroups fit on a CU and one's slab load and
+    // barriers overlap the others' MFMAs (the kernel is latency-bound: with
+    // two workgroups per CU its MFMA pipes are busy 40 % of the time and
+    // its LDS 24 %).  Two stages (64 KB, two workgroups per CU): each
+    // workgroup loads slab kt + 2 while it multiplies slab kt + 1; each
+    // operand and stage then has its own array, so that the compiler sees
+    // that the LDS-destination loads of one stage do not touch the other.
+    static_assert(STAGES == 1 || (STAGES == 2 && KTC >= 2), "stages");
+    constexpr bool ONE = STAGES == 1;
     constexpr int S1 = SA + SB > 4 * STG ? SA + SB : 4 * STG;
-    __shared__ __attribute__((aligned(16))) uint16_t sA0[KTC == 1 ? S1 : SA], sB0[KTC == 1 ? 8 : SB],
-        sA1[KTC == 1 ? 8 : SA], sB1[KTC == 1 ? 8 : SB];
+    __shared__ __attribute__((aligned(16))) uint16_t sA0[ONE ? S1 : SA], sB0[ONE ? 8 : SB],
+        sA1[ONE ? 8 : SA], sB1[ONE ? 8 : SB];
 
     const int mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
     const int tiles = mt * nt;
@@ -556,11 +563,15 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
                 for (int j = 0; j < TN; ++j) acc[i][j] = mfma32(bfr[j], af[i], acc[i][j]);
         }
     };
-    if constexpr (KTC == 1) {
-        load_slab(0, sA0, sA0 + SA);
-        asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-        compute(sA0, sA0 + SA);
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if constexpr (ONE) {
+#pragma unroll
+        for (int kt = 0; kt < KTC; ++kt) {
+            load_slab(kt, sA0, sA0 + SA);
+            asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+            compute(sA0, sA0 + SA);
+            // every wave has read the stage: it takes the next slab (or the output)
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        }
         epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, sA0 + wave * STG);
     } else {
     load_slab(0, sA0, sB0);
@@ -603,10 +614,12 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
         GEMM_LAUNCH(false);
     } else if constexpr (fwd) {
         // forward layers with a slab count the MLP has: slabs loaded straight into LDS
-        if (kt == 1) hipLaunchKernelGGL((gemm_dma_kernel<EP, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
-        else if (kt == 16) hipLaunchKernelGGL((gemm_dma_kernel<EP, 16>), dim3(grid), dim3(NTHREADS), 0, s, g);
-        else if (kt == 8) hipLaunchKernelGGL((gemm_dma_kernel<EP, 8>), dim3(grid), dim3(NTHREADS), 0, s, g);
-        else if (kt == 4) hipLaunchKernelGGL((gemm_dma_kernel<EP, 4>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        // stages as measured fastest: one (four workgroups per CU) for 1, 8
+        // and 16 slabs; two for 4 slabs (the last layer, N = 32)
+        if (kt == 1) hipLaunchKernelGGL((gemm_dma_kernel<EP, 1, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 16) hipLaunchKernelGGL((gemm_dma_kernel<EP, 16, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 8) hipLaunchKernelGGL((gemm_dma_kernel<EP, 8, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 4) hipLaunchKernelGGL((gemm_dma_kernel<EP, 4, 2>), dim3(grid), dim3(NTHREADS), 0, s, g);
         else GEMM_LAUNCH(true);
     } else {
         GEMM_LAUNCH(true);
