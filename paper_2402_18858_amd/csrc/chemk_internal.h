@@ -25,8 +25,10 @@ struct PhaseTimer {
             pool.pop_back();
             return e;
         }
+        // Timing only (read after a stream synchronize): no system-scope
+        // fence, whose cache writeback would slow the launches that follow.
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
     void begin(int ph, hipStream_t s) {
