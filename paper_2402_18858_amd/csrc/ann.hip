@@ -188,12 +188,24 @@ __global__ void __launch_bounds__(ING_THREADS) ingest_kernel(int K, int n,
     const double lop = tab[ti_lo + K + 1], hip = tab[ti_hi + K + 1], mup = tab[ti_mu + K + 1],
                  isdp = tab[ti_sd + K + 1];
     const unsigned long long gmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
-    for (int g = blockIdx.x * (ING_THREADS / 64) + wave; g * CPW < n; g += waves) {
-        const int c = g * CPW + sub;
+    // this lane's mass fraction, T and p of group gg (the last cell past n)
+    auto fetch = [&](int gg, double &y, double &Tc, double &pc) {
+        const int c = gg * CPW + sub;
         const bool cv = c < n;
         const int cc = cv ? c : n - 1;
-        const double y = (cv && sp) ? Y[(size_t)cc * K + k] : 0.0;
-        const double Tc = T[cc], pc = p[cc];
+        y = (cv && sp) ? Y[(size_t)cc * K + k] : 0.0;
+        Tc = T[cc];
+        pc = p[cc];
+    };
+    int g = blockIdx.x * (ING_THREADS / 64) + wave;
+    double yN = 0.0, TN = 0.0, pN = 0.0;
+    if (g * CPW < n) fetch(g, yN, TN, pN);
+    for (; g * CPW < n; g += waves) {
+        const int c = g * CPW + sub;
+        const bool cv = c < n;
+        const double y = yN, Tc = TN, pc = pN;
+        // the next group's loads travel during this group's arithmetic
+        if ((g + waves) * CPW < n) fetch(g + waves, yN, TN, pN);
         const double raw = box_cox(y);
         double cpR, hRT;
         sp_cp_h(a, Tc, 1.0 / Tc, cpR, hRT);
