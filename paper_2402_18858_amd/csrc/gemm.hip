@@ -85,7 +85,7 @@ __device__ __forceinline__ float erf_as(float x) {
 // x clamped to +-4.5 outside (where Phi is within 3.4e-6 of 0 or 1).  P is a
 // degree-11 polynomial in t = x^2 - 8.1 (centred, so that its terms do not
 // cancel in FP32), fitted near-minimax to the error function on the clamped
-// range: |Phi error| <= 1.9e-7, GELU absolute error <= 5.7e-7 for |x| <= 3
+// range: |Phi error| <= 2.1e-7, GELU absolute error <= 5.7e-7 for |x| <= 3
 // and relative error <= 3.6e-6 for x > 0.05, so that the BF16 activations
 // it feeds round as those of the exact GELU do in all but about 2.5 % of
 // cases, each one BF16 step apart.  Cost: a clamp and thirteen FMAs, no
