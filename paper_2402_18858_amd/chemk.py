@@ -149,6 +149,9 @@ class Mechanism:
                      *(k[n].ctypes.data for n in ("em", "comp", "nasa", "reac", "prod", "lnA",
                                                   "beta", "Ea", "tb", "rev")))
         h = C.c_void_p()
+        # bound here: at interpreter exit the module's globals may be gone
+        # before this object is
+        self._free = lib.chemk_mech_free
         _check(lib.chemk_mech_create(C.byref(d), C.byref(h)))
         self.handle = h
         K, R, E = C.c_int32(), C.c_int32(), C.c_int32()
@@ -158,7 +161,7 @@ class Mechanism:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            lib.chemk_mech_free(h)
+            self._free(h)
             self.handle = None
 
 
@@ -167,6 +170,7 @@ class Context:
 
     def __init__(self, mech, device: int = 0):
         self.mech = mech if isinstance(mech, Mechanism) else Mechanism(mech)
+        self._free = lib.chemk_ctx_free   # bound here, as for the mechanism
         h = C.c_void_p()
         _check(lib.chemk_ctx_create(int(device), self.mech.handle, C.byref(h)))
         self.handle = h
@@ -175,7 +179,7 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
-            lib.chemk_ctx_free(self.handle)
+            self._free(self.handle)
             self.handle = None
 
     def __del__(self):
