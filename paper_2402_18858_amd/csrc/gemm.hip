@@ -18,9 +18,9 @@
 //    four workgroups per CU, which hide each other's slab loads); 4 slabs
 //    (the last layer) use two stages and prefetch;
 //  * everything else (training products, transposing loads, other K): two
-//    LDS stages, and a ring of registers holds the next slabs (buffer loads, which read zeros
-//    past an operand's edge, so no load sits behind a branch) and the tile is
-//    stored into LDS rows with a 16-byte pad.
+//    LDS stages, and a ring of registers holds the next slabs (buffer loads,
+//    which read zeros past an operand's edge, so no load sits behind a
+//    branch); the tile is stored into LDS rows with a 16-byte pad.
 // Forward BF16 outputs leave through LDS so that each store instruction
 // writes whole 128-byte row segments.  Workgroups are mapped to tiles so that
 // each of the 8 XCDs walks a contiguous range of row blocks (the A rows it
@@ -574,28 +574,28 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
         }
         epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, sA0 + wave * STG);
     } else {
-    load_slab(0, sA0, sB0);
-    load_slab(1, sA1, sB1);
-    asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+        load_slab(0, sA0, sB0);
+        load_slab(1, sA1, sB1);
+        asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
 #pragma unroll
-    for (int kt = 0; kt < KTC; ++kt) {
-        uint16_t *sa = (kt & 1) ? sA1 : sA0, *sb = (kt & 1) ? sB1 : sB0;
-        compute(sa, sb);
-        if (kt + 1 < KTC) {
-            // every wave has read this stage: it takes slab kt+2
-            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-            if (kt + 2 < KTC) {
-                load_slab(kt + 2, sa, sb);
-                asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");   // slab kt+1 landed everywhere
-            } else {
-                asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+        for (int kt = 0; kt < KTC; ++kt) {
+            uint16_t *sa = (kt & 1) ? sA1 : sA0, *sb = (kt & 1) ? sB1 : sB0;
+            compute(sa, sb);
+            if (kt + 1 < KTC) {
+                // every wave has read this stage: it takes slab kt+2
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                if (kt + 2 < KTC) {
+                    load_slab(kt + 2, sa, sb);
+                    asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");   // slab kt+1 landed everywhere
+                } else {
+                    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+                }
             }
         }
-    }
-    // the stages become the waves' output staging areas, one array each
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    uint16_t *stage = wave == 0 ? sA0 : wave == 1 ? sB0 : wave == 2 ? sA1 : sB1;
-    epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, stage);
+        // the stages become the waves' output staging areas, one array each
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        uint16_t *stage = wave == 0 ? sA0 : wave == 1 ? sB0 : wave == 2 ? sA1 : sB1;
+        epilogue<BM, BN, EPI>(g, acc, m0, n0, wm, wn, lane, stage);
     }
 }
 
