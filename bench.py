@@ -110,8 +110,9 @@ def main():
     ap.add_argument("--wpc", type=int, default=0, help="fixed DI waves per CU (with --bins)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the chemistry advance has no "
-              "cross-GPU step (cells are independent; see the sharding notes).", file=sys.stderr)
+        print("bench.py: runs on one GPU only. The chemistry advance has no cross-GPU step: "
+              "cells are independent, so each further GPU would advance its own share of them.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
