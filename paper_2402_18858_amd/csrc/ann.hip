@@ -465,13 +465,34 @@ template <typename Fn> static hipError_t with_km(int K, Fn &&f) {
     return hipErrorInvalidValue;
 }
 
+// Workgroups of ingest_kernel<KP> that are resident on the current device at
+// once (CUs x workgroups per CU), found once per device and lane group.  The
+// kernel's grid-stride loop then spreads the groups evenly over waves that
+// all start together, instead of leaving a last round of workgroups to run
+// nearly alone.
+template <int KP> static int ingest_resident_grid() {
+    static int cache[64] = {};   // per device; a race only writes the same value
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 2048;
+    if (cache[dev] > 0) return cache[dev];
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ingest_kernel<KP>, ING_THREADS, 0) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+        return 2048;
+    cache[dev] = cus * per_cu;
+    return cache[dev];
+}
+
 static hipError_t launch_ingest(int K, const double *tab, int n, const double *T, const double *p,
                                 const double *Y, uint16_t *X, int *route, double *h0, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     return with_km(K, [&](auto km) {
         constexpr int KP = decltype(km)::v;
         const int64_t groups = ((int64_t)n + 64 / KP - 1) / (64 / KP);
-        const int grid = (int)std::min<int64_t>(2048, (groups + ING_THREADS / 64 - 1) / (ING_THREADS / 64));
+        const int grid = (int)std::min<int64_t>(ingest_resident_grid<KP>(),
+                                                (groups + ING_THREADS / 64 - 1) / (ING_THREADS / 64));
         hipLaunchKernelGGL(ingest_kernel<KP>, dim3(grid), dim3(ING_THREADS), 0, s, K, n, tab, T, p, Y, X,
                            route, h0);
         return hipGetLastError();
