@@ -658,8 +658,12 @@ __global__ void pack_targets_kernel(int K, int n, const double *Y, const double 
     }
 }
 
-__global__ void fill_int_kernel(int *p, int v, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+// the step's counters in one launch: routed count, DI queue counter, stats[4]
+__global__ void reset_step_kernel(int *n_routed, int *counter, unsigned long long *stats) {
+    const int t = threadIdx.x;
+    if (t == 0) *n_routed = 0;
+    if (t == 1) *counter = 0;
+    if (t < 4) stats[t] = 0ull;
 }
 
 }  // namespace
@@ -886,9 +890,8 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     const int n = (int)x.n;
     PhaseTimer *tm = x.timer;
     // counters: stats, routed count, DI queue counter
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, x.n_routed, 0, 1);
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, x.counter, 0, 1);
-    if ((e = launch_zero_u64(x.stats, 4, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_step_kernel, dim3(1), dim3(64), 0, s, x.n_routed, x.counter, x.stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     // ingest
     if (tm) tm->begin(CHEMK_PHASE_INGEST, s);
     const double *ti, *tp;
