@@ -126,3 +126,45 @@ def test_post_state_clips_then_conserves():
     # clipped species stay at (numerically) zero after the projection
     clipped = Y + dY < 0
     assert np.abs(out[clipped]).max() < 1e-25
+
+
+# Standard normal CDF at 1 and 2.5, from printed tables of the normal
+# distribution (independent of any erf routine): Phi(1), Phi(-2.5) = 1 - Phi(2.5).
+PHI_1 = 0.8413447460685429
+PHI_M2_5 = 0.0062096653257762
+
+
+def _tiny_net():
+    """A 2-2-1 network whose weights and input are exact in bfloat16."""
+    W0 = np.array([[1.0, -1.0], [0.5, 2.0]])      # (in, out)
+    b0 = np.array([0.25, -0.5])
+    W1 = np.array([[2.0], [-1.0]])
+    b1 = np.array([0.125])
+    x = np.array([[1.0, -0.5]])
+    return [W0, W1], [b0, b1], x
+
+
+def test_forward_hand_computed_value():
+    """Worked by hand: z0 = x W0 + b0 = (1 - 0.25 + 0.25, -1 - 1 - 0.5) = (1, -2.5);
+    a0 = (1 Phi(1), -2.5 Phi(-2.5)); out = 2 a0[0] - a0[1] + 0.125."""
+    Ws, bs, x = _tiny_net()
+    out, cache = ann.forward(Ws, bs, x, quantize=False)
+    assert np.array_equal(cache["Z"][0], [[1.0, -2.5]])
+    a0 = np.array([PHI_1, -2.5 * PHI_M2_5])
+    assert np.allclose(cache["A"][1], a0, rtol=1e-14, atol=0)
+    want = 2.0 * a0[0] - a0[1] + 0.125
+    assert out[0, 0] == pytest.approx(want, rel=1e-14)
+    assert out[0, 0] == pytest.approx(1.823213655451526, rel=1e-14)
+
+
+def test_forward_hand_computed_value_bf16():
+    """The same network with the GPU's rounding points: the hidden activations
+    are rounded to bfloat16 (8 significant bits).  a0[0] = 0.84134.. lies
+    between 215/256 and 216/256 and rounds to 215/256 = 0.83984375;
+    a0[1] = -0.0155241.. lies between 254 and 255 steps of 2^-14 and rounds
+    to -254 * 2^-14 = -0.0155029296875.  Every other operand is exact, so
+    out = 2 * 0.83984375 + 0.0155029296875 + 0.125 = 1.8201904296875 exactly."""
+    Ws, bs, x = _tiny_net()
+    out, cache = ann.forward(Ws, bs, x, quantize=True)
+    assert np.array_equal(cache["A"][1], [[0.83984375, -0.0155029296875]])
+    assert out[0, 0] == 1.8201904296875
