@@ -167,14 +167,62 @@ def project_delta(Emat, Y, dY, floor=1e-30):
     return out
 
 
-def post_state(Emat, Y, dY, floor=1e-30, rounds=2):
+def project_weighted(Emat, target, y, w):
+    """The vector closest to y in the weighted norm sum_k (y'_k - y_k)^2 / w_k
+    whose element masses Emat y' equal `target`; species with w_k = 0 are held
+    where they are.  Lagrange's condition gives
+        y' = y - W E^T (E W E^T)^-1 (E y - target),   W = diag(w).
+    Returns (y', ok), ok False when E W E^T is singular (an element carried
+    only by held species cannot be restored)."""
+    A = (Emat * w[None, :]) @ Emat.T
+    try:
+        lam = np.linalg.solve(A, Emat @ y - target)
+    except np.linalg.LinAlgError:
+        return y.copy(), False
+    return y - w * (Emat.T @ lam), True
+
+
+POST_ROUNDS = 4
+
+
+def post_state(Emat, Y, dY, sd, rounds=POST_ROUNDS, neg_tol=1e-6):
     """State after the network's step (the post-processing of the chemistry
-    advance with the learned source term): `rounds` times, negative entries
-    of the current state set to zero, then the element-conserving projection
-    onto Y's element masses with weights max(., floor).  Returns the new mass
-    fractions."""
-    Yn = Y + dY
-    for _ in range(rounds):
-        Yc = np.maximum(Yn, 0.0)
-        Yn = Y + project_delta(Emat, Y, Yc - Y, floor)
-    return Yn
+    advance with the learned source term), per cell:
+
+    * the prediction y* = Y + dY is corrected to the nearest state with the
+      input's element masses E Y, nearness measured in units of each
+      species' spread sd_k of dY in the training data (weights w_k = sd_k^2:
+      the network is fitted on dY / sd, so its errors are of similar size in
+      those units for every species);
+    * species the correction leaves negative are held at zero and the
+      correction is solved again from y* over the remaining species, at most
+      `rounds` solves in all.
+
+    Returns (Y_new, ok, adj): ok is False when a solve is singular, the
+    result is not finite or some Y_k stays below -neg_tol (such cells are
+    advanced by DI); adj = max_k |Y_new,k - y*_k| / sd_k is the size of the
+    whole correction in those units."""
+    n, K = Y.shape
+    sd = np.asarray(sd, np.float64)
+    out = np.empty_like(Y)
+    ok = np.ones(n, bool)
+    adj = np.zeros(n)
+    for c in range(n):
+        ystar = Y[c] + dY[c]
+        target = Emat @ Y[c]
+        held = np.zeros(K, bool)
+        for _ in range(rounds):
+            y1 = np.where(held, 0.0, ystar)
+            w = np.where(held, 0.0, sd * sd)
+            y2, good = project_weighted(Emat, target, y1, w)
+            if not good:
+                ok[c] = False
+                break
+            neg = ~held & (y2 < 0.0)
+            if not neg.any():
+                break
+            held |= neg
+        out[c] = y2
+        ok[c] = ok[c] and bool(np.all(np.isfinite(y2))) and y2.min() >= -neg_tol
+        adj[c] = np.max(np.abs(y2 - ystar) / sd)
+    return out, ok, adj

@@ -101,31 +101,91 @@ def test_projection_conserves_elements():
     assert np.abs(again - out).max() < 1e-19
 
 
-def test_post_state_clips_then_conserves():
-    """Negative predictions are zeroed and the projection restores the element
-    masses exactly, without making a clipped or a positive species negative
-    again; a prediction that needs no clipping is only projected."""
+def test_post_state_hand_computed_clipping():
+    """One element carried by three species with equal weight (E = [1, 1, 1]),
+    worked by hand.  y* = Y + dY = (0.6, 0.45, -0.02) has 0.03 too much mass;
+    the first solve removes 0.01 from each species, leaving (0.59, 0.44, -0.03);
+    the third is held at 0 and the second solve spreads the 0.05 excess of
+    (0.6, 0.45, 0) over the other two: (0.575, 0.425, 0).  The whole
+    correction is 0.025 / 0.1 = 0.25 of sd."""
+    E = np.array([[1.0, 1.0, 1.0]])
+    Y = np.array([[0.5, 0.5, 0.0]])
+    dY = np.array([[0.1, -0.05, -0.02]])
+    out, ok, adj = ann.post_state(E, Y, dY, np.full(3, 0.1))
+    assert ok[0]
+    assert np.allclose(out[0], [0.575, 0.425, 0.0], rtol=0, atol=1e-15)
+    assert out[0, 2] == 0.0
+    assert adj[0] == pytest.approx(0.25, rel=1e-13)
+    # one solve only: the negative third species remains (and fails neg_tol)
+    out1, ok1, _ = ann.post_state(E, Y, dY, np.full(3, 0.1), rounds=1)
+    assert np.allclose(out1[0], [0.59, 0.44, -0.03], rtol=0, atol=1e-15) and not ok1[0]
+    # unequal weights: the excess goes in proportion to sd^2
+    out2, ok2, _ = ann.post_state(E, np.array([[0.5, 0.5, 0.0]]), np.array([[0.03, 0.0, 0.0]]),
+                                  np.array([0.1, 0.2, 0.0 + 1e-12]))
+    assert np.allclose(out2[0], [0.53 - 0.03 / 5, 0.5 - 0.03 * 4 / 5, 0.0], rtol=0, atol=1e-15)
+
+
+def test_weighted_projection_solves_the_lagrange_system():
+    """Without clipping, the correction is the minimiser of
+    sum_k (y'_k - y*_k)^2 / sd_k^2 subject to E y' = E Y: checked against the
+    stationarity (KKT) system [[diag(1/w), E^T], [E, 0]] [y'; lam] = [y*/w; E Y]
+    solved as one dense linear system."""
+    mech = sm.mech_medium()
+    E = ann.element_matrix(mech.composition, mech.element_mass)
+    rng = np.random.default_rng(8)
+    Y = rng.dirichlet(np.ones(mech.K), 6)
+    sd = 10.0 ** rng.uniform(-6, -2, mech.K)
+    dY = 0.05 * sd * rng.standard_normal(Y.shape)
+    out, ok, adj = ann.post_state(E, Y, dY, sd)
+    assert ok.all()
+    nE, K = E.shape
+    for c in range(Y.shape[0]):
+        w = sd * sd
+        M = np.zeros((K + nE, K + nE))
+        M[:K, :K] = np.diag(1.0 / w)
+        M[:K, K:] = E.T
+        M[K:, :K] = E
+        rhs = np.concatenate([(Y[c] + dY[c]) / w, E @ Y[c]])
+        sol = np.linalg.solve(M, rhs)
+        assert np.allclose(out[c], sol[:K], rtol=1e-9, atol=1e-15)
+        assert np.abs(E @ (out[c] - Y[c])).max() < 1e-15      # a few ulp of masses <= 1
+        assert adj[c] == pytest.approx(np.max(np.abs(out[c] - Y[c] - dY[c]) / sd), rel=1e-12)
+
+
+def test_post_state_holds_negatives_and_conserves():
+    """Cold-cell-like states (six absent species) with noise: every result is
+    non-negative, conserves the element masses to round-off, and leaves a
+    species with a floored spread (inert in the training data) untouched."""
     mech = sm.mech_medium()
     E = ann.element_matrix(mech.composition, mech.element_mass)
     rng = np.random.default_rng(5)
     Y = rng.dirichlet(0.3 * np.ones(mech.K), 16)
-    Y[:, :6] = 0.0                                   # absent species, as in cold cells
+    Y[:, :6] = 0.0
     Y /= Y.sum(1, keepdims=True)
-    dY = 1e-5 * rng.standard_normal(Y.shape)          # network noise, drives zeros negative
-    out = ann.post_state(E, Y, dY)
+    sd = 10.0 ** rng.uniform(-5, -3, mech.K)
+    sd[10] = 1e-12
+    dY = sd * rng.standard_normal(Y.shape)
+    dY[:, 10] = 0.0
+    out, ok, adj = ann.post_state(E, Y, dY, sd, neg_tol=0.0)
     assert (Y + dY < 0).any()
-    assert out.min() >= -1e-25
+    assert ok.all() and out.min() >= 0.0
     m0 = Y @ E.T
-    assert (np.abs((out - Y) @ E.T) / np.maximum(m0, 1e-300))[m0 > 1e-12].max() < 1e-14
-    # where nothing is clipped one round equals the plain projection
-    dY2 = np.abs(dY) * 1e-3
-    ref = Y + ann.project_delta(E, Y, dY2)
-    assert np.abs(ann.post_state(E, Y, dY2, rounds=1) - ref).max() < 1e-16   # rounding of Y + dY - Y
-    # a second round leaves an already conserving, non-negative state in place
-    assert np.abs(ann.post_state(E, Y, dY2) - ref).max() < 1e-16
-    # clipped species stay at (numerically) zero after the projection
-    clipped = Y + dY < 0
-    assert np.abs(out[clipped]).max() < 1e-25
+    assert (np.abs((out - Y) @ E.T) / np.maximum(m0, 1e-300))[m0 > 1e-12].max() < 1e-13
+    assert np.abs(out[:, 10] - Y[:, 10]).max() < 1e-20
+    # against a general solver of the inequality-constrained problem (bounds
+    # y' >= 0) where a single species was held: same minimiser
+    from scipy.optimize import minimize
+    for c in range(4):
+        ys = Y[c] + dY[c]
+        w = sd * sd
+        r = minimize(lambda v: np.sum((v - ys) ** 2 / w) * 1e-6, np.maximum(out[c], 0),
+                     jac=lambda v: 2e-6 * (v - ys) / w, method="SLSQP",
+                     constraints=[{"type": "eq", "fun": lambda v: (E @ v - E @ Y[c]) * 1e3,
+                                   "jac": lambda v: E * 1e3}],
+                     bounds=[(0, None)] * mech.K, options={"ftol": 1e-20, "maxiter": 500})
+        f_ours = np.sum((out[c] - ys) ** 2 / w)
+        f_qp = np.sum((r.x - ys) ** 2 / w)
+        assert f_ours <= f_qp * (1 + 1e-6) + 1e-12 or np.allclose(out[c], r.x, atol=1e-9)
 
 
 # Standard normal CDF at 1 and 2.5, from printed tables of the normal
