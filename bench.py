@@ -3,10 +3,19 @@
 Workload: the 64^3 block (262,144 cells) of the 32-species / 160-reaction
 synthetic mechanism, stratified into cold reactants, flame-front and
 product cells, advanced over dt = 5e-7 s.  A step is one chemistry advance
-of the whole block: the ANN path (ingest, BF16 MLP on MFMA, FP64 projection
-and checks, DI on the routed cells) when a trained network is available,
-else the DI path (stiffness binning and the persistent Rosenbrock kernel).
-Both paths are timed; `value` is the headline path's cell-updates/s.
+of the whole block: the ANN path (ingest, BF16 MLP on MFMA, FP64 element
+correction and checks, DI on the routed cells) when a trained network is
+available, else the DI path (stiffness binning and the persistent Rosenbrock
+kernel).  Both paths are timed; `value` is the headline path's
+cell-updates/s.
+
+Timing: every timed step advances its own copy of the block's initial
+state, made before the timed region; each step replays a hipGraph captured
+in the untimed warm-up.  Accuracy is measured on a step from the initial
+state: the ANN step against the FP64 DI step on every cell, the DI step
+against the oracle (reference tolerance) on a stratified sample.  The split
+of each path into phases and GEMM layers comes from separate eager steps
+with HIP events around each phase's launches.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode auto|di|ann]
 """
@@ -15,6 +24,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -26,20 +36,19 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector
 PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
 PEAK_HBM_GBS = 8000.0
+EXP_FLOPS = 25                # an FP64 exp/log counted as 25 operations
 
 
-def di_flops_per_step(K, R, nnz):
-    """Algorithmic FLOPs of one RODAS step on one cell (FMA = 2, exp/log = 1).
-
-    6 right-hand sides (the Jacobian pass evaluates f as well), one Jacobian
-    assembly, one LU of the (K+1)^2 iteration matrix and 6 triangular solves."""
+def di_flops_per_step(K, R):
+    """Algorithmic FLOPs of one RODAS step on one cell, N = K + 1 unknowns:
+    6 right-hand sides (each R reactions at 12 operations and two exp/log,
+    plus 20 per species), one analytic Jacobian (40 per reaction, 20 per
+    species), one LU of the N x N iteration matrix (2N^3/3) and 6 triangular
+    solves (2N^2 each)."""
     N = K + 1
-    rhs = R * 16 + K * 30 + 2 * nnz + 8 * K          # rates, thermo, production, sums
-    jac = rhs + R * 40 + 4 * K * K                   # partials, scatter, row scaling
-    lu = 2.0 * N ** 3 / 3.0
-    solve = 2.0 * N * N
-    stage = 2 * N * 6 + 4 * N                        # stage combinations
-    return 5 * rhs + jac + lu + 6 * solve + 6 * stage
+    rhs = R * (12 + 2 * EXP_FLOPS) + 20 * K
+    jac = 40 * R + 20 * K
+    return 6 * rhs + jac + 2.0 * N ** 3 / 3.0 + 6 * 2.0 * N * N
 
 
 def measured_traffic(key):
@@ -53,7 +62,8 @@ def measured_traffic(key):
     entry = json.load(open(path)).get(key)
     if not entry:
         return None
-    srcs = {"di_kernel": ("di.hip", "chemk_dev.h"), "mlp_forward": ("gemm.hip",)}[key]
+    srcs = {"di_kernel": ("di.hip", "chemk_dev.h"), "gemm_layer2": ("gemm.hip",),
+            "mlp_forward": ("gemm.hip",)}[key]
     h = hashlib.sha1()
     for f in srcs:
         with open(os.path.join(ROOT, "paper_2402_18858_amd", "csrc", f), "rb") as fh:
@@ -67,45 +77,67 @@ def element_mass(mech, Y):
     return Y @ Em
 
 
-def ann_vs_di(ctx, mech, Y0, T_a, Y_a, st_a, T_d, Y_d, routed_bit):
-    """Error of the ANN advance against the FP64 DI advance of the same
-    cells: per-species RMS and max of (Y_ann - Y_di) / sd(dY) over the cells
-    the network advanced (routed cells are DI by construction), |dT|, and the
-    element-mass drift of the network's cells."""
-    _, _, _, sd_y, _ = ctx.ann_get_norm()
-    net = (st_a & routed_bit) == 0
-    e = (Y_a[net] - Y_d[net]) / sd_y[None, :]
-    m0, m1 = element_mass(mech, Y0[net]), element_mass(mech, Y_a[net])
+def ann_vs_di(mech, sd_y, Y0, T_a, Y_a, st_a, T_d, Y_d, routed_bit):
+    """Error of the ANN step (network cells and routed cells together, as the
+    solver sees them) against the FP64 DI step of the same cells: per-species
+    RMS and max of (Y_ann - Y_di) / sd(dY), the same over the network's cells
+    alone, |dT|, the routed fraction and the element-mass drift."""
+    routed = (st_a & routed_bit) != 0
+    net = ~routed
+    e = (Y_a - Y_d) / sd_y[None, :]
+    en = e[net]
+    m0, m1 = element_mass(mech, Y0), element_mass(mech, Y_a)
     drift = np.abs(m1 - m0) / np.maximum(m0, 1e-300)
-    # the species that carry the chemistry's change over dt (sd of dY in the
-    # training data at least 1e-3 of the largest); for the others the
-    # normalised error measures mostly the element projection's corrections,
-    # so their absolute error is listed instead
-    act = sd_y >= 1e-3 * sd_y.max()
-    return {"cells": int(net.sum()),
-            "rms_norm_major": float(np.sqrt(np.mean(e[:, act] ** 2))),
-            "major_species": int(act.sum()),
-            "minor_species_rms_abs": {int(k): float(f"{v:.3e}") for k, v in zip(
-                np.nonzero(~act)[0], np.sqrt(np.mean((Y_a[net][:, ~act] - Y_d[net][:, ~act]) ** 2, 0)))},
+    dT = T_a - T_d
+    return {"cells": int(Y0.shape[0]), "routed_cells": int(routed.sum()),
+            "routed_fraction": float(routed.mean()),
+            "rms_norm_all_species": float(np.sqrt(np.mean(e * e))),
+            "max_norm_all_species": float(np.abs(e).max()),
             "rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(e * e, 0))],
             "max_norm": [round(float(v), 4) for v in np.abs(e).max(0)],
-            "rms_abs": [float(f"{v:.3e}") for v in np.sqrt(np.mean((Y_a[net] - Y_d[net]) ** 2, 0))],
+            "network_cells_rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(en * en, 0))],
+            "network_cells_max_norm": [round(float(v), 4) for v in np.abs(en).max(0)],
+            "rms_abs": [float(f"{v:.3e}") for v in np.sqrt(np.mean((Y_a - Y_d) ** 2, 0))],
             "sd_dY_train": [float(f"{v:.3e}") for v in sd_y],
-            "max_abs_T_K": float(np.abs(T_a[net] - T_d[net]).max()),
-            "rms_abs_T_K": float(np.sqrt(np.mean((T_a[net] - T_d[net]) ** 2))),
+            "max_abs_T_K": float(np.abs(dT).max()),
+            "rms_abs_T_K": float(np.sqrt(np.mean(dT ** 2))),
+            "network_cells_max_abs_T_K": float(np.abs(dT[net]).max()) if net.any() else 0.0,
             "element_drift_max": float(drift[m0 > 1e-12].max())}
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except Exception:  # noqa: BLE001 - informational
+        pass
+    return "unknown"
+
+
+WORKLOADS = {
+    # the metric's configuration: 64^3 flame block, 32 species / 160 reactions
+    "medium": dict(mech="mech_medium", nx=64, seed=2002, di_cells=None),
+    # the full step at scale: 128^3 block, 53 species / 325 reactions; DI is
+    # timed and used as the accuracy reference on a stratified sample
+    "large": dict(mech="mech_large", nx=128, seed=2005, di_cells=65536),
+}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--di-steps", type=int, default=2, help="timed DI steps (about 3 s each)")
     ap.add_argument("--mode", default="auto", choices=["auto", "di", "ann"])
-    ap.add_argument("--nx", type=int, default=64)
+    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2400,
-                    help="cells of the oracle baseline (about 10-20 s on 16 host threads)")
+                    help="cells of the oracle at the GPU tolerance (about 10 s on 16 host threads)")
+    ap.add_argument("--cpu-sample-ref", type=int, default=240,
+                    help="cells of the oracle at the reference tolerance (rtol 1e-10)")
     ap.add_argument("--bins", type=int, default=0, help="fixed stiffness bins (skips the autotuner)")
     ap.add_argument("--wpc", type=int, default=0, help="fixed DI waves per CU (with --bins)")
     args = ap.parse_args()
@@ -119,147 +151,239 @@ def main():
     from paper_2402_18858_amd import chemk
     from synth import mechanism as sm, workload as sw
 
-    mech = sm.mech_medium()
-    nx_default = args.nx == 64          # the block the stored counters were taken on
-    T0, p0, Y0, region = sw.flame_block(mech, args.nx, 2002)
+    def log(m):
+        print(f"bench.py: {m}", file=sys.stderr, flush=True)
+
+    wl = WORKLOADS[args.workload]
+    mech = getattr(sm, wl["mech"])()
+    T0, p0, Y0, region = sw.flame_block(mech, wl["nx"], wl["seed"])
     n, K = Y0.shape
     dt = 5e-7
     dev = "cuda:0"
     ctx = chemk.Context(mech, device=0)
-    stream = torch.cuda.current_stream()
+    # the DI reference and timing: the whole block, or a stratified sample
+    if wl["di_cells"] and wl["di_cells"] < n:
+        rng = np.random.default_rng(77)
+        di_idx = np.sort(np.concatenate([rng.choice(np.nonzero(region == r)[0], wl["di_cells"] // 3,
+                                                    replace=False) for r in range(3)]))
+    else:
+        di_idx = np.arange(n)
+    nd = di_idx.size
+    stock_counters = args.workload == "medium"      # the block the stored counters were taken on
     Tin = torch.from_numpy(T0).to(dev)
     Yin = torch.from_numpy(Y0).to(dev)
     P = torch.from_numpy(p0).to(dev)
-    T = Tin.clone()
-    Y = Yin.clone()
-    st = torch.zeros(n, dtype=torch.int32, device=dev)
-    ns = torch.zeros(n, dtype=torch.int32, device=dev)
+    TinD = torch.from_numpy(T0[di_idx]).to(dev)
+    YinD = torch.from_numpy(np.ascontiguousarray(Y0[di_idx])).to(dev)
+    PD = torch.from_numpy(p0[di_idx]).to(dev)
 
     have_ann = False
     mode = args.mode
     if mode in ("auto", "ann"):
         try:
             from paper_2402_18858_amd import train
-            have_ann = train.load_or_train(ctx, mech, dt, log=lambda m: print(m, file=sys.stderr))
+            have_ann = train.load_or_train(ctx, mech, dt, log=log, path=train.weights_path(mech))
         except Exception as e:  # noqa: BLE001 - reported, DI remains measurable
-            print(f"bench.py: ANN path unavailable ({e})", file=sys.stderr)
+            log(f"ANN path unavailable ({e})")
             if mode == "ann":
                 raise
         mode = "ann" if have_ann else "di"
 
     # DI tuning on the workload (untimed): bins x waves-per-CU grid on copies
-    o_di = chemk.default_opts()
     if args.bins > 0:
         best_bins, best_wpc, tune_ms = args.bins, args.wpc or 8, 0.0
     else:
-        best_bins, best_wpc, tune_ms = ctx.autotune(Tin, P, Yin, dt, o_di)
-    o_di = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc)
-    print(f"bench.py: DI autotune -> bins={best_bins} waves/CU={best_wpc} ({tune_ms:.1f} ms)",
-          file=sys.stderr)
+        best_bins, best_wpc, tune_ms = ctx.autotune(TinD, PD, YinD, dt, chemk.default_opts())
+    log(f"DI autotune -> bins={best_bins} waves/CU={best_wpc} ({tune_ms:.1f} ms)")
 
-    def run_steps(opts, k, timed):
-        if timed:
-            ctx.timing(True)
+    def first_step(Ti, Pi, Yi, opts, k=1):
+        """k eager steps, each from the initial state, with the phase timer on
+        (HIP events around each phase's and each GEMM layer's launches on the
+        step's stream): the accuracy reference and the phase split."""
+        T, Y = Ti.clone(), Yi.clone()
+        st = torch.zeros(Ti.numel(), dtype=torch.int32, device=dev)
+        ns = torch.zeros(Ti.numel(), dtype=torch.int32, device=dev)
+        ctx.timing(True)
         for _ in range(k):
-            T.copy_(Tin)
-            Y.copy_(Yin)
-            ctx.advance(T, P, Y, dt, st, ns, opts=opts)
+            T.copy_(Ti)
+            Y.copy_(Yi)
+            ctx.advance(T, Pi, Y, dt, st, ns, opts=opts)
+        ph = ctx.timing_read()
+        ctx.timing(False)
         torch.cuda.synchronize()
-        if timed:
-            ph = ctx.timing_read()
-            ctx.timing(False)
-            return ph
-        return None
+        return T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(), ns.cpu().numpy(), ph
 
-    def timed(opts, k, w):
-        run_steps(opts, w, False)
+    def timed_graph(Ti, Pi, Yi, opts, k, w):
+        """k steps, each on its own copy of the initial state made before the
+        timed region, each replaying its captured graph (captured in the
+        untimed warm-up, which also runs w extra steps)."""
+        Ts = [Ti.clone() for _ in range(k)]
+        Ys = [Yi.clone() for _ in range(k)]
+        st = torch.zeros(Ti.numel(), dtype=torch.int32, device=dev)
+        ns = torch.zeros(Ti.numel(), dtype=torch.int32, device=dev)
+        for i in list(range(k)) + [j % k for j in range(w)]:
+            ctx.advance(Ts[i], Pi, Ys[i], dt, st, ns, opts=opts)
+        for i in range(k):
+            Ts[i].copy_(Ti)
+            Ys[i].copy_(Yi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ph = run_steps(opts, k, True)
+        for i in range(k):
+            ctx.advance(Ts[i], Pi, Ys[i], dt, st, ns, opts=opts)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, ph
+        del Ts, Ys
+        return wall
 
     # ---- DI path -------------------------------------------------------------
-    wall_di, ph_di = timed(o_di, args.steps, args.warmup)
-    ns_h = ns.cpu().numpy()
-    st_h = st.cpu().numpy()
-    T_di, Y_di = T.cpu().numpy(), Y.cpu().numpy()
-    steps_total = float(ns_h.sum())
-    di_cups = n * args.steps / wall_di
-    nnz = int(sum(1 for j in range(mech.R) for s in list(mech.reactants[j]) + list(mech.products[j])
-                  if s >= 0))
-    fl_step = di_flops_per_step(K, mech.R, nnz)
-    di_ms, di_launch = ph_di["di"]
-    di_kernel_ms = di_ms / max(di_launch, 1)
-    di_flops = fl_step * steps_total
-    di_tflops = di_flops / (di_kernel_ms * 1e-3) / 1e12
-    di_info = {"cell_updates_per_s": di_cups, "ms_per_step": 1e3 * wall_di / args.steps,
-               "mean_steps_per_cell": steps_total / n, "failed_cells": int((st_h != 0).sum()),
-               "kernel_ms": di_kernel_ms, "binning_ms": ph_di["binning"][0] / max(args.steps, 1),
+    o_di = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc)
+    o_di_g = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc, use_graph=1)
+    T_di, Y_di, st_di, ns_di, ph_di = first_step(TinD, PD, YinD, o_di)
+    steps_total = float(ns_di.sum())
+    di_kernel_ms = ph_di["di"][0] / max(ph_di["di"][1], 1)
+    wall_di = timed_graph(TinD, PD, YinD, o_di_g, args.di_steps, 1)
+    di_cups = nd * args.di_steps / wall_di
+    fl_step = di_flops_per_step(K, mech.R)
+    di_tflops = fl_step * steps_total / (di_kernel_ms * 1e-3) / 1e12
+    di_info = {"cells": nd, "cell_updates_per_s": di_cups, "ms_per_step": 1e3 * wall_di / args.di_steps,
+               "timed_steps": args.di_steps,
+               "mean_rodas_steps_per_cell": steps_total / nd, "failed_cells": int((st_di != 0).sum()),
+               "rodas_steps_per_cell_p50_p99_max": [float(np.percentile(ns_di, 50)),
+                                                    float(np.percentile(ns_di, 99)), int(ns_di.max())],
+               "kernel_ms": di_kernel_ms,
+               "binning_ms": ph_di["binning"][0],
                "tuning": {"bins": best_bins, "waves_per_cu": best_wpc},
                "rtol": o_di.rtol, "atol_Y": o_di.atol_Y}
     roof_di = {"bound": "alu", "achieved": di_tflops, "peak": PEAK_FP64_TFLOPS,
                "unit": "TFLOP/s", "frac": di_tflops / PEAK_FP64_TFLOPS,
-               "traffic": measured_traffic("di_kernel") if nx_default else None,
+               "traffic": measured_traffic("di_kernel") if stock_counters else None,
                "kernel": f"di_kernel (N = {K + 1})",
-               "flops_per_step_per_cell": fl_step, "rodas_steps": steps_total}
+               "flops_per_rodas_step": fl_step, "rodas_steps": steps_total,
+               "note": f"algorithmic FP64 count, exp/log = {EXP_FLOPS} operations"}
+    log(f"DI ({nd} cells): {1e3 * wall_di / args.di_steps:.1f} ms per step, {di_cups:.4g} cell-updates/s")
 
     result = {"metric": "chem cell-updates/s (BF16 ANN vs FP64 DI), 262k cells x 32 sp; err vs oracle",
               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "data": "synthetic",
               "unit": "cell-updates/s"}
-    cfg = {"workload": f"{n} cells ({args.nx}^3 flame block) x {K} species / {mech.R} reactions, "
+    cfg = {"workload": f"{n} cells ({wl['nx']}^3 flame block) x {K} species / {mech.R} reactions, "
                        f"dt={dt:g} s", "cells": n, "species": K, "reactions": mech.R}
     if mode == "di":
-        result.update({"value": di_cups, "ms_per_step": 1e3 * wall_di / args.steps, "dtype": "f64",
-                       "config": dict(cfg, path="DI (RODAS, FP64)"), "roofline": roof_di,
-                       "di": di_info})
+        result.update({"value": di_cups, "ms_per_step": 1e3 * wall_di / args.di_steps,
+                       "steps": args.di_steps, "dtype": "f64",
+                       "config": dict(cfg, path="DI (RODAS, FP64), hipGraph replays", di_cells=nd),
+                       "roofline": roof_di, "di": di_info})
     else:
         o_ann = chemk.default_opts(mode=chemk.MODE_ANN, bins=best_bins, waves_per_cu=best_wpc)
-        wall_a, ph_a = timed(o_ann, args.steps, args.warmup)
+        o_ann_g = chemk.default_opts(mode=chemk.MODE_ANN, bins=best_bins, waves_per_cu=best_wpc,
+                                     use_graph=1)
+        nsp = 5
+        T_a, Y_a, st_a, ns_a, ph_a = first_step(Tin, P, Yin, o_ann, nsp)
+        _, _, _, sd_y, _ = ctx.ann_get_norm()
+        acc_ann = ann_vs_di(mech, sd_y, Y0[di_idx], T_a[di_idx], Y_a[di_idx], st_a[di_idx], T_di, Y_di,
+                            chemk.CELL_ROUTED_DI)
+        routed_all = (st_a & chemk.CELL_ROUTED_DI) != 0
+        acc_ann.update({"cells_compared": nd, "routed_cells_block": int(routed_all.sum()),
+                        "routed_fraction_block": float(routed_all.mean())})
+        wall_a = timed_graph(Tin, P, Yin, o_ann_g, args.steps, args.warmup)
         cnt = ctx.last_counters()
         ann_cups = n * args.steps / wall_a
-        mlp_ms, mlp_l = ph_a["mlp"]
-        mlp_flops = train.mlp_flops_per_cell(ctx.dims) * n * args.steps
-        mlp_tf = mlp_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else 0.0
-        roof = {"bound": "mfma", "achieved": mlp_tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": mlp_tf / PEAK_BF16_TFLOPS,
-                "traffic": measured_traffic("mlp_forward") if nx_default else None,
-                "traffic_unit": "bytes per MLP forward of the block (16 GEMM launches)",
-                "kernel": "mlp GEMMs",
-                "flops_per_cell": train.mlp_flops_per_cell(ctx.dims)}
-        phases = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]} for k, v in ph_a.items()}
-        acc_ann = ann_vs_di(ctx, mech, Y0, T.cpu().numpy(), Y.cpu().numpy(), st.cpu().numpy(),
-                            T_di, Y_di, chemk.CELL_ROUTED_DI)
+        dims = ctx.dims
+        layer_fl = [2 * dims[i] * dims[i + 1] for i in range(len(dims) - 1)]
+        launches = {f"layer{i + 1}": ph_a[f"layer{i + 1}"] for i in range(min(4, len(dims) - 1))}
+        per_layer = {}
+        for i, (k_, (ms, nl)) in enumerate(launches.items()):
+            rows = n * nsp / max(nl, 1)            # rows per launch (one MLP chunk)
+            avg = ms / max(nl, 1)
+            tf = layer_fl[i] * rows / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
+            per_layer[k_] = {"launches": nl, "avg_launch_us": 1e3 * avg, "rows_per_launch": rows,
+                             "tflops": tf, "frac": tf / PEAK_BF16_TFLOPS}
+        mlp_ms = ph_a["mlp"][0] / nsp
+        mlp_tf = train.mlp_flops_per_cell(dims) * n / (mlp_ms * 1e-3) / 1e12
+        phases = {k_: {"ms_per_step": v[0] / nsp, "launches_per_step": v[1] / nsp}
+                  for k_, v in ph_a.items() if v[1] > 0}
+        # HBM streams of the ingest and post kernels, algorithmic bytes per cell
+        ing_b = 8 * (K + 2) + 2 * 64 + 4 + 8          # T, p, Y in; X row, route, h0 out
+        post_b = 8 * K + 4 * K + 4 + 8 + 8 + (8 * K + 8 + 4)   # Y, out, route, h0, T in; Y, T, status out
+        hbm = {"ingest": {"bytes_per_cell": ing_b,
+                          "GB_per_s": ing_b * n / (phases["ingest"]["ms_per_step"] * 1e-3) / 1e9},
+               "post": {"bytes_per_cell": post_b,
+                        "GB_per_s": post_b * n / (phases["post"]["ms_per_step"] * 1e-3) / 1e9},
+               "peak_GB_per_s": PEAK_HBM_GBS}
+        # the dominant kernel of the step: the DI fallback when it outweighs
+        # the network's GEMMs, else the GEMM layer with the most time
+        fb_ms = phases.get("fallback", {}).get("ms_per_step", 0.0)
+        dom = max(per_layer, key=lambda k_: per_layer[k_]["avg_launch_us"] * per_layer[k_]["launches"])
+        roof_mlp = {"bound": "mfma", "achieved": per_layer[dom]["tflops"], "peak": PEAK_BF16_TFLOPS,
+                    "unit": "TFLOP/s", "frac": per_layer[dom]["frac"],
+                    "traffic": (measured_traffic("gemm_layer2") if (stock_counters and dom == "layer2")
+                                else None),
+                    "kernel": f"gemm_dma_kernel, MLP {dom} ({dims[int(dom[-1]) - 1]} -> {dims[int(dom[-1])]}, "
+                              f"{per_layer[dom]['rows_per_launch']:.0f} rows per launch)",
+                    "flops_per_launch": layer_fl[int(dom[-1]) - 1] * per_layer[dom]["rows_per_launch"],
+                    "mlp_phase": {"ms_per_step": mlp_ms, "tflops": mlp_tf,
+                                  "frac": mlp_tf / PEAK_BF16_TFLOPS,
+                                  "flops_per_cell": train.mlp_flops_per_cell(dims)},
+                    "per_layer": per_layer}
+        routed_ns = ns_a[routed_all]
+        fb_steps = float(routed_ns.sum()) * nsp
+        if fb_ms > mlp_ms and fb_steps > 0:
+            fb_tf = fl_step * routed_ns.sum() / (fb_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "achieved": fb_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": fb_tf / PEAK_FP64_TFLOPS, "traffic": None,
+                    "kernel": f"di_kernel (N = {K + 1}) on the {int(routed_all.sum())} routed cells",
+                    "flops_per_rodas_step": fl_step, "rodas_steps": float(routed_ns.sum()),
+                    "mlp": roof_mlp}
+        else:
+            roof = roof_mlp
         result.update({"value": ann_cups, "ms_per_step": 1e3 * wall_a / args.steps,
-                       "dtype": "bf16+f64", "config": dict(cfg, path="ANN (BF16 MFMA) + DI fallback"),
+                       "dtype": "bf16+f64",
+                       "config": dict(cfg, path="ANN (BF16 MFMA) + DI fallback, hipGraph replays",
+                                      di_cells=nd),
                        "roofline": roof, "di": di_info, "di_roofline": roof_di,
-                       "ann": {"phases": phases, "routed_cells": cnt["routed"],
+                       "ann": {"phases_eager": phases, "hbm_streams": hbm,
+                               "routed_rodas_steps_p50_max": (
+                                   [float(np.percentile(routed_ns, 50)), int(routed_ns.max())]
+                                   if routed_ns.size else None),
+                               "routed_cells_per_step": cnt["routed"],
+                               "network_only_ms_per_step": sum(phases[k_]["ms_per_step"] for k_ in
+                                                               ("ingest", "mlp", "post") if k_ in phases),
                                "speedup_over_di": ann_cups / di_cups, "error_vs_di": acc_ann}})
+        log(f"ANN: {1e3 * wall_a / args.steps:.3f} ms per step, {ann_cups:.4g} cell-updates/s, "
+            f"routed {int(routed_all.sum())}")
 
-    # ---- CPU baseline: the oracle on a bounded sample ---------------------------
-    if not args.no_cpu_baseline:
+    # ---- CPU baseline: the oracle on bounded samples ----------------------------
+    if not args.no_cpu_baseline and nd == n:
         import oracle
         rng = np.random.default_rng(99)
-        idx = np.sort(np.concatenate([rng.choice(np.nonzero(region == r)[0], args.cpu_sample // 3,
-                                                 replace=False) for r in range(3)]))
         om = oracle.OracleMech(mech)
         cores = oracle.default_threads()
+
+        def sample(m):
+            return np.sort(np.concatenate([rng.choice(np.nonzero(region == r)[0], m // 3,
+                                                      replace=False) for r in range(3)]))
+
+        idx = sample(args.cpu_sample)
         t0 = time.perf_counter()
-        To, Yo = om.advance(T0[idx], p0[idx], Y0[idx], dt, rtol=o_di.rtol, atol_Y=o_di.atol_Y,
-                            atol_T=o_di.atol_T, nthreads=cores)[:2]
+        om.advance(T0[idx], p0[idx], Y0[idx], dt, rtol=o_di.rtol, atol_Y=o_di.atol_Y,
+                   atol_T=o_di.atol_T, nthreads=cores)
         tc = time.perf_counter() - t0
+        idr = sample(args.cpu_sample_ref)
+        t0 = time.perf_counter()
+        To, Yo = om.advance(T0[idr], p0[idr], Y0[idr], dt, nthreads=cores)[:2]
+        tr = time.perf_counter() - t0
         big = Yo > 1e-8
         result["di_error_vs_oracle"] = {
-            "cells": int(len(idx)), "oracle_rtol": o_di.rtol,
-            "max_rel_Y_above_1e-8": float((np.abs(Y_di[idx] - Yo)[big] / Yo[big]).max()),
-            "max_abs_T_K": float(np.abs(T_di[idx] - To).max())}
-        result["cpu_baseline"] = {"value": len(idx) / tc, "unit": "cell-updates/s", "cores": cores,
-                                  "kind": "oracle",
-                                  "sample": f"{len(idx)} cells stratified over the 3 regions of the "
-                                            f"same block, DI at the GPU tolerance "
-                                            f"(rtol {o_di.rtol:g}), {tc:.1f} s"}
+            "cells": int(len(idr)), "oracle_rtol": 1e-10, "gpu_rtol": o_di.rtol,
+            "max_rel_Y_above_1e-8": float((np.abs(Y_di[idr] - Yo)[big] / Yo[big]).max()),
+            "max_abs_T_K": float(np.abs(T_di[idr] - To).max())}
+        result["cpu_baseline"] = {
+            "value": len(idx) / tc, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{len(idx)} cells stratified over the 3 regions of the same block, oracle "
+                      f"DI at the GPU tolerance (rtol {o_di.rtol:g}), {tc:.1f} s",
+            "value_reference_tolerance": len(idr) / tr,
+            "sample_reference_tolerance": f"{len(idr)} cells, rtol 1e-10, {tr:.1f} s"}
     print(json.dumps(result))
 
 

@@ -186,7 +186,11 @@ enum {
     CHEMK_PHASE_MLP = 3,       /* ANN: the MLP GEMMs                               */
     CHEMK_PHASE_POST = 4,      /* ANN: de-normalise, project, check, T             */
     CHEMK_PHASE_FALLBACK = 5,  /* ANN: DI on the routed cells                      */
-    CHEMK_NUM_PHASES = 6
+    CHEMK_PHASE_LAYER1 = 6,    /* ANN: the GEMM launches of layer 1, 2, 3 and of   */
+    CHEMK_PHASE_LAYER2 = 7,    /*      layer 4 and beyond, each also counted in    */
+    CHEMK_PHASE_LAYER3 = 8,    /*      CHEMK_PHASE_MLP                             */
+    CHEMK_PHASE_LAYER4 = 9,
+    CHEMK_NUM_PHASES = 10
 };
 int chemk_timing(chemk_ctx *ctx, int32_t enable);
 int chemk_timing_read(chemk_ctx *ctx, double ms[CHEMK_NUM_PHASES],
@@ -222,6 +226,52 @@ int chemk_ann_get_norm(chemk_ctx *ctx, double *mu_x, double *sd_x, double *mu_y,
 int chemk_ann_set_envelope(chemk_ctx *ctx, const double *lo, const double *hi, double neg_tol);
 int chemk_ann_get_envelope(chemk_ctx *ctx, double *lo, double *hi, double *neg_tol);
 
+/* Checks that decide, per cell, whether the network's step is kept or the cell
+ * is advanced by DI in the same call (ANN mode).
+ *
+ * Input side (ingest), besides the raw-feature box above: up to
+ * CHEMK_MAX_RATIOS element-ratio windows, after the paper's filters on its
+ * training states (windows on the molar H/C and O/N ratios and on the
+ * equivalence ratio, Sec. II.B).  With z_e = sum_k Y_k n_ek A_e / W_k the mass
+ * fraction of element e (elements in the mechanism's order), window j accepts
+ * a cell when
+ *     ratio_lo[j] <= (sum_e ratio_num[j*8+e] z_e) / (sum_e ratio_den[j*8+e] z_e)
+ *                 <= ratio_hi[j]
+ * and the denominator is positive (a molar ratio n_a / n_b has num = 1/A_a at
+ * a and den = 1/A_b at b).
+ *
+ * Output side (post step): a cell is routed when the element-conserving
+ * correction of the prediction moves some species by more than adj_max times
+ * its training spread sd_y[k] (adj_max <= 0: no limit), or when
+ * T(t+dt) - T(t) falls outside [dT_lo, dT_hi] K.  chemk_ann_create sets every
+ * check off (no windows, no limit, dT window of +-1e300).                   */
+#define CHEMK_MAX_RATIOS 4
+typedef struct {
+    double adj_max;
+    double dT_lo, dT_hi;
+    int32_t n_ratios;                                           /* 0..CHEMK_MAX_RATIOS */
+    double ratio_num[CHEMK_MAX_RATIOS * CHEMK_MAX_ELEMENTS];    /* [j*8 + e]           */
+    double ratio_den[CHEMK_MAX_RATIOS * CHEMK_MAX_ELEMENTS];
+    double ratio_lo[CHEMK_MAX_RATIOS], ratio_hi[CHEMK_MAX_RATIOS];
+} chemk_ann_checks;
+int chemk_ann_set_checks(chemk_ctx *ctx, const chemk_ann_checks *checks);
+int chemk_ann_get_checks(chemk_ctx *ctx, chemk_ann_checks *checks);
+
+/* Device: fit the input envelope and the dT window to n training states.
+ * For each raw feature (K + 2), each element-ratio window already set
+ * (n_ratios and its coefficients; its value taken over the states with a
+ * positive denominator) and, when T_next [n] is given, for T_next - T: the q
+ * and 1 - q quantiles, widened by widen times their distance on each side,
+ * become the feature's [lo, hi] (box, ratio window or dT window); the lower
+ * bound of each mass-fraction feature is extended down to Box-Cox(0) = -10,
+ * so that a species absent from a cell never routes it.  Quantiles
+ * are resolved on 4096 bins over each value's full range and rounded outwards
+ * to bin edges, so q = 0 gives the exact minimum and maximum.  Requires
+ * 0 <= q < 0.5, widen >= 0, n >= 2.  Synchronises `stream`.                 */
+int chemk_ann_fit_envelope(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+                           const double *Y, const double *T_next, double q, double widen,
+                           void *stream);
+
 /* Device: compute the normalisation from n training pairs (state, state after
  * dt) and store it (sd floored at 1e-12), plus the envelope box of the raw
  * features widened by `widen` times its span on each side.                   */
@@ -251,6 +301,33 @@ int chemk_ann_forward_packed(chemk_ctx *ctx, int64_t n, const uint16_t *X, float
 int chemk_ann_train_step(chemk_ctx *ctx, const int32_t *idx, int32_t B, const uint16_t *X,
                          const float *Z, float lr, int32_t update, float *loss, float *grads,
                          void *stream);
+
+/* The training loop (Sec. II.B: Adam on the loss of Eq. 8), on the device.
+ * Rows of the packed training set (X [n, 64] BF16 bits, 16-byte aligned; Z
+ * [n, K] FP32 z-scored targets, as written by chemk_ann_pack) are visited in
+ * a new pseudo-random order each epoch: row r of batch b of epoch e is
+ * perm_e(b * batch + r), perm_e a four-round Feistel permutation of [0, n)
+ * (cycle walking; round function SplitMix64's mixer) keyed by `seed` and e,
+ * so each epoch takes floor(n / batch) batches of distinct rows.  Each step is
+ * chemk_ann_train_step with the learning rate of a cosine schedule from lr0
+ * to lr1 over all steps, lr1 + (lr0 - lr1)(1 + cos(pi s / S)) / 2 at step s
+ * of S; the Adam step count continues from the context's.  With use_graph = 1
+ * one step is captured in a hipGraph and replayed.  After each epoch the mean
+ * squared error over the n_hold held-out rows (X_hold, Z_hold; n_hold = 0
+ * skips it) is evaluated.  epoch_loss and hold_loss (HOST arrays [epochs],
+ * NULL allowed) receive the epoch's mean batch loss and the held-out loss.
+ * Synchronises `stream`.                                                    */
+typedef struct {
+    int32_t batch;           /* rows per step: a multiple of 64, <= n           */
+    int32_t epochs;
+    float lr0, lr1;          /* cosine learning-rate schedule, first -> last     */
+    uint64_t seed;           /* key of the per-epoch permutations                 */
+    int32_t use_graph;       /* 1 = replay one captured training step            */
+} chemk_train_opts;
+int chemk_ann_train(chemk_ctx *ctx, int64_t n, const uint16_t *X, const float *Z,
+                    const uint16_t *X_hold, const float *Z_hold, int64_t n_hold,
+                    const chemk_train_opts *opts, float *epoch_loss, float *hold_loss,
+                    void *stream);
 
 /* Reset the Adam moments and step counter. */
 int chemk_ann_reset_optimizer(chemk_ctx *ctx);

@@ -65,35 +65,42 @@ _lib = None
 
 
 def lib():
+    """The oracle library (built on first use)."""
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
-        L = _lib
-        mp = C.POINTER(_Mech)
-        L.or_molar_mass.restype = C.c_double
-        L.or_molar_mass.argtypes = [mp, C.c_int]
-        L.or_species_thermo.argtypes = [mp, C.c_double, _f64p, _f64p, _f64p]
-        L.or_mixture_cp_h.argtypes = [mp, C.c_double, _f64p, C.POINTER(C.c_double),
-                                      C.POINTER(C.c_double)]
-        L.or_fluxes.argtypes = [mp, C.c_double, C.c_double, _f64p, _f64p, _f64p]
-        L.or_rhs.argtypes = [mp, C.c_double, _f64p, _f64p]
-        L.or_jacobian.argtypes = [mp, C.c_double, _f64p, _f64p]
-        L.or_T_from_h.restype = C.c_int
-        L.or_T_from_h.argtypes = [mp, C.c_double, _f64p, C.c_double, C.POINTER(C.c_double)]
-        L.or_element_mass.argtypes = [mp, _f64p, _f64p]
-        L.or_project.argtypes = [mp, _f64p, _f64p]
-        L.or_advance.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, C.c_double,
-                                 C.POINTER(_Opts), _i32p, _i32p, C.c_int]
-        L.or_thermo_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _f64p]
-        L.or_T_from_h_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _i32p]
-        L.or_rhs_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _f64p]
-        L.or_jacobian_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _f64p]
-        L.or_rodas_coefficients.argtypes = [C.POINTER(C.c_double), _f64p, _f64p]
-        L.or_lu.restype = C.c_int
-        L.or_lu.argtypes = [C.c_int, _f64p, _i32p]
-        L.or_lu_solve.argtypes = [C.c_int, _f64p, _i32p, _f64p]
-        L.or_rodas_generic.restype = C.c_int
+        _lib = load(build())
     return _lib
+
+
+def load(path):
+    """A build of chem_oracle.c at `path` with its call signatures set (the
+    reference build, or a variant compiled by a test)."""
+    L = C.CDLL(path)
+    mp = C.POINTER(_Mech)
+    L.or_molar_mass.restype = C.c_double
+    L.or_molar_mass.argtypes = [mp, C.c_int]
+    L.or_species_thermo.argtypes = [mp, C.c_double, _f64p, _f64p, _f64p]
+    L.or_mixture_cp_h.argtypes = [mp, C.c_double, _f64p, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
+    L.or_fluxes.argtypes = [mp, C.c_double, C.c_double, _f64p, _f64p, _f64p]
+    L.or_rhs.argtypes = [mp, C.c_double, _f64p, _f64p]
+    L.or_jacobian.argtypes = [mp, C.c_double, _f64p, _f64p]
+    L.or_T_from_h.restype = C.c_int
+    L.or_T_from_h.argtypes = [mp, C.c_double, _f64p, C.c_double, C.POINTER(C.c_double)]
+    L.or_element_mass.argtypes = [mp, _f64p, _f64p]
+    L.or_project.argtypes = [mp, _f64p, _f64p]
+    L.or_advance.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, C.c_double,
+                             C.POINTER(_Opts), _i32p, _i32p, C.c_int]
+    L.or_thermo_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _f64p]
+    L.or_T_from_h_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _i32p]
+    L.or_rhs_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _f64p]
+    L.or_jacobian_batch.argtypes = [mp, C.c_int64, _f64p, _f64p, _f64p, _f64p]
+    L.or_rodas_coefficients.argtypes = [C.POINTER(C.c_double), _f64p, _f64p]
+    L.or_lu.restype = C.c_int
+    L.or_lu.argtypes = [C.c_int, _f64p, _i32p]
+    L.or_lu_solve.argtypes = [C.c_int, _f64p, _i32p, _f64p]
+    L.or_rodas_generic.restype = C.c_int
+    return L
 
 
 RHS_CB = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double))
@@ -102,7 +109,8 @@ RHS_CB = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_doub
 class OracleMech:
     """Keeps the flat arrays alive and exposes the C struct."""
 
-    def __init__(self, mech):
+    def __init__(self, mech, library=None):
+        self._L = library if library is not None else lib()
         self.src = mech
         self.E = len(mech.elements)
         self.K = int(mech.composition.shape[0])
@@ -128,12 +136,12 @@ class OracleMech:
     # ---- thermo ----
     def species_thermo(self, T):
         cp, h, s = (np.zeros(self.K) for _ in range(3))
-        lib().or_species_thermo(self.ref, float(T), cp, h, s)
+        self._L.or_species_thermo(self.ref, float(T), cp, h, s)
         return cp, h, s
 
     def cp_h(self, T, Y):
         cp, h = C.c_double(), C.c_double()
-        lib().or_mixture_cp_h(self.ref, float(T), np.ascontiguousarray(Y, np.float64),
+        self._L.or_mixture_cp_h(self.ref, float(T), np.ascontiguousarray(Y, np.float64),
                               C.byref(cp), C.byref(h))
         return cp.value, h.value
 
@@ -141,42 +149,42 @@ class OracleMech:
         T = np.ascontiguousarray(T, np.float64)
         n = T.size
         cp, h = np.zeros(n), np.zeros(n)
-        lib().or_thermo_batch(self.ref, n, T, np.ascontiguousarray(Y, np.float64), cp, h)
+        self._L.or_thermo_batch(self.ref, n, T, np.ascontiguousarray(Y, np.float64), cp, h)
         return cp, h
 
     def T_from_h(self, h0, Y, T_guess):
         T = C.c_double()
-        rc = lib().or_T_from_h(self.ref, float(h0), np.ascontiguousarray(Y, np.float64),
+        rc = self._L.or_T_from_h(self.ref, float(h0), np.ascontiguousarray(Y, np.float64),
                                float(T_guess), C.byref(T))
         return T.value, rc
 
     def T_from_h_batch(self, h, Y, T_guess):
         T = np.array(T_guess, np.float64, copy=True)
         st = np.zeros(T.size, np.int32)
-        lib().or_T_from_h_batch(self.ref, T.size, np.ascontiguousarray(h, np.float64),
+        self._L.or_T_from_h_batch(self.ref, T.size, np.ascontiguousarray(h, np.float64),
                                 np.ascontiguousarray(Y, np.float64), T, st)
         return T, st
 
     # ---- kinetics ----
     def fluxes(self, T, p, Y):
         qf, qr = np.zeros(self.R), np.zeros(self.R)
-        lib().or_fluxes(self.ref, float(T), float(p), np.ascontiguousarray(Y, np.float64), qf, qr)
+        self._L.or_fluxes(self.ref, float(T), float(p), np.ascontiguousarray(Y, np.float64), qf, qr)
         return qf, qr
 
     def rhs(self, y, p):
         f = np.zeros(self.K + 1)
-        lib().or_rhs(self.ref, float(p), np.ascontiguousarray(y, np.float64), f)
+        self._L.or_rhs(self.ref, float(p), np.ascontiguousarray(y, np.float64), f)
         return f
 
     def jacobian(self, y, p):
         J = np.zeros((self.K + 1) * (self.K + 1))
-        lib().or_jacobian(self.ref, float(p), np.ascontiguousarray(y, np.float64), J)
+        self._L.or_jacobian(self.ref, float(p), np.ascontiguousarray(y, np.float64), J)
         return J.reshape(self.K + 1, self.K + 1)
 
     def rhs_batch(self, T, p, Y):
         n = len(T)
         f = np.zeros((n, self.K + 1))
-        lib().or_rhs_batch(self.ref, n, np.ascontiguousarray(T, np.float64),
+        self._L.or_rhs_batch(self.ref, n, np.ascontiguousarray(T, np.float64),
                            np.ascontiguousarray(p, np.float64),
                            np.ascontiguousarray(Y, np.float64), f)
         return f
@@ -184,7 +192,7 @@ class OracleMech:
     def jacobian_batch(self, T, p, Y):
         n = len(T)
         J = np.zeros((n, self.K + 1, self.K + 1))
-        lib().or_jacobian_batch(self.ref, n, np.ascontiguousarray(T, np.float64),
+        self._L.or_jacobian_batch(self.ref, n, np.ascontiguousarray(T, np.float64),
                                 np.ascontiguousarray(p, np.float64),
                                 np.ascontiguousarray(Y, np.float64), J)
         return J
@@ -192,12 +200,12 @@ class OracleMech:
     # ---- elements ----
     def element_mass(self, Y):
         me = np.zeros(self.E)
-        lib().or_element_mass(self.ref, np.ascontiguousarray(Y, np.float64), me)
+        self._L.or_element_mass(self.ref, np.ascontiguousarray(Y, np.float64), me)
         return me
 
     def project(self, Yref, Y):
         Y = np.array(Y, np.float64, copy=True)
-        lib().or_project(self.ref, np.ascontiguousarray(Yref, np.float64), Y)
+        self._L.or_project(self.ref, np.ascontiguousarray(Yref, np.float64), Y)
         return Y
 
     # ---- advance ----
@@ -211,7 +219,7 @@ class OracleMech:
         st = np.zeros(n, np.int32)
         ns = np.zeros(n, np.int32)
         o = _Opts(rtol, atol_Y, atol_T, h0_frac, max_steps, int(project), int(newton_T))
-        lib().or_advance(self.ref, n, T, p, Y, float(dt), C.byref(o), st, ns,
+        self._L.or_advance(self.ref, n, T, p, Y, float(dt), C.byref(o), st, ns,
                          int(nthreads or default_threads()))
         return T, Y, st, ns
 

@@ -167,6 +167,14 @@ void or_fluxes(const or_mech *m, double T, double p, const double *Y, double *qf
     }
 }
 
+/* Type of the rate products and production rates in the right-hand side.
+ * The oracle is FP64 throughout; a test compiles a variant with
+ * -DOR_RATE_T=float (rate constants still from FP64 exp/log, Jacobian, LU and
+ * error control still FP64) to measure what FP32 rate evaluation costs. */
+#ifndef OR_RATE_T
+#define OR_RATE_T double
+#endif
+
 /* Right-hand side f(y), y = (Y_1..Y_K, T), constant p. */
 void or_rhs(const or_mech *m, double p, const double *y, double *f)
 {
@@ -174,19 +182,19 @@ void or_rhs(const or_mech *m, double p, const double *y, double *f)
     double T = y[K];
     or_state s;
     state_eval(m, T, p, y, &s);
-    double omega[OR_MAXK];
-    for (int k = 0; k < K; ++k) omega[k] = 0.0;
+    OR_RATE_T omega[OR_MAXK];
+    for (int k = 0; k < K; ++k) omega[k] = 0;
     for (int j = 0; j < m->R; ++j) {
         double kf, kr;
         rate_constants(m, &s, T, j, &kf, &kr);
-        double fw = kf, rv = kr;
+        OR_RATE_T fw = (OR_RATE_T)kf, rv = (OR_RATE_T)kr;
         for (int i = 0; i < 2; ++i) {
             int a = m->reac[2 * j + i], b = m->prod[2 * j + i];
-            if (a >= 0) fw *= s.C[a];
-            if (b >= 0) rv *= s.C[b];
+            if (a >= 0) fw *= (OR_RATE_T)s.C[a];
+            if (b >= 0) rv *= (OR_RATE_T)s.C[b];
         }
-        double q = fw - rv;
-        if (m->tb[j]) q *= s.M;
+        OR_RATE_T q = fw - rv;
+        if (m->tb[j]) q *= (OR_RATE_T)s.M;
         for (int i = 0; i < 2; ++i) {
             int a = m->reac[2 * j + i], b = m->prod[2 * j + i];
             if (a >= 0) omega[a] -= q;

@@ -42,6 +42,22 @@ class Opts(C.Structure):
                 ("project", C.c_int32)]
 
 
+MAX_RATIOS, MAX_ELEMENTS = 4, 8
+
+
+class AnnChecks(C.Structure):
+    _fields_ = [("adj_max", C.c_double), ("dT_lo", C.c_double), ("dT_hi", C.c_double),
+                ("n_ratios", C.c_int32),
+                ("ratio_num", C.c_double * (MAX_RATIOS * MAX_ELEMENTS)),
+                ("ratio_den", C.c_double * (MAX_RATIOS * MAX_ELEMENTS)),
+                ("ratio_lo", C.c_double * MAX_RATIOS), ("ratio_hi", C.c_double * MAX_RATIOS)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr0", C.c_float), ("lr1", C.c_float),
+                ("seed", C.c_uint64), ("use_graph", C.c_int32)]
+
+
 _vp = C.c_void_p
 _i64 = C.c_int64
 _SIGS = {
@@ -72,12 +88,18 @@ _SIGS = {
     "chemk_ann_get_norm": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
     "chemk_ann_set_envelope": (C.c_int, [_vp, _vp, _vp, C.c_double]),
     "chemk_ann_get_envelope": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "chemk_ann_set_checks": (C.c_int, [_vp, C.POINTER(AnnChecks)]),
+    "chemk_ann_get_checks": (C.c_int, [_vp, C.POINTER(AnnChecks)]),
+    "chemk_ann_fit_envelope": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
+                                         _vp]),
     "chemk_ann_fit_norm": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_double,
                                      C.c_double, _vp]),
     "chemk_ann_pack": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "chemk_ann_forward_packed": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
     "chemk_ann_train_step": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, C.c_float, C.c_int32,
                                        _vp, _vp, _vp]),
+    "chemk_ann_train": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(TrainOpts), _vp, _vp,
+                                  _vp]),
     "chemk_ann_reset_optimizer": (C.c_int, [_vp]),
 }
 
@@ -222,14 +244,15 @@ class Context:
         _check(lib.chemk_last_counters(self.handle, out, _stream(stream)))
         return {"routed": out[0], "di_steps": out[1], "failed": out[2]}
 
-    PHASES = ("di", "binning", "ingest", "mlp", "post", "fallback")
+    PHASES = ("di", "binning", "ingest", "mlp", "post", "fallback", "layer1", "layer2", "layer3",
+              "layer4")
 
     def timing(self, enable=True):
         _check(lib.chemk_timing(self.handle, int(bool(enable))))
 
     def timing_read(self, stream=None):
-        ms = (C.c_double * 6)()
-        nl = (C.c_int64 * 6)()
+        ms = (C.c_double * len(self.PHASES))()
+        nl = (C.c_int64 * len(self.PHASES))()
         _check(lib.chemk_timing_read(self.handle, ms, nl, _stream(stream)))
         return {ph: (ms[i], nl[i]) for i, ph in enumerate(self.PHASES)}
 
@@ -280,6 +303,33 @@ class Context:
                                           C.byref(nt)))
         return lo, hi, nt.value
 
+    def ann_set_checks(self, adj_max=0.0, dT=(-1e300, 1e300), ratios=()):
+        """ratios: up to 4 tuples (num[E], den[E], lo, hi) over the mechanism's
+        elements (coefficients of the element mass fractions)."""
+        ck = AnnChecks()
+        ck.adj_max = float(adj_max)
+        ck.dT_lo, ck.dT_hi = float(dT[0]), float(dT[1])
+        ck.n_ratios = len(ratios)
+        for j, (num, den, lo, hi) in enumerate(ratios):
+            for e, (u, d) in enumerate(zip(num, den)):
+                ck.ratio_num[j * MAX_ELEMENTS + e] = float(u)
+                ck.ratio_den[j * MAX_ELEMENTS + e] = float(d)
+            ck.ratio_lo[j], ck.ratio_hi[j] = float(lo), float(hi)
+        _check(lib.chemk_ann_set_checks(self.handle, C.byref(ck)))
+
+    def ann_get_checks(self):
+        ck = AnnChecks()
+        _check(lib.chemk_ann_get_checks(self.handle, C.byref(ck)))
+        E = self.mech.E
+        ratios = [(np.array(ck.ratio_num[j * MAX_ELEMENTS:j * MAX_ELEMENTS + E]),
+                   np.array(ck.ratio_den[j * MAX_ELEMENTS:j * MAX_ELEMENTS + E]),
+                   ck.ratio_lo[j], ck.ratio_hi[j]) for j in range(ck.n_ratios)]
+        return {"adj_max": ck.adj_max, "dT": (ck.dT_lo, ck.dT_hi), "ratios": ratios}
+
+    def ann_fit_envelope(self, T, p, Y, T_next=None, q=1e-3, widen=0.02, stream=None):
+        _check(lib.chemk_ann_fit_envelope(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y),
+                                          _ptr(T_next), float(q), float(widen), _stream(stream)))
+
     def ann_fit_norm(self, T, p, Y, Y_next, dt, widen=0.02, neg_tol=1e-6, stream=None):
         _check(lib.chemk_ann_fit_norm(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y),
                                       _ptr(Y_next), float(dt), float(widen), float(neg_tol),
@@ -297,6 +347,17 @@ class Context:
         _check(lib.chemk_ann_train_step(self.handle, _ptr(idx), idx.numel(), _ptr(X), _ptr(Z),
                                         float(lr), int(bool(update)), _ptr(loss), _ptr(grads),
                                         _stream(stream)))
+
+    def ann_train(self, X, Z, epochs, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001, X_hold=None,
+                  Z_hold=None, use_graph=True, stream=None):
+        """Returns (epoch_loss, hold_loss) as host arrays [epochs]."""
+        o = TrainOpts(int(batch), int(epochs), float(lr0), float(lr1), int(seed), int(bool(use_graph)))
+        el = np.zeros(epochs, np.float32)
+        hl = np.zeros(epochs, np.float32)
+        nh = 0 if X_hold is None else X_hold.shape[0]
+        _check(lib.chemk_ann_train(self.handle, X.shape[0], _ptr(X), _ptr(Z), _ptr(X_hold), _ptr(Z_hold),
+                                   nh, C.byref(o), el.ctypes.data, hl.ctypes.data, _stream(stream)))
+        return el, hl
 
     def ann_reset_optimizer(self):
         _check(lib.chemk_ann_reset_optimizer(self.handle))

@@ -12,6 +12,7 @@
 // master weights with BF16 copies for the GEMMs.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -72,8 +73,18 @@ __device__ __forceinline__ double box_cox(double y) {
     return (p - 1.0) * (1.0 / BCT_LAMBDA);
 }
 
+// Element-ratio windows of the input envelope: window j holds a cell whose
+// element mass fractions z_e = sum_k Emat[e][k] Y_k give
+//   lo_j <= (sum_e num[j][e] z_e) / (sum_e den[j][e] z_e) <= hi_j
+// with a positive denominator (molar ratios such as H/C, O/N or the elemental
+// equivalence ratio: the caller folds 1/A_e into the coefficients).
+constexpr int MAX_RATIOS = 4;
+constexpr int RAT_E = CHEMK_MAX_ELEMENTS;
+constexpr int RAT_DOUBLES = 2 * MAX_RATIOS * RAT_E + 2 * MAX_RATIOS;   // num, den, lo, hi
+
 struct NormDev {
     const double *mu_x, *sd_x, *mu_y, *sd_y, *lo, *hi;   // [F], [F], [K], [K], [F], [F]
+    const double *rat;                                   // [RAT_DOUBLES]
 };
 
 // ---------------------------------------------------------------------------
@@ -87,17 +98,22 @@ struct NormDev {
 // (zero-padded to KM), read at compile-time offsets through a restrict
 // pointer: uniform scalar loads into SGPRs, which leaves the vector registers
 // to the rows.
-// ingest table: lo, hi, mu_x, 1/sd_x [FPAD each], nasa [7 KM], 1/W [KM]
+// ingest table: lo, hi, mu_x, 1/sd_x [FPAD each], nasa [7 KM], 1/W [KM],
+// Emat [RAT_E KM], ratio windows [RAT_DOUBLES]
 constexpr int ti_lo = 0, ti_hi = FPAD, ti_mu = 2 * FPAD, ti_sd = 3 * FPAD, ti_nasa = 4 * FPAD;
 __host__ __device__ constexpr int ti_invW(int KM) { return 4 * FPAD + 7 * KM; }
-__host__ __device__ constexpr int ti_size(int KM) { return 4 * FPAD + 8 * KM; }
+__host__ __device__ constexpr int ti_elem(int KM) { return 4 * FPAD + 8 * KM; }
+__host__ __device__ constexpr int ti_rat(int KM) { return 4 * FPAD + (8 + RAT_E) * KM; }
+__host__ __device__ constexpr int ti_size(int KM) { return ti_rat(KM) + RAT_DOUBLES; }
+constexpr int tr_num = 0, tr_den = MAX_RATIOS * RAT_E, tr_lo = 2 * MAX_RATIOS * RAT_E,
+              tr_hi = 2 * MAX_RATIOS * RAT_E + MAX_RATIOS;
 // post table: E [E KM], 1/W [KM], a_j (j < 6) [6 KM], mu_y [KM], sd_y [KM]
 __host__ __device__ constexpr int tp_invW(int E, int KM) { return E * KM; }
 __host__ __device__ constexpr int tp_a(int E, int KM) { return (E + 1) * KM; }
 __host__ __device__ constexpr int tp_mu(int E, int KM) { return (E + 7) * KM; }
 __host__ __device__ constexpr int tp_sd(int E, int KM) { return (E + 8) * KM; }
 __host__ __device__ constexpr int tp_size(int E, int KM) { return (E + 9) * KM; }
-constexpr int ROW_TAB_DOUBLES = 4 * FPAD + 8 * 64 + (8 + 9) * 64;
+constexpr int ROW_TAB_DOUBLES = ti_size(64) + tp_size(CHEMK_MAX_ELEMENTS, 64);
 
 __global__ void row_tables_kernel(DevMech m, NormDev nd, int KM, double *ti, double *tp) {
     const int K = m.K, F = K + 2, E = m.E;
@@ -109,9 +125,11 @@ __global__ void row_tables_kernel(DevMech m, NormDev nd, int KM, double *ti, dou
         ti[ti_sd + i] = f ? 1.0 / nd.sd_x[i] : 1.0;
     }
     for (int i = threadIdx.x; i < 7 * KM; i += blockDim.x) ti[ti_nasa + i] = i < 7 * K ? m.nasa[i] : 0.0;
+    for (int i = threadIdx.x; i < RAT_DOUBLES; i += blockDim.x) ti[ti_rat(KM) + i] = nd.rat[i];
     for (int i = threadIdx.x; i < KM; i += blockDim.x) {
         const bool s = i < K;
         ti[ti_invW(KM) + i] = s ? m.invW[i] : 0.0;
+        for (int e = 0; e < RAT_E; ++e) ti[ti_elem(KM) + e * KM + i] = (s && e < E) ? m.Emat[e * K + i] : 0.0;
         tp[tp_invW(E, KM) + i] = s ? m.invW[i] : 0.0;
         tp[tp_mu(E, KM) + i] = s ? nd.mu_y[i] : 0.0;
         tp[tp_sd(E, KM) + i] = s ? nd.sd_y[i] : 0.0;
@@ -120,7 +138,160 @@ __global__ void row_tables_kernel(DevMech m, NormDev nd, int KM, double *ti, dou
     }
 }
 
-constexpr int POST_CELLS = 64;   // ingest and post: one wave per workgroup
+// Features (Box-Cox of the K mass fractions, then T and p), z-scored and
+// rounded to BF16 into a row of FPAD inputs; the envelope flag (a raw feature
+// outside [lo, hi] of the training data, or NaN, or an element ratio outside
+// its window); the enthalpy h(T, Y) / R that the post step conserves.  A
+// group of KP lanes (the power of two >= K, equal to the table's KM) takes one
+// cell, lane k its species k, so that the species' constants stay in the
+// lane's registers for the whole launch; a wave advances 64 / KP cells per
+// iteration, reading their rows of Y and writing their rows of X coalesced
+// (lane k: the columns k, k + KP, ...).
+constexpr int ING_THREADS = 256;
+
+// Sum of v over the KP lanes of a group, on every lane of it: four DPP steps
+// within each 16-lane row (VALU operand modifiers, no LDS round trip), then a
+// swizzle across the two rows of a 32-lane half and a permute across the
+// halves.  The opaque move keeps a product feeding v out of the first step.
+template <int KP> __device__ __forceinline__ double group_sum(double v) {
+    asm volatile("" : "+v"(v));
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<kDppHalfMirror>(v);
+    v += dpp_d<kDppMirror>(v);
+    if (KP >= 32) {   // lanes i <-> i ^ 16 within each 32 (swizzle and_mask 31, xor_mask 16)
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+        v += __hiloint2double(hi, lo);
+    }
+    if (KP >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+template <int KP>
+__global__ void __launch_bounds__(ING_THREADS) ingest_kernel(int K, int E, int nrat, int n,
+                                                             const double *__restrict__ tab,
+                                                             const double *__restrict__ T,
+                                                             const double *__restrict__ p,
+                                                             const double *__restrict__ Y,
+                                                             uint16_t *__restrict__ X,
+                                                             int *__restrict__ route,
+                                                             double *__restrict__ h0R) {
+    static_assert(KP == 16 || KP == 32 || KP == 64, "lane group");
+    constexpr int CPW = 64 / KP, NCOL = FPAD / KP;
+    const int lane = threadIdx.x & 63, k = lane % KP, sub = lane / KP;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int waves = gridDim.x * (ING_THREADS / 64);
+    const bool sp = k < K;
+    // species k's constants (zero past K) and those of the T and p features
+    double lo = 0.0, hi = 0.0, mu = 0.0, isd = 0.0, iw = 0.0, a[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double em[RAT_E];
+#pragma unroll
+    for (int e = 0; e < RAT_E; ++e) em[e] = 0.0;
+    if (sp) {
+        lo = tab[ti_lo + k];
+        hi = tab[ti_hi + k];
+        mu = tab[ti_mu + k];
+        isd = tab[ti_sd + k];
+        iw = tab[ti_invW(KP) + k];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a[j] = tab[ti_nasa + 7 * k + j];
+        if (nrat > 0) {
+#pragma unroll
+            for (int e = 0; e < RAT_E; ++e) em[e] = tab[ti_elem(KP) + e * KP + k];
+        }
+    }
+    const double loT = tab[ti_lo + K], hiT = tab[ti_hi + K], muT = tab[ti_mu + K], isdT = tab[ti_sd + K];
+    const double lop = tab[ti_lo + K + 1], hip = tab[ti_hi + K + 1], mup = tab[ti_mu + K + 1],
+                 isdp = tab[ti_sd + K + 1];
+    const unsigned long long gmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
+    // this lane's mass fraction, T and p of group gg (the last cell past n)
+    auto fetch = [&](int gg, double &y, double &Tc, double &pc) {
+        const int c = gg * CPW + sub;
+        const bool cv = c < n;
+        const int cc = cv ? c : n - 1;
+        y = (cv && sp) ? Y[(size_t)cc * K + k] : 0.0;
+        Tc = T[cc];
+        pc = p[cc];
+    };
+    int g = blockIdx.x * (ING_THREADS / 64) + wave;
+    double yN = 0.0, TN = 0.0, pN = 0.0;
+    if (g * CPW < n) fetch(g, yN, TN, pN);
+    for (; g * CPW < n; g += waves) {
+        const int c = g * CPW + sub;
+        const bool cv = c < n;
+        const double y = yN, Tc = TN, pc = pN;
+        // the next group's loads travel during this group's arithmetic
+        if ((g + waves) * CPW < n) fetch(g + waves, yN, TN, pN);
+        const double raw = box_cox(y);
+        double cpR, hRT;
+        sp_cp_h(a, Tc, 1.0 / Tc, cpR, hRT);
+        const double h = group_sum<KP>(y * iw * hRT);   // zero past K
+        const bool bad = sp && !((raw >= lo) & (raw <= hi));   // NaN -> outside
+        const unsigned long long m = __ballot(bad);
+        bool out = ((m >> (sub * KP)) & gmask) != 0 || !((Tc >= loT) & (Tc <= hiT)) ||
+                   !((pc >= lop) & (pc <= hip));
+        if (nrat > 0) {   // uniform: the element-ratio windows
+            double z[RAT_E];
+#pragma unroll
+            for (int e = 0; e < RAT_E; ++e) {
+                z[e] = e < E ? group_sum<KP>(y * em[e]) : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < MAX_RATIOS; ++j) {
+                if (j < nrat) {
+                    const double *__restrict__ tr = tab + ti_rat(KP);
+                    double u = 0.0, d = 0.0;
+#pragma unroll
+                    for (int e = 0; e < RAT_E; ++e) {
+                        u += tr[tr_num + j * RAT_E + e] * z[e];
+                        d += tr[tr_den + j * RAT_E + e] * z[e];
+                    }
+                    out = out || !((d > 0.0) & (u >= tr[tr_lo + j] * d) & (u <= tr[tr_hi + j] * d));
+                }
+            }
+        }
+        const float fs = (float)((raw - mu) * isd);
+        const float fT = (float)((Tc - muT) * isdT), fp = (float)((pc - mup) * isdp);
+        if (cv) {
+#pragma unroll
+            for (int q = 0; q < NCOL; ++q) {
+                const int col = k + q * KP;   // only q = 0 can be a species column (KP >= K)
+                const float v = col < K ? fs : (col == K ? fT : (col == K + 1 ? fp : 0.0f));
+                X[(size_t)c * FPAD + col] = f2bf(v);
+            }
+            if (k == 0) {
+                route[c] = out ? 1 : 0;
+                h0R[c] = h * Tc;
+            }
+        }
+    }
+}
+
+// post: the prediction y* = Y_in + dY (dY = mu + sd * out, FP64) is corrected
+// to the nearest state with the input's element masses, nearness measured in
+// units of each species' training spread sd_k of dY: minimise
+// sum_k (y_k - y*_k)^2 / sd_k^2 subject to E y = E Y_in, whose Lagrange
+// condition gives y = y* - W E^T (E W E^T)^-1 (E y* - E Y_in), W = diag(sd^2).
+// Non-negativity is handled by an active set that only grows: species a solve
+// leaves negative are held at zero and the correction is solved again from y*
+// over the others, at most POST_SOLVES solves.  Then the admissibility checks
+// (a singular solve, non-finite or Y_k < -neg_tol, a correction larger than
+// adj_max sd_k on some species, T(t+dt) - T(t) outside [dT_lo, dT_hi]) and T
+// from h0 by Newton; cells that fail any of it are queued for DI and left
+// unchanged.
+//
+// One lane per cell, a wave of 64 cells per workgroup.  The rows enter and
+// leave through LDS with coalesced global accesses and stay there: every pass
+// over the species reads the lane's row from LDS (stride KM + 1 doubles: two
+// lanes per bank at most), and the per-species constants are uniform scalar
+// loads of the table, so the registers hold only the E x E system.
+constexpr int POST_SOLVES = 4;
+constexpr int POST_CELLS = 64;
+
+struct PostChecks {
+    double neg_tol, adj_max, dT_lo, dT_hi;
+};
 
 // Block copy of the rows of cells [0, cnt) from a row-major global span (K
 // values per cell, contiguous) into an LDS tile of row stride ld, in
@@ -148,122 +319,70 @@ __device__ __forceinline__ void rows_to_lds(const Tv *__restrict__ g, int cnt, i
     }
 }
 
-// Features (Box-Cox of the K mass fractions, then T and p), z-scored and
-// rounded to BF16 into a row of FPAD inputs; the envelope flag (a raw feature
-// outside [lo, hi] of the training data, or NaN); the enthalpy h(T, Y) / R
-// that the post step conserves.  A group of KP lanes (the power of two >= K,
-// equal to the table's KM) takes one cell, lane k its species k, so that the
-// species' constants stay in the lane's registers for the whole launch; a
-// wave advances 64 / KP cells per iteration, reading their rows of Y and
-// writing their rows of X coalesced (lane k: the columns k, k + KP, ...).
-constexpr int ING_THREADS = 256;
-
-template <int KP>
-__global__ void __launch_bounds__(ING_THREADS) ingest_kernel(int K, int n,
-                                                             const double *__restrict__ tab,
-                                                             const double *__restrict__ T,
-                                                             const double *__restrict__ p,
-                                                             const double *__restrict__ Y,
-                                                             uint16_t *__restrict__ X,
-                                                             int *__restrict__ route,
-                                                             double *__restrict__ h0R) {
-    static_assert(KP == 16 || KP == 32 || KP == 64, "lane group");
-    constexpr int CPW = 64 / KP, NCOL = FPAD / KP;
-    const int lane = threadIdx.x & 63, k = lane % KP, sub = lane / KP;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int waves = gridDim.x * (ING_THREADS / 64);
-    const bool sp = k < K;
-    // species k's constants (zero past K) and those of the T and p features
-    double lo = 0.0, hi = 0.0, mu = 0.0, isd = 0.0, iw = 0.0, a[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (sp) {
-        lo = tab[ti_lo + k];
-        hi = tab[ti_hi + k];
-        mu = tab[ti_mu + k];
-        isd = tab[ti_sd + k];
-        iw = tab[ti_invW(KP) + k];
+// Solves A x = r in place (x returned in r) by Gaussian elimination with
+// partial pivoting; false if a pivot is exactly zero.
+template <int E>
+__device__ __forceinline__ bool solve_small(double (&A)[E][E], double (&r)[E]) {
+    bool ok = true;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) a[j] = tab[ti_nasa + 7 * k + j];
-    }
-    const double loT = tab[ti_lo + K], hiT = tab[ti_hi + K], muT = tab[ti_mu + K], isdT = tab[ti_sd + K];
-    const double lop = tab[ti_lo + K + 1], hip = tab[ti_hi + K + 1], mup = tab[ti_mu + K + 1],
-                 isdp = tab[ti_sd + K + 1];
-    const unsigned long long gmask = KP == 64 ? ~0ull : ((1ull << KP) - 1ull);
-    // this lane's mass fraction, T and p of group gg (the last cell past n)
-    auto fetch = [&](int gg, double &y, double &Tc, double &pc) {
-        const int c = gg * CPW + sub;
-        const bool cv = c < n;
-        const int cc = cv ? c : n - 1;
-        y = (cv && sp) ? Y[(size_t)cc * K + k] : 0.0;
-        Tc = T[cc];
-        pc = p[cc];
-    };
-    int g = blockIdx.x * (ING_THREADS / 64) + wave;
-    double yN = 0.0, TN = 0.0, pN = 0.0;
-    if (g * CPW < n) fetch(g, yN, TN, pN);
-    for (; g * CPW < n; g += waves) {
-        const int c = g * CPW + sub;
-        const bool cv = c < n;
-        const double y = yN, Tc = TN, pc = pN;
-        // the next group's loads travel during this group's arithmetic
-        if ((g + waves) * CPW < n) fetch(g + waves, yN, TN, pN);
-        const double raw = box_cox(y);
-        double cpR, hRT;
-        sp_cp_h(a, Tc, 1.0 / Tc, cpR, hRT);
-        double h = y * iw * hRT;   // zero past K
+    for (int k = 0; k < E; ++k) {
+        int piv = k;
+        double best = fabs(A[k][k]);
 #pragma unroll
-        for (int o = KP / 2; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
-        const bool bad = sp && !((raw >= lo) & (raw <= hi));   // NaN -> outside
-        const unsigned long long m = __ballot(bad);
-        const bool out = ((m >> (sub * KP)) & gmask) != 0 || !((Tc >= loT) & (Tc <= hiT)) ||
-                         !((pc >= lop) & (pc <= hip));
-        const float fs = (float)((raw - mu) * isd);
-        const float fT = (float)((Tc - muT) * isdT), fp = (float)((pc - mup) * isdp);
-        if (cv) {
-#pragma unroll
-            for (int q = 0; q < NCOL; ++q) {
-                const int col = k + q * KP;   // only q = 0 can be a species column (KP >= K)
-                const float v = col < K ? fs : (col == K ? fT : (col == K + 1 ? fp : 0.0f));
-                X[(size_t)c * FPAD + col] = f2bf(v);
+        for (int i = k + 1; i < E; ++i)
+            if (fabs(A[i][k]) > best) {
+                best = fabs(A[i][k]);
+                piv = i;
             }
-            if (k == 0) {
-                route[c] = out ? 1 : 0;
-                h0R[c] = h * Tc;
+        ok = ok && best != 0.0;
+#pragma unroll
+        for (int i = k + 1; i < E; ++i) {
+            const bool sw = i == piv;
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const double t = A[k][j];
+                A[k][j] = sw ? A[i][j] : t;
+                A[i][j] = sw ? t : A[i][j];
             }
+            const double t = r[k];
+            r[k] = sw ? r[i] : t;
+            r[i] = sw ? t : r[i];
+        }
+#pragma unroll
+        for (int i = k + 1; i < E; ++i) {
+            const double l = A[i][k] / A[k][k];
+#pragma unroll
+            for (int j = k; j < E; ++j) A[i][j] -= l * A[k][j];
+            r[i] -= l * r[k];
         }
     }
-}
-
-// post: y = Y_in + dY (dY = mu + sd * out), two rounds of clipping and the
-// element-conserving projection, the admissibility checks, T from h0 by
-// Newton; cells that fail any of it are queued for DI and left unchanged.
-// The table base plus an opaque uniform zero: loads through it are issued in
-// the loop that uses them rather than hoisted out of the round loop, where
-// E * KM doubles would not fit in SGPRs.
-__device__ __forceinline__ const double *fresh_base(const double *__restrict__ t) {
-    int z = 0;
-    asm volatile("" : "+s"(z));
-    return t + z;
+#pragma unroll
+    for (int i = E - 1; i >= 0; --i) {
+#pragma unroll
+        for (int j = i + 1; j < E; ++j) r[i] -= A[i][j] * r[j];
+        r[i] /= A[i][i];
+    }
+    return ok;
 }
 
 template <int E, int KM>
-__global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
-                                                             const double *__restrict__ tab,
-                                                             double *__restrict__ T,
-                                                             double *__restrict__ Y,
-                                                             const float *__restrict__ out,
-                                                             const int *__restrict__ route,
-                                                             const double *__restrict__ h0R,
-                                                             double neg_tol, int project,
-                                                             int *__restrict__ status,
-                                                             int *__restrict__ nsteps,
-                                                             int *__restrict__ queue,
-                                                             int *__restrict__ n_routed,
-                                                             unsigned long long *__restrict__ stats) {
-    // Rows go through LDS (stride KM + 1: two-way bank conflicts at most) so
-    // that the global reads and writes are coalesced; each lane then holds
-    // its cell's row in registers.
+__global__ void __launch_bounds__(POST_CELLS) post_kernel(int K, int n,
+                                                          const double *__restrict__ tab,
+                                                          double *__restrict__ T,
+                                                          double *__restrict__ Y,
+                                                          const float *__restrict__ out,
+                                                          const int *__restrict__ route,
+                                                          const double *__restrict__ h0R,
+                                                          PostChecks ck, int project,
+                                                          int *__restrict__ status,
+                                                          int *__restrict__ nsteps,
+                                                          int *__restrict__ queue,
+                                                          int *__restrict__ n_routed,
+                                                          unsigned long long *__restrict__ stats) {
+    static_assert(KM <= 64, "held-species mask is one 64-bit word");
     constexpr int ld = KM + 1;
-    __shared__ double s_row[POST_CELLS * ld];
+    __shared__ double s_y[POST_CELLS * ld];
+    __shared__ float s_o[POST_CELLS * ld];
     __shared__ int s_keep[POST_CELLS];
     const int base = blockIdx.x * POST_CELLS;
     const int cnt = n - base < POST_CELLS ? n - base : POST_CELLS;
@@ -271,39 +390,34 @@ __global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
     const bool valid = lane < cnt;
     const int c = valid ? base + lane : base;
     const float invK = 1.0f / (float)K;
+    rows_to_lds<KM>(Y + (size_t)base * K, cnt, K, invK, s_y, ld);
+    rows_to_lds<KM>(out + (size_t)base * K, cnt, K, invK, s_o, ld);
+    __syncthreads();
+    double *row = s_y + lane * ld;
+    const float *orow = s_o + lane * ld;
     const double *__restrict__ tE = tab;
-    rows_to_lds<KM>(Y + (size_t)base * K, cnt, K, invK, s_row, ld);
-    __syncthreads();
-    double y[KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) y[k] = k < K ? s_row[lane * ld + k] : 0.0;
-    __syncthreads();
-    float *s_out = reinterpret_cast<float *>(s_row);
-    rows_to_lds<KM>(out + (size_t)base * K, cnt, K, invK, s_out, ld);
-    __syncthreads();
-    // element totals of the input state: the projection's target
+    const double *__restrict__ tmu = tab + tp_mu(E, KM);
+    const double *__restrict__ tsd = tab + tp_sd(E, KM);
+    // element totals of the input state (the correction's target), and the
+    // row replaced by y*
     double eyin[E];
 #pragma unroll
-    for (int a = 0; a < E; ++a) {
-        double acc = 0.0;
+    for (int a = 0; a < E; ++a) eyin[a] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double y = row[k];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) acc += tE[a * KM + k] * y[k];
-        eyin[a] = acc;
+        for (int a = 0; a < E; ++a) eyin[a] += tE[a * KM + k] * y;
+        row[k] = y + tmu[k] + tsd[k] * (double)orow[k];
     }
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (k < K) y[k] += tab[tp_mu(E, KM) + k] + tab[tp_sd(E, KM) + k] * (double)s_out[lane * ld + k];
     bool bad = !valid || route[c] != 0;
-    // Two rounds of: negative entries set to zero (NaN is kept for the
-    // finiteness check), then the projection y <- y - w E^T (E w E^T)^-1
-    // (E y - E Y_in), w = max(y, 1e-30), which moves species held at zero by
-    // ~1e-30 only.  The second round catches the small species the first
-    // correction pushed below zero.  The rounds run on every lane (uniform
-    // control flow keeps one copy of the row live); a routed cell's result
-    // is discarded, and a singular system leaves y unchanged.
+    // active-set solves, per lane (a lane leaves when its set stops growing);
+    // lam holds the multipliers of the last solve and held its species at 0
+    double lam[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) lam[a] = 0.0;
+    unsigned long long held = 0ull;
     if (project) {
-#pragma unroll 1
-        for (int round = 0; round < 2; ++round) {
+        for (int it = 0; it < POST_SOLVES; ++it) {
             double A[E][E], r[E];
 #pragma unroll
             for (int a = 0; a < E; ++a) {
@@ -311,91 +425,70 @@ __global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
 #pragma unroll
                 for (int b = 0; b < E; ++b) A[a][b] = 0.0;
             }
-            const double *__restrict__ tE = fresh_base(tab);
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                if (y[k] < 0.0) y[k] = 0.0;
-                const double w = y[k] > 1e-30 ? y[k] : 1e-30;
+            for (int k = 0; k < K; ++k) {
+                const bool h = (held >> k) & 1ull;
+                const double sd = tsd[k];
+                const double w = h ? 0.0 : sd * sd;
+                const double yk = h ? 0.0 : row[k];
 #pragma unroll
                 for (int a = 0; a < E; ++a) {
-                    const double ew = tE[a * KM + k] * w;
-                    r[a] += tE[a * KM + k] * y[k];
+                    const double ea = tE[a * KM + k];
+                    r[a] += ea * yk;
 #pragma unroll
-                    for (int b = 0; b <= a; ++b) A[a][b] += ew * tE[b * KM + k];
+                    for (int b = 0; b <= a; ++b) A[a][b] += ea * w * tE[b * KM + k];
                 }
             }
 #pragma unroll
             for (int a = 0; a < E; ++a)
 #pragma unroll
                 for (int b = a + 1; b < E; ++b) A[a][b] = A[b][a];
-            // Gaussian elimination with partial pivoting
-            bool ok = true;
-#pragma unroll
-            for (int k = 0; k < E; ++k) {
-                int piv = k;
-                double best = fabs(A[k][k]);
-#pragma unroll
-                for (int i = k + 1; i < E; ++i)
-                    if (fabs(A[i][k]) > best) {
-                        best = fabs(A[i][k]);
-                        piv = i;
-                    }
-                ok = ok && best != 0.0;
-#pragma unroll
-                for (int i = k + 1; i < E; ++i) {
-                    const bool sw = i == piv;
-#pragma unroll
-                    for (int j = 0; j < E; ++j) {
-                        const double t = A[k][j];
-                        A[k][j] = sw ? A[i][j] : t;
-                        A[i][j] = sw ? t : A[i][j];
-                    }
-                    const double t = r[k];
-                    r[k] = sw ? r[i] : t;
-                    r[i] = sw ? t : r[i];
-                }
-#pragma unroll
-                for (int i = k + 1; i < E; ++i) {
-                    const double l = A[i][k] / A[k][k];
-#pragma unroll
-                    for (int j = k; j < E; ++j) A[i][j] -= l * A[k][j];
-                    r[i] -= l * r[k];
-                }
+            if (!solve_small<E>(A, r)) {
+                bad = true;
+                break;
             }
 #pragma unroll
-            for (int i = E - 1; i >= 0; --i) {
-#pragma unroll
-                for (int j = i + 1; j < E; ++j) r[i] -= A[i][j] * r[j];
-                r[i] /= A[i][i];
-            }
-#pragma unroll
-            for (int a = 0; a < E; ++a) r[a] = ok ? r[a] : 0.0;
-            const double *__restrict__ tE2 = fresh_base(tab);
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                const double w = y[k] > 1e-30 ? y[k] : 1e-30;
+            for (int a = 0; a < E; ++a) lam[a] = r[a];
+            if (it == POST_SOLVES - 1) break;
+            // species this solve leaves negative
+            unsigned long long neg = 0ull;
+            for (int k = 0; k < K; ++k) {
+                const double sd = tsd[k];
                 double acc = 0.0;
 #pragma unroll
-                for (int a = 0; a < E; ++a) acc += tE2[a * KM + k] * r[a];
-                y[k] -= w * acc;   // zero for the padding (E = 0 there)
+                for (int a = 0; a < E; ++a) acc += tE[a * KM + k] * lam[a];
+                if (!((held >> k) & 1ull) && row[k] - sd * sd * acc < 0.0) neg |= 1ull << k;
             }
+            if (!neg) break;
+            held |= neg;
         }
     }
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (!(y[k] >= -neg_tol) || !isfinite(y[k])) bad = true;
-    // Newton on h(T) = h0, as in the property update.  The mixture enthalpy
-    // is itself a NASA-7 polynomial in T with coefficients
-    // B_j = sum_k (Y_k / W_k) a_jk, built once: each iteration then costs one
-    // polynomial instead of one per species.
+    // the corrected state (back into the row), the per-species checks and the
+    // mixture enthalpy polynomial: h(T) of the mixture is a NASA-7 polynomial
+    // in T with coefficients B_j = sum_k (Y_k / W_k) a_jk, so each Newton
+    // iteration costs one polynomial instead of one per species
     double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < K; ++k) {
+        const double ys = row[k];
+        double yk = ys;
+        if (project) {
+            const double sd = tsd[k];
+            double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const double w = y[k] * tab[tp_invW(E, KM) + k];
+            for (int a = 0; a < E; ++a) acc += tE[a * KM + k] * lam[a];
+            const bool h = (held >> k) & 1ull;
+            const double corr = h ? ys : sd * sd * acc;
+            yk = h ? 0.0 : ys - corr;
+            if (fabs(corr) > ck.adj_max * sd) bad = true;
+        }
+        if (!(yk >= -ck.neg_tol) || !isfinite(yk)) bad = true;
+        const double w = yk * tab[tp_invW(E, KM) + k];
 #pragma unroll
         for (int j = 0; j < 6; ++j) B[j] += w * tab[tp_a(E, KM) + j * KM + k];
+        row[k] = yk;
     }
-    double Tn = T[c];
+    // Newton on h(T) = h0, as in the property update
+    const double Tin = T[c];
+    double Tn = Tin;
     if (!bad) {
         const double h0 = h0R[c];
         int st = 1;
@@ -413,26 +506,26 @@ __global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
                 break;
             }
         }
-        if (st) bad = true;
+        if (st || !((Tn - Tin >= ck.dT_lo) & (Tn - Tin <= ck.dT_hi))) bad = true;
     }
-    if (valid && bad) {
-        const int slot = atomicAdd(n_routed, 1);
-        queue[slot] = c;
-        atomicAdd(&stats[0], 1ull);
+    // routed cells: one queue reservation per wave
+    const bool rt = valid && bad;
+    const unsigned long long rm = __ballot(rt);
+    int slot0 = 0;
+    if (lane == 0 && rm) {
+        slot0 = atomicAdd(n_routed, (int)__popcll(rm));
+        atomicAdd(&stats[0], (unsigned long long)__popcll(rm));
+    }
+    slot0 = __shfl(slot0, 0, 64);
+    if (rt) {
+        queue[slot0 + (int)__popcll(rm & ((1ull << lane) - 1ull))] = c;
     } else if (valid) {
         T[c] = Tn;
         status[c] = 0;
         if (nsteps) nsteps[c] = 0;
     }
     // new rows of the cells that passed; the others keep Y_in
-    const bool keep = valid && !bad;
-    __syncthreads();
-    if (keep) {
-#pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (k < K) s_row[lane * ld + k] = y[k];
-    }
-    s_keep[lane] = keep ? 1 : 0;
+    s_keep[lane] = (valid && !bad) ? 1 : 0;
     __syncthreads();
     double *dst = Y + (size_t)base * K;
     const int total = cnt * K;
@@ -444,7 +537,7 @@ __global__ void __launch_bounds__(POST_CELLS, 2) post_kernel(int K, int n,
         const int ii = i < total ? i : 0;
         const int cc = (int)(((float)ii + 0.5f) * invK);
         kp[r] = i < total ? s_keep[cc] : 0;
-        v[r] = s_row[cc * ld + (ii - cc * K)];
+        v[r] = s_y[cc * ld + (ii - cc * K)];
     }
 #pragma unroll
     for (int r = 0; r < KM; ++r)
@@ -485,16 +578,17 @@ template <int KP> static int ingest_resident_grid() {
     return cache[dev];
 }
 
-static hipError_t launch_ingest(int K, const double *tab, int n, const double *T, const double *p,
-                                const double *Y, uint16_t *X, int *route, double *h0, hipStream_t s) {
+static hipError_t launch_ingest(int K, int E, int nrat, const double *tab, int n, const double *T,
+                                const double *p, const double *Y, uint16_t *X, int *route, double *h0,
+                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
     return with_km(K, [&](auto km) {
         constexpr int KP = decltype(km)::v;
         const int64_t groups = ((int64_t)n + 64 / KP - 1) / (64 / KP);
         const int grid = (int)std::min<int64_t>(ingest_resident_grid<KP>(),
                                                 (groups + ING_THREADS / 64 - 1) / (ING_THREADS / 64));
-        hipLaunchKernelGGL(ingest_kernel<KP>, dim3(grid), dim3(ING_THREADS), 0, s, K, n, tab, T, p, Y, X,
-                           route, h0);
+        hipLaunchKernelGGL(ingest_kernel<KP>, dim3(grid), dim3(ING_THREADS), 0, s, K, E, nrat, n, tab, T,
+                           p, Y, X, route, h0);
         return hipGetLastError();
     });
 }
@@ -512,9 +606,18 @@ __global__ void gather_rows_kernel(const int *__restrict__ idx, int B, const uin
     for (int k = threadIdx.x; k < K; k += blockDim.x) Zb[(size_t)r * K + k] = Z[(size_t)src * K + k];
 }
 
+// Where a batch's loss goes: loss_acc[0], or with ctl the slot of the current
+// epoch, loss_acc[ctl[0] / spe], scaled by `scale` (1 / batches per epoch).
+struct LossSink {
+    float *acc;
+    const long long *ctl;
+    int spe;
+    float scale;
+};
+
 // MSE on z-scored outputs: loss = mean((out - tgt)^2); dOut = bf16(2 (out - tgt) / count)
 __global__ void mse_kernel(const float *__restrict__ out, const float *__restrict__ tgt, int count,
-                           uint16_t *dout, float *loss_acc) {
+                           uint16_t *dout, LossSink sink) {
     __shared__ float red[256];
     float s = 0.f;
     const float sc = 2.0f / (float)count;
@@ -529,15 +632,145 @@ __global__ void mse_kernel(const float *__restrict__ out, const float *__restric
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && loss_acc) atomicAdd(loss_acc, red[0] / (float)count);
+    if (threadIdx.x == 0 && sink.acc) {
+        float *dst = sink.ctl ? sink.acc + sink.ctl[0] / sink.spe : sink.acc;
+        atomicAdd(dst, red[0] / (float)count * sink.scale);
+    }
 }
 
-// db[o] = sum_b dZ[b][o]  (FP32 accumulation of the BF16 gradient)
-__global__ void colsum_kernel(const uint16_t *__restrict__ dZ, int B, int N, float *db) {
+// Sum over `count` values of (out - tgt)^2 / denom into *acc (held-out loss).
+__global__ void sq_err_kernel(const float *__restrict__ out, const float *__restrict__ tgt,
+                              long long count, double denom, float *acc) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float d = out[i] - tgt[i];
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(acc, (float)(red[0] / denom));
+}
+
+__global__ void zero_f32_kernel(float *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// the training loop's device-side schedule
+// ---------------------------------------------------------------------------
+// ctl[0] = steps done in this training call, ctl[1] = optimizer steps before
+// it.  Every step's kernels read them, so one captured step is replayed for
+// all steps.
+
+// SplitMix64's output function (Steele, Lea, Flood 2014): a bijective 64-bit
+// mixer, the round function of the permutation below.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// A pseudo-random permutation of [0, n): a four-round balanced Feistel
+// network on 2 * half bits (2^(2 half) >= n) keyed by `key`, with cycle
+// walking (values >= n are mapped again until they fall inside; the walk ends
+// because the cycle through i comes back to i < n).
+__device__ __forceinline__ unsigned int feistel_perm(unsigned int i, unsigned int n, int half,
+                                                     unsigned long long key) {
+    const unsigned int mask = (1u << half) - 1u;
+    unsigned int x = i;
+    do {
+        unsigned int L = x >> half, R = x & mask;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const unsigned int t =
+                L ^ (unsigned int)(mix64(key + 0x9e3779b97f4a7c15ull * (unsigned long long)(r + 1) + R) & mask);
+            L = R;
+            R = t;
+        }
+        x = (L << half) | R;
+    } while (x >= n);
+    return x;
+}
+
+// Rows of the current step's batch: epoch e = s / spe, batch b = s % spe,
+// row r -> perm_e(b B + r) with the epoch's key mix64(seed ^ mix64(e + 1)).
+__global__ void batch_index_kernel(const long long *ctl, int B, int spe, unsigned int n, int half,
+                                   unsigned long long seed, int *idx) {
+    const long long st = ctl[0];
+    const unsigned long long e = (unsigned long long)(st / spe);
+    const unsigned int b = (unsigned int)(st % spe);
+    const unsigned long long key = mix64(seed ^ mix64(e + 1ull));
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < B; r += gridDim.x * blockDim.x)
+        idx[r] = (int)feistel_perm(b * (unsigned int)B + (unsigned int)r, n, half, key);
+}
+
+// Adam (Kingma & Ba 2015, Alg. 1) with the step count t = ctl[1] + ctl[0] + 1
+// and the cosine learning rate lr1 + (lr0 - lr1)(1 + cos(pi s / total)) / 2,
+// s = ctl[0], both read from the device.
+__global__ void adam_sched_kernel(float *p, const float *__restrict__ g, float *mo, float *vo, int64_t n,
+                                  const long long *ctl, double lr0, double lr1, long long total, double b1d,
+                                  double b2d, float eps) {
+    __shared__ float sh[3];
+    const float b1 = (float)b1d, b2 = (float)b2d;
+    if (threadIdx.x == 0) {
+        const long long st = ctl[0];
+        const double t = (double)(ctl[1] + st + 1);
+        const double lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(M_PI * (double)st / (double)(total > 0 ? total : 1)));
+        sh[0] = (float)lr;
+        sh[1] = (float)(1.0 / (1.0 - pow(b1d, t)));
+        sh[2] = (float)(1.0 / (1.0 - pow(b2d, t)));
+    }
+    __syncthreads();
+    const float lr = sh[0], bc1 = sh[1], bc2 = sh[2];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float m = b1 * mo[i] + (1.f - b1) * gi;
+        const float v = b2 * vo[i] + (1.f - b2) * gi * gi;
+        mo[i] = m;
+        vo[i] = v;
+        p[i] -= lr * (m * bc1) / (sqrtf(v * bc2) + eps);
+    }
+}
+
+__global__ void step_end_kernel(long long *ctl) {
+    if (threadIdx.x == 0) ctl[0] += 1;
+}
+
+__global__ void ctl_init_kernel(long long *ctl, long long before) {
+    if (threadIdx.x == 0) {
+        ctl[0] = 0;
+        ctl[1] = before;
+    }
+}
+
+// db[o] = sum_b dZ[b][o] (FP32 accumulation of the BF16 gradient) in two
+// passes with a fixed order: block row y sums rows [y R, (y + 1) R) of a
+// 256-column slab into part[y][o] (a row of 256 columns per load, coalesced),
+// then part is summed over y in order.
+constexpr int COLSUM_ROWS = 64;
+
+__global__ void colsum_part_kernel(const uint16_t *__restrict__ dZ, int B, int N, float *part) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= N) return;
+    const int b0 = blockIdx.y * COLSUM_ROWS, b1 = min(B, b0 + COLSUM_ROWS);
+    float s = 0.f;
+    for (int b = b0; b < b1; ++b) s += bf2f(dZ[(size_t)b * N + o]);
+    part[(size_t)blockIdx.y * N + o] = s;
+}
+
+__global__ void colsum_final_kernel(const float *__restrict__ part, int P, int N, float *db) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= N) return;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += bf2f(dZ[(size_t)b * N + o]);
+    for (int y = 0; y < P; ++y) s += part[(size_t)y * N + o];
     db[o] = s;
 }
 
@@ -648,6 +881,142 @@ __global__ void decode_minmax_kernel(int nf, const unsigned long long *mn, const
     hi[j] = unordered(mx[j]);
 }
 
+// Values whose quantiles make the envelope: raw feature j < F of state c,
+// then the element-ratio windows (valid where the denominator is positive),
+// then T_next - T.
+struct EnvSrc {
+    int K, E, F, nrat, has_dT, n;
+    const double *T, *p, *Y, *Tn, *Emat;   // Emat [E*K]
+    double num[MAX_RATIOS * RAT_E], den[MAX_RATIOS * RAT_E];
+};
+
+__device__ __forceinline__ bool env_value(const EnvSrc &s, int j, int c, double &v) {
+    if (j < s.K) {
+        v = box_cox(s.Y[(size_t)c * s.K + j]);
+        return true;
+    }
+    if (j == s.K) {
+        v = s.T[c];
+        return true;
+    }
+    if (j == s.K + 1) {
+        v = s.p[c];
+        return true;
+    }
+    const int r = j - s.F;
+    if (r < s.nrat) {
+        double u = 0.0, d = 0.0;
+        for (int e = 0; e < s.E; ++e) {
+            double z = 0.0;
+            for (int k = 0; k < s.K; ++k) z += s.Emat[e * s.K + k] * s.Y[(size_t)c * s.K + k];
+            u += s.num[r * RAT_E + e] * z;
+            d += s.den[r * RAT_E + e] * z;
+        }
+        v = u / d;
+        return d > 0.0 && isfinite(v);
+    }
+    v = s.Tn[c] - s.T[c];
+    return isfinite(v);
+}
+
+// pass 0: minimum, maximum (order-preserving integer keys) and count of the
+// valid values of value j = blockIdx.y
+__global__ void env_range_kernel(EnvSrc s, unsigned long long *mn, unsigned long long *mx,
+                                 unsigned long long *cnt) {
+    const int j = blockIdx.y;
+    __shared__ unsigned long long rmn[256], rmx[256], rc[256];
+    unsigned long long lmn = ~0ull, lmx = 0ull, lc = 0ull;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < s.n; c += gridDim.x * blockDim.x) {
+        double v;
+        if (env_value(s, j, c, v)) {
+            const unsigned long long o = ordered(v);
+            lmn = o < lmn ? o : lmn;
+            lmx = o > lmx ? o : lmx;
+            lc += 1;
+        }
+    }
+    rmn[threadIdx.x] = lmn;
+    rmx[threadIdx.x] = lmx;
+    rc[threadIdx.x] = lc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rmn[threadIdx.x] = rmn[threadIdx.x + o] < rmn[threadIdx.x] ? rmn[threadIdx.x + o] : rmn[threadIdx.x];
+            rmx[threadIdx.x] = rmx[threadIdx.x + o] > rmx[threadIdx.x] ? rmx[threadIdx.x + o] : rmx[threadIdx.x];
+            rc[threadIdx.x] += rc[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(&mn[j], rmn[0]);
+        atomicMax(&mx[j], rmx[0]);
+        atomicAdd(&cnt[j], rc[0]);
+    }
+}
+
+constexpr int ENV_BINS = 4096;
+
+__device__ __forceinline__ int env_bin(double v, double lo, double hi) {
+    const double t = hi > lo ? (v - lo) / (hi - lo) * ENV_BINS : 0.0;
+    int b = (int)t;
+    return b < 0 ? 0 : (b >= ENV_BINS ? ENV_BINS - 1 : b);
+}
+
+// pass 1: histogram of value j over ENV_BINS equal bins between its
+// minimum and maximum (per block in LDS, then added to the global one)
+__global__ void env_hist_kernel(EnvSrc s, const unsigned long long *mn, const unsigned long long *mx,
+                                unsigned int *hist) {
+    const int j = blockIdx.y;
+    __shared__ unsigned int h[ENV_BINS];
+    for (int i = threadIdx.x; i < ENV_BINS; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const double lo = unordered(mn[j]), hi = unordered(mx[j]);
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < s.n; c += gridDim.x * blockDim.x) {
+        double v;
+        if (env_value(s, j, c, v)) atomicAdd(&h[env_bin(v, lo, hi)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ENV_BINS; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[(size_t)j * ENV_BINS + i], h[i]);
+}
+
+// pass 2 (one thread per value): the bins holding the ranks floor(q cnt) from
+// either end; lo = lower edge of the first, hi = upper edge of the second
+__global__ void env_quantile_kernel(int nv, const unsigned long long *mn, const unsigned long long *mx,
+                                    const unsigned long long *cnt, const unsigned int *hist, double q,
+                                    double *qlo, double *qhi) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const double lo = unordered(mn[j]), hi = unordered(mx[j]);
+    if (cnt[j] == 0) {
+        qlo[j] = NAN;
+        qhi[j] = NAN;
+        return;
+    }
+    const unsigned long long skip = (unsigned long long)(q * (double)cnt[j]);
+    const unsigned int *h = hist + (size_t)j * ENV_BINS;
+    const double w = (hi - lo) / ENV_BINS;
+    unsigned long long acc = 0ull;
+    int blo = 0, bhi = ENV_BINS - 1;
+    for (int b = 0; b < ENV_BINS; ++b) {
+        acc += h[b];
+        if (acc > skip) {
+            blo = b;
+            break;
+        }
+    }
+    acc = 0ull;
+    for (int b = ENV_BINS - 1; b >= 0; --b) {
+        acc += h[b];
+        if (acc > skip) {
+            bhi = b;
+            break;
+        }
+    }
+    qlo[j] = blo == 0 ? lo : lo + w * blo;
+    qhi[j] = bhi == ENV_BINS - 1 ? hi : lo + w * (bhi + 1);
+}
+
 // training targets: z-scored dY, FP32
 __global__ void pack_targets_kernel(int K, int n, const double *Y, const double *Yn,
                                     const double *mu_y, const double *sd_y, float *Z) {
@@ -685,6 +1054,10 @@ struct AnnState {
     bool rowtab_stale = true;
     std::vector<double> mu_x, sd_x, mu_y, sd_y, lo, hi;
     double dt = 0.0, neg_tol = 1e-6;
+    chemk_ann_checks checks{};   // output checks and element-ratio windows
+    // Changes whenever something a captured step graph holds by value or by
+    // address changes (buffers, tables, checks): part of the graph cache key.
+    uint64_t generation = 1;
     bool have_w = false, have_norm = false, have_env = false;
     long step = 0;
     // inference scratch
@@ -698,6 +1071,8 @@ struct AnnState {
     int tB = 0;
     uint16_t *tX = nullptr, *tdZ[2] = {nullptr, nullptr};
     float *tZt = nullptr, *tOut = nullptr, *tLoss = nullptr;
+    float *tWork = nullptr;   // split-K and column-sum partials
+    size_t tWorkCap = 0;
     std::vector<float *> tZ;          // pre-activations per hidden layer
     std::vector<uint16_t *> tA;       // activations per layer input
 };
@@ -738,6 +1113,7 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->tZt);
     (void)hipFree(a->tOut);
     (void)hipFree(a->tLoss);
+    (void)hipFree(a->tWork);
     for (auto p : a->tZ) (void)hipFree(p);
     for (size_t i = 1; i < a->tA.size(); ++i) (void)hipFree(a->tA[i]);   // tA[0] aliases tX
     delete a;
@@ -755,6 +1131,13 @@ static hipError_t refresh_bf16(AnnState *a, hipStream_t s) {
     return hipGetLastError();
 }
 
+static uint64_t next_generation() {
+    static std::atomic<uint64_t> g{1};
+    return ++g;
+}
+
+static size_t normdev_doubles(const AnnState *a) { return 4 * a->F + 2 * a->K + RAT_DOUBLES; }
+
 static NormDev norm_dev(const AnnState *a) {
     const int F = a->F, K = a->K;
     NormDev nd;
@@ -764,19 +1147,31 @@ static NormDev norm_dev(const AnnState *a) {
     nd.sd_y = a->normdev + 2 * F + K;
     nd.lo = a->normdev + 2 * F + 2 * K;
     nd.hi = a->normdev + 3 * F + 2 * K;
+    nd.rat = a->normdev + 4 * F + 2 * K;
     return nd;
 }
 
 static hipError_t upload_norm(AnnState *a) {
     const int F = a->F, K = a->K;
-    std::vector<double> h(4 * F + 2 * K);
+    std::vector<double> h(normdev_doubles(a), 0.0);
     std::memcpy(h.data(), a->mu_x.data(), 8 * F);
     std::memcpy(h.data() + F, a->sd_x.data(), 8 * F);
     std::memcpy(h.data() + 2 * F, a->mu_y.data(), 8 * K);
     std::memcpy(h.data() + 2 * F + K, a->sd_y.data(), 8 * K);
     std::memcpy(h.data() + 2 * F + 2 * K, a->lo.data(), 8 * F);
     std::memcpy(h.data() + 3 * F + 2 * K, a->hi.data(), 8 * F);
+    double *r = h.data() + 4 * F + 2 * K;
+    const chemk_ann_checks &ck = a->checks;
+    for (int j = 0; j < ck.n_ratios; ++j) {
+        for (int e = 0; e < RAT_E; ++e) {
+            r[tr_num + j * RAT_E + e] = ck.ratio_num[j * RAT_E + e];
+            r[tr_den + j * RAT_E + e] = ck.ratio_den[j * RAT_E + e];
+        }
+        r[tr_lo + j] = ck.ratio_lo[j];
+        r[tr_hi + j] = ck.ratio_hi[j];
+    }
     a->rowtab_stale = true;
+    a->generation = next_generation();
     return hipMemcpy(a->normdev, h.data(), 8 * h.size(), hipMemcpyHostToDevice);
 }
 
@@ -798,7 +1193,7 @@ static hipError_t row_tables(AnnState *a, const DevMech &m, hipStream_t s, const
 // forward of `rows` packed inputs X [rows x FPAD] into out [rows x K] (FP32)
 static hipError_t mlp_forward(AnnState *a, const uint16_t *X, int rows, float *out, uint16_t *buf0,
                               uint16_t *buf1, hipStream_t s, float **Zsave = nullptr,
-                              uint16_t **Asave = nullptr) {
+                              uint16_t **Asave = nullptr, PhaseTimer *tm = nullptr) {
     const uint16_t *in = X;
     uint16_t *bufs[2] = {buf0, buf1};
     for (int l = 0; l < a->L; ++l) {
@@ -812,6 +1207,8 @@ static hipError_t mlp_forward(AnnState *a, const uint16_t *X, int rows, float *o
         g.ldb = a->pd[l];
         g.bias = a->master + a->boff[l];
         const bool last = l == a->L - 1;
+        const int ph = CHEMK_PHASE_LAYER1 + (l < 3 ? l : 3);
+        if (tm) tm->begin(ph, s);
         hipError_t e;
         if (last) {
             g.Cf = out;
@@ -826,6 +1223,7 @@ static hipError_t mlp_forward(AnnState *a, const uint16_t *X, int rows, float *o
             e = launch_gemm(g, true, true, EPI_BIAS_GELU, s);
             in = dst;
         }
+        if (tm) tm->end(ph, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -851,20 +1249,38 @@ static hipError_t ensure_infer(AnnState *a, int64_t n) {
     if ((e = hipMalloc(&a->act[0], sizeof(uint16_t) * ch * wmax)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->act[1], sizeof(uint16_t) * ch * wmax)) != hipSuccess) return e;
     a->cap = n;
+    a->generation = next_generation();
     return hipSuccess;
 }
+
+// Called before a step is enqueued or captured: allocates what the step of n
+// cells needs and builds stale tables, so that a captured graph holds no
+// allocation and replays the current tables.
+hipError_t ann_prepare(AnnState *a, const chemk::DevMech &m, int64_t n, hipStream_t s) {
+    hipError_t e = ensure_infer(a, n);
+    if (e != hipSuccess) return e;
+    const double *ti, *tp;
+    return row_tables(a, m, s, &ti, &tp);
+}
+
+uint64_t ann_generation(const AnnState *a) { return a ? a->generation : 0; }
 
 static hipError_t launch_post(AnnState *a, const AnnStepArgs &x, const double *tab, hipStream_t s) {
     const DevMech &m = *x.dm;
     const int n = (int)x.n, K = m.K;
     const int grid = (n + POST_CELLS - 1) / POST_CELLS;
+    PostChecks ck;
+    ck.neg_tol = a->neg_tol;
+    ck.adj_max = a->checks.adj_max > 0.0 ? a->checks.adj_max : INFINITY;
+    ck.dT_lo = a->checks.dT_lo;
+    ck.dT_hi = a->checks.dT_hi;
     return with_km(K, [&](auto km) {
         constexpr int KM = decltype(km)::v;
 #define POST_CASE(EE)                                                                             \
     case EE:                                                                                      \
         hipLaunchKernelGGL((post_kernel<EE, KM>), dim3(grid), dim3(POST_CELLS), 0, s, K, n, tab, x.T, \
-                           x.Y, a->out, a->route, a->h0, a->neg_tol, x.project, x.status,         \
-                           x.nsteps, x.queue, x.n_routed, x.stats);                              \
+                           x.Y, a->out, a->route, a->h0, ck, x.project, x.status, x.nsteps,      \
+                           x.queue, x.n_routed, x.stats);                                        \
         break;
         switch (m.E) {
             POST_CASE(1)
@@ -896,14 +1312,16 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     if (tm) tm->begin(CHEMK_PHASE_INGEST, s);
     const double *ti, *tp;
     if ((e = row_tables(a, m, s, &ti, &tp)) != hipSuccess) return e;
-    if ((e = launch_ingest(m.K, ti, n, x.T, x.p, x.Y, a->X, a->route, a->h0, s)) != hipSuccess) return e;
+    if ((e = launch_ingest(m.K, m.E, a->checks.n_ratios, ti, n, x.T, x.p, x.Y, a->X, a->route, a->h0,
+                           s)) != hipSuccess)
+        return e;
     if (tm) tm->end(CHEMK_PHASE_INGEST, s);
     // MLP in chunks
     if (tm) tm->begin(CHEMK_PHASE_MLP, s);
     for (int64_t c0 = 0; c0 < n; c0 += CHUNK) {
         const int rows = (int)std::min<int64_t>(CHUNK, n - c0);
-        if ((e = mlp_forward(a, a->X + c0 * FPAD, rows, a->out + c0 * a->K, a->act[0], a->act[1], s)) !=
-            hipSuccess)
+        if ((e = mlp_forward(a, a->X + c0 * FPAD, rows, a->out + c0 * a->K, a->act[0], a->act[1], s,
+                             nullptr, nullptr, tm)) != hipSuccess)
             return e;
     }
     if (tm) tm->end(CHEMK_PHASE_MLP, s);
@@ -1002,7 +1420,7 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
         a->Wt.push_back(wt);
         a->Wb.push_back(wb);
     }
-    ANN_TRY(hipMalloc(&a->normdev, 8 * (4 * a->F + 2 * K)));
+    ANN_TRY(hipMalloc(&a->normdev, 8 * normdev_doubles(a)));
     ANN_TRY(hipMalloc(&a->rowtab, 8 * ROW_TAB_DOUBLES));
     a->mu_x.assign(a->F, 0.0);
     a->sd_x.assign(a->F, 1.0);
@@ -1010,6 +1428,9 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
     a->sd_y.assign(K, 1.0);
     a->lo.assign(a->F, -1e300);
     a->hi.assign(a->F, 1e300);
+    a->checks = chemk_ann_checks{};
+    a->checks.dT_lo = -1e300;
+    a->checks.dT_hi = 1e300;
     ANN_TRY(upload_norm(a));
     return CHEMK_OK;
 }
@@ -1141,6 +1562,133 @@ extern "C" int chemk_ann_get_envelope(chemk_ctx *c, double *lo, double *hi, doub
     return CHEMK_OK;
 }
 
+extern "C" int chemk_ann_set_checks(chemk_ctx *c, const chemk_ann_checks *ck) {
+    ctx_set_error("");
+    AnnState *a;
+    if (int r = need_ann(c, &a)) return r;
+    if (!ck) ANN_FAIL(CHEMK_E_ARG, "null checks");
+    if (std::isnan(ck->adj_max)) ANN_FAIL(CHEMK_E_ARG, "adj_max is NaN");
+    if (!(ck->dT_lo <= ck->dT_hi)) ANN_FAIL(CHEMK_E_ARG, "dT window: need dT_lo <= dT_hi");
+    if (ck->n_ratios < 0 || ck->n_ratios > CHEMK_MAX_RATIOS)
+        ANN_FAIL(CHEMK_E_ARG, "n_ratios=%d outside [0, %d]", ck->n_ratios, CHEMK_MAX_RATIOS);
+    const int E = ctx_devmech(c).E;
+    for (int j = 0; j < ck->n_ratios; ++j) {
+        if (!(ck->ratio_lo[j] <= ck->ratio_hi[j]))
+            ANN_FAIL(CHEMK_E_ARG, "ratio window %d: need lo <= hi", j);
+        for (int e = 0; e < CHEMK_MAX_ELEMENTS; ++e) {
+            const double u = ck->ratio_num[j * CHEMK_MAX_ELEMENTS + e];
+            const double d = ck->ratio_den[j * CHEMK_MAX_ELEMENTS + e];
+            if (!std::isfinite(u) || !std::isfinite(d))
+                ANN_FAIL(CHEMK_E_ARG, "ratio window %d: non-finite coefficient", j);
+            if (e >= E && (u != 0.0 || d != 0.0))
+                ANN_FAIL(CHEMK_E_ARG, "ratio window %d: coefficient of element %d >= E = %d", j, e, E);
+        }
+    }
+    a->checks = *ck;
+    for (int j = ck->n_ratios; j < CHEMK_MAX_RATIOS; ++j) {   // unused windows zeroed
+        for (int e = 0; e < CHEMK_MAX_ELEMENTS; ++e)
+            a->checks.ratio_num[j * CHEMK_MAX_ELEMENTS + e] = a->checks.ratio_den[j * CHEMK_MAX_ELEMENTS + e] = 0.0;
+        a->checks.ratio_lo[j] = a->checks.ratio_hi[j] = 0.0;
+    }
+    ANN_TRY(upload_norm(a));
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_ann_get_checks(chemk_ctx *c, chemk_ann_checks *ck) {
+    ctx_set_error("");
+    AnnState *a;
+    if (int r = need_ann(c, &a)) return r;
+    if (!ck) ANN_FAIL(CHEMK_E_ARG, "null checks");
+    *ck = a->checks;
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_ann_fit_envelope(chemk_ctx *c, int64_t n, const double *T, const double *p,
+                                      const double *Y, const double *Tn, double q, double widen,
+                                      void *stream) {
+    ctx_set_error("");
+    AnnState *a;
+    if (int r = need_ann(c, &a)) return r;
+    if (n < 2 || n > (1ll << 31) - 1) ANN_FAIL(CHEMK_E_ARG, "need 2 <= n < 2^31 states");
+    if (!T || !p || !Y) ANN_FAIL(CHEMK_E_ARG, "null array");
+    if (!(q >= 0.0 && q < 0.5) || !(widen >= 0.0) || !std::isfinite(widen))
+        ANN_FAIL(CHEMK_E_ARG, "need 0 <= q < 0.5 and widen >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const DevMech m = ctx_devmech(c);
+    EnvSrc src{};
+    src.K = a->K;
+    src.E = m.E;
+    src.F = a->F;
+    src.nrat = a->checks.n_ratios;
+    src.has_dT = Tn ? 1 : 0;
+    src.n = (int)n;
+    src.T = T;
+    src.p = p;
+    src.Y = Y;
+    src.Tn = Tn;
+    src.Emat = m.Emat;
+    for (int i = 0; i < MAX_RATIOS * RAT_E; ++i) {
+        src.num[i] = a->checks.ratio_num[i];
+        src.den[i] = a->checks.ratio_den[i];
+    }
+    const int nv = a->F + src.nrat + src.has_dT;
+    unsigned long long *mn = nullptr, *mx = nullptr, *cnt = nullptr;
+    unsigned int *hist = nullptr;
+    double *qlo = nullptr, *qhi = nullptr;
+    auto release = [&]() {
+        (void)hipFree(mn);
+        (void)hipFree(mx);
+        (void)hipFree(cnt);
+        (void)hipFree(hist);
+        (void)hipFree(qlo);
+        (void)hipFree(qhi);
+    };
+    hipError_t e = hipSuccess;
+    std::vector<double> hl(nv), hh(nv);
+    do {
+        if ((e = hipMalloc(&mn, 8 * nv)) || (e = hipMalloc(&mx, 8 * nv)) || (e = hipMalloc(&cnt, 8 * nv)) ||
+            (e = hipMalloc(&hist, 4 * (size_t)nv * ENV_BINS)) || (e = hipMalloc(&qlo, 8 * nv)) ||
+            (e = hipMalloc(&qhi, 8 * nv)))
+            break;
+        if ((e = hipMemsetAsync(mn, 0xff, 8 * nv, s)) || (e = hipMemsetAsync(mx, 0, 8 * nv, s)) ||
+            (e = hipMemsetAsync(cnt, 0, 8 * nv, s)) ||
+            (e = hipMemsetAsync(hist, 0, 4 * (size_t)nv * ENV_BINS, s)))
+            break;
+        const int gx = (int)std::min<int64_t>(512, (n + 255) / 256);
+        hipLaunchKernelGGL(env_range_kernel, dim3(gx, nv), dim3(256), 0, s, src, mn, mx, cnt);
+        hipLaunchKernelGGL(env_hist_kernel, dim3(gx, nv), dim3(256), 0, s, src, mn, mx, hist);
+        hipLaunchKernelGGL(env_quantile_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, nv, mn, mx, cnt,
+                           hist, q, qlo, qhi);
+        if ((e = hipGetLastError())) break;
+        if ((e = hipMemcpyAsync(hl.data(), qlo, 8 * nv, hipMemcpyDeviceToHost, s)) ||
+            (e = hipMemcpyAsync(hh.data(), qhi, 8 * nv, hipMemcpyDeviceToHost, s)))
+            break;
+        e = hipStreamSynchronize(s);
+    } while (false);
+    release();
+    ANN_TRY(e);
+    for (int j = 0; j < nv; ++j)
+        if (!std::isfinite(hl[j]) || !std::isfinite(hh[j]))
+            ANN_FAIL(CHEMK_E_ARG, "envelope value %d has no finite training value", j);
+    auto widened = [&](int j, double &lo, double &hi) {
+        const double span = hh[j] - hl[j];
+        lo = hl[j] - widen * span;
+        hi = hh[j] + widen * span;
+    };
+    a->lo.resize(a->F);
+    a->hi.resize(a->F);
+    for (int j = 0; j < a->F; ++j) widened(j, a->lo[j], a->hi[j]);
+    // a species absent from a cell (Y_k = 0, Box-Cox -1/lambda) is inside the
+    // envelope whatever the training data's lower quantile: the lower tail of
+    // a mass fraction is its trace regime, where the feature changes little
+    for (int k = 0; k < a->K; ++k) a->lo[k] = std::min(a->lo[k], -1.0 / BCT_LAMBDA);
+    for (int r = 0; r < src.nrat; ++r) widened(a->F + r, a->checks.ratio_lo[r], a->checks.ratio_hi[r]);
+    if (src.has_dT) widened(a->F + src.nrat, a->checks.dT_lo, a->checks.dT_hi);
+    ANN_TRY(upload_norm(a));
+    a->have_env = true;
+    return CHEMK_OK;
+}
+
 extern "C" int chemk_ann_fit_norm(chemk_ctx *c, int64_t n, const double *T, const double *p,
                                   const double *Y, const double *Yn, double dt, double widen,
                                   double neg_tol, void *stream) {
@@ -1223,7 +1771,7 @@ extern "C" int chemk_ann_pack(chemk_ctx *c, int64_t n, const double *T, const do
     const DevMech m = ctx_devmech(c);
     const double *ti, *tp;
     ANN_TRY(row_tables(a, m, s, &ti, &tp));
-    ANN_TRY(launch_ingest(m.K, ti, (int)n, T, p, Y, X, route, h0, s));
+    ANN_TRY(launch_ingest(m.K, m.E, a->checks.n_ratios, ti, (int)n, T, p, Y, X, route, h0, s));
     if (Z) {
         const int g2 = (int)std::min<int64_t>(8192, (n * a->K + 255) / 256);
         hipLaunchKernelGGL(pack_targets_kernel, dim3(g2), dim3(256), 0, s, a->K, (int)n, Y, Yn,
@@ -1254,6 +1802,16 @@ extern "C" int chemk_ann_forward_packed(chemk_ctx *c, int64_t n, const uint16_t 
     return CHEMK_OK;
 }
 
+// K slices of the weight-gradient product dW = A^T dZ (in x out, K = the
+// batch): enough slices that the 128 x 128 output tiles times the slices
+// reach about 256 workgroups, each slice at least 64 rows of the batch.
+static int dw_split(int in, int out, int B) {
+    const int tiles = ((in + 127) / 128) * ((out + 127) / 128);
+    int s = 1;
+    while (tiles * s < 256 && B % (2 * s) == 0 && B / (2 * s) >= 64) s *= 2;
+    return s;
+}
+
 static hipError_t ensure_train(AnnState *a, int B) {
     if (B <= a->tB) return hipSuccess;
     (void)hipFree(a->tX);
@@ -1262,6 +1820,8 @@ static hipError_t ensure_train(AnnState *a, int B) {
     (void)hipFree(a->tZt);
     (void)hipFree(a->tOut);
     (void)hipFree(a->tLoss);
+    (void)hipFree(a->tWork);
+    a->tWork = nullptr;
     for (auto p : a->tZ) (void)hipFree(p);
     for (size_t i = 1; i < a->tA.size(); ++i) (void)hipFree(a->tA[i]);   // tA[0] aliases tX
     a->tZ.clear();
@@ -1276,6 +1836,12 @@ static hipError_t ensure_train(AnnState *a, int B) {
     if ((e = hipMalloc(&a->tZt, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tOut, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tLoss, 4)) != hipSuccess) return e;
+    // split-K partials of the largest weight gradient, then the column-sum partials
+    size_t work = 0;
+    for (int l = 0; l < a->L; ++l)
+        work = std::max(work, (size_t)dw_split(a->pd[l], a->pd[l + 1], B) * a->pd[l] * a->pd[l + 1]);
+    a->tWorkCap = work + (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * wmax;
+    if ((e = hipMalloc(&a->tWork, 4 * a->tWorkCap)) != hipSuccess) return e;
     for (int l = 0; l < a->L - 1; ++l) {
         float *z = nullptr;
         if ((e = hipMalloc(&z, 4 * (size_t)B * a->pd[l + 1])) != hipSuccess) return e;
@@ -1291,28 +1857,18 @@ static hipError_t ensure_train(AnnState *a, int B) {
     return hipSuccess;
 }
 
-extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B, const uint16_t *X,
-                                    const float *Z, float lr, int32_t update, float *loss,
-                                    float *grads, void *stream) {
-    ctx_set_error("");
-    AnnState *a;
-    if (int r = need_ann(c, &a)) return r;
-    if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
-    if (!idx || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null array");
-    if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
-    if (!(lr >= 0) || !std::isfinite(lr)) ANN_FAIL(CHEMK_E_ARG, "bad learning rate");
-    ANN_TRY(ensure_train(a, B));
-    hipStream_t s = (hipStream_t)stream;
+// One training step's forward (saving Z and A), loss and backward on rows
+// idx[0..B-1] of (X, Z): the gradient lands in a->grad, the batch loss in sink.
+static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t *X, const float *Z,
+                          LossSink sink, hipStream_t s) {
     const int K = a->K, L = a->L;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(B), dim3(64), 0, s, idx, B, X, FPAD, Z, K, a->tX, a->tZt);
     a->tA[0] = a->tX;
-    ANN_TRY(hipMemsetAsync(a->tLoss, 0, 4, s));
-    // forward with saved pre-activations and activations
-    ANN_TRY(mlp_forward(a, a->tX, B, a->tOut, nullptr, nullptr, s, a->tZ.data(), a->tA.data()));
-    // loss and output gradient
+    hipError_t e;
+    if ((e = mlp_forward(a, a->tX, B, a->tOut, nullptr, nullptr, s, a->tZ.data(), a->tA.data())) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(mse_kernel, dim3(std::min(1024, (B * K + 255) / 256)), dim3(256), 0, s, a->tOut,
-                       a->tZt, B * K, a->tdZ[0], a->tLoss);
-    // backward
+                       a->tZt, B * K, a->tdZ[0], sink);
     int cur = 0;
     for (int l = L - 1; l >= 0; --l) {
         const int in = a->pd[l], out = a->pd[l + 1];
@@ -1327,9 +1883,12 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
         gw.ldb = out;
         gw.Cf = a->grad + a->woff[l];
         gw.ldc = out;
-        ANN_TRY(launch_gemm(gw, false, false, EPI_STORE_F32, s));
-        hipLaunchKernelGGL(colsum_kernel, dim3((out + 255) / 256), dim3(256), 0, s, dZ, B, out,
-                           a->grad + a->boff[l]);
+        if ((e = launch_gemm_splitk(gw, dw_split(in, out, B), a->tWork, s)) != hipSuccess) return e;
+        const int P = (B + COLSUM_ROWS - 1) / COLSUM_ROWS;
+        hipLaunchKernelGGL(colsum_part_kernel, dim3((out + 255) / 256, P), dim3(256), 0, s, dZ, B, out,
+                           a->tWork + a->tWorkCap - (size_t)P * out);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((out + 255) / 256), dim3(256), 0, s,
+                           a->tWork + a->tWorkCap - (size_t)P * out, P, out, a->grad + a->boff[l]);
         if (l > 0) {
             GemmArgs ga{};
             ga.M = B;
@@ -1343,11 +1902,28 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
             ga.ldcb = in;
             ga.Zin = a->tZ[l - 1];
             ga.ldz = in;
-            ANN_TRY(launch_gemm(ga, true, true, EPI_GELU_GRAD, s));
+            if ((e = launch_gemm(ga, true, true, EPI_GELU_GRAD, s)) != hipSuccess) return e;
             cur ^= 1;
         }
     }
-    ANN_TRY(hipGetLastError());
+    return hipGetLastError();
+}
+
+extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B, const uint16_t *X,
+                                    const float *Z, float lr, int32_t update, float *loss,
+                                    float *grads, void *stream) {
+    ctx_set_error("");
+    AnnState *a;
+    if (int r = need_ann(c, &a)) return r;
+    if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
+    if (!idx || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null array");
+    if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
+    if (!(lr >= 0) || !std::isfinite(lr)) ANN_FAIL(CHEMK_E_ARG, "bad learning rate");
+    ANN_TRY(ensure_train(a, B));
+    hipStream_t s = (hipStream_t)stream;
+    const int L = a->L;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, s, a->tLoss, 1);
+    ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s));
     if (loss) ANN_TRY(hipMemcpyAsync(loss, a->tLoss, 4, hipMemcpyDeviceToDevice, s));
     if (grads) {
         size_t p = 0;
@@ -1370,6 +1946,117 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
                            (int64_t)a->nparam, lr, (float)b1, (float)b2, 1e-8f, bc1, bc2);
         ANN_TRY(refresh_bf16(a, s));
     }
+    return CHEMK_OK;
+}
+
+// Held-out loss: the network's forward over the n rows of (X, Z) in chunks,
+// the mean squared error added to *acc.
+static hipError_t holdout_loss(AnnState *a, int64_t n, const uint16_t *X, const float *Z, float *acc,
+                               hipStream_t s) {
+    for (int64_t c0 = 0; c0 < n; c0 += CHUNK) {
+        const int rows = (int)std::min<int64_t>(CHUNK, n - c0);
+        hipError_t e = mlp_forward(a, X + c0 * FPAD, rows, a->out, a->act[0], a->act[1], s);
+        if (e != hipSuccess) return e;
+        const long long cnt = (long long)rows * a->K;
+        hipLaunchKernelGGL(sq_err_kernel, dim3((unsigned)std::min<long long>(1024, (cnt + 255) / 256)),
+                           dim3(256), 0, s, a->out, Z + c0 * a->K, cnt, (double)n * a->K, acc);
+    }
+    return hipGetLastError();
+}
+
+extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const float *Z,
+                               const uint16_t *X_hold, const float *Z_hold, int64_t n_hold,
+                               const chemk_train_opts *o, float *epoch_loss, float *hold_loss,
+                               void *stream) {
+    ctx_set_error("");
+    AnnState *a;
+    if (int r = need_ann(c, &a)) return r;
+    if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
+    if (!o || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null argument");
+    const int B = o->batch;
+    if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
+    if (n < B || n > (1ll << 31) - 1) ANN_FAIL(CHEMK_E_ARG, "need batch <= n < 2^31 training rows");
+    if (o->epochs < 1 || o->epochs > 100000) ANN_FAIL(CHEMK_E_ARG, "epochs=%d outside [1, 1e5]", o->epochs);
+    if (!(o->lr0 >= 0) || !(o->lr1 >= 0) || !std::isfinite(o->lr0) || !std::isfinite(o->lr1))
+        ANN_FAIL(CHEMK_E_ARG, "bad learning rates");
+    if (n_hold < 0 || n_hold > (1ll << 31) - 1 || (n_hold > 0 && (!X_hold || !Z_hold)))
+        ANN_FAIL(CHEMK_E_ARG, "bad held-out set");
+    if (reinterpret_cast<uintptr_t>(X) % 16 || (X_hold && reinterpret_cast<uintptr_t>(X_hold) % 16))
+        ANN_FAIL(CHEMK_E_ARG, "X must be 16-byte aligned");
+    hipStream_t s0 = (hipStream_t)stream;
+    const int spe = (int)(n / B);
+    const long long total = (long long)spe * o->epochs;
+    int half = 1;
+    while ((1ll << (2 * half)) < n) ++half;
+    // buffers first: nothing is allocated inside the capture
+    ANN_TRY(ensure_train(a, B));
+    if (n_hold > 0) ANN_TRY(ensure_infer(a, std::min<int64_t>(n_hold, CHUNK)));
+    long long *ctl = nullptr;
+    int *idx = nullptr;
+    float *eloss = nullptr, *hloss = nullptr;
+    hipStream_t own = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    auto release = [&]() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (own) (void)hipStreamDestroy(own);
+        (void)hipFree(ctl);
+        (void)hipFree(idx);
+        (void)hipFree(eloss);
+        (void)hipFree(hloss);
+    };
+    hipError_t e = hipSuccess;
+    std::vector<float> he(o->epochs, 0.f), hh(o->epochs, 0.f);
+    do {
+        if ((e = hipMalloc(&ctl, 2 * sizeof(long long))) || (e = hipMalloc(&idx, 4 * (size_t)B)) ||
+            (e = hipMalloc(&eloss, 4 * (size_t)o->epochs)) || (e = hipMalloc(&hloss, 4 * (size_t)o->epochs)))
+            break;
+        hipStream_t s = s0;
+        if (o->use_graph && !s) {   // capture needs a stream other than the null stream
+            if ((e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking))) break;
+            s = own;
+        }
+        hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(64), 0, s, ctl, (long long)a->step);
+        hipLaunchKernelGGL(zero_f32_kernel, dim3((o->epochs + 255) / 256), dim3(256), 0, s, eloss, o->epochs);
+        hipLaunchKernelGGL(zero_f32_kernel, dim3((o->epochs + 255) / 256), dim3(256), 0, s, hloss, o->epochs);
+        if ((e = hipGetLastError())) break;
+        const int gadam = (int)std::min<size_t>(4096, (a->nparam + 255) / 256);
+        auto one_step = [&](hipStream_t st) -> hipError_t {
+            hipLaunchKernelGGL(batch_index_kernel, dim3((B + 255) / 256), dim3(256), 0, st, ctl, B, spe,
+                               (unsigned int)n, half, (unsigned long long)o->seed, idx);
+            hipError_t ee = fwd_bwd(a, idx, B, X, Z, LossSink{eloss, ctl, spe, 1.0f / (float)spe}, st);
+            if (ee != hipSuccess) return ee;
+            hipLaunchKernelGGL(adam_sched_kernel, dim3(gadam), dim3(256), 0, st, a->master, a->grad, a->m1,
+                               a->m2, (int64_t)a->nparam, ctl, (double)o->lr0, (double)o->lr1, total, 0.9,
+                               0.999, 1e-8f);
+            if ((ee = refresh_bf16(a, st)) != hipSuccess) return ee;
+            hipLaunchKernelGGL(step_end_kernel, dim3(1), dim3(64), 0, st, ctl);
+            return hipGetLastError();
+        };
+        if (o->use_graph) {
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal))) break;
+            hipError_t ec = one_step(s);
+            e = hipStreamEndCapture(s, &graph);
+            if (ec) e = ec;
+            if (e) break;
+            if ((e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0))) break;
+        }
+        for (int ep = 0; ep < o->epochs && !e; ++ep) {
+            for (int b = 0; b < spe && !e; ++b) e = o->use_graph ? hipGraphLaunch(gexec, s) : one_step(s);
+            if (!e && n_hold > 0) e = holdout_loss(a, n_hold, X_hold, Z_hold, hloss + ep, s);
+        }
+        if (e) break;
+        if ((e = hipMemcpyAsync(he.data(), eloss, 4 * (size_t)o->epochs, hipMemcpyDeviceToHost, s)) ||
+            (e = hipMemcpyAsync(hh.data(), hloss, 4 * (size_t)o->epochs, hipMemcpyDeviceToHost, s)))
+            break;
+        e = hipStreamSynchronize(s);
+    } while (false);
+    release();
+    ANN_TRY(e);
+    a->step += total;
+    if (epoch_loss) std::memcpy(epoch_loss, he.data(), 4 * (size_t)o->epochs);
+    if (hold_loss) std::memcpy(hold_loss, hh.data(), 4 * (size_t)o->epochs);
     return CHEMK_OK;
 }
 

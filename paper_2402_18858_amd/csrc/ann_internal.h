@@ -30,3 +30,5 @@ void ann_destroy(AnnState *a);
 bool ann_ready(const AnnState *a);
 double ann_dt(const AnnState *a);
 hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &args, hipStream_t s);
+hipError_t ann_prepare(AnnState *a, const chemk::DevMech &m, int64_t n, hipStream_t s);
+uint64_t ann_generation(const AnnState *a);

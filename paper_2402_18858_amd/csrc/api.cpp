@@ -147,17 +147,21 @@ extern "C" int chemk_mech_info(const chemk_mech *m, int32_t *K, int32_t *R, int3
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+// A captured step is replayed only for the same arguments and, in ANN mode,
+// the same generation of the network's state (buffers, tables and checks
+// that the graph holds by address or by value).
 struct GraphKey {
     int64_t n;
     const void *T, *p, *Y, *st, *ns;
     double dt;
     int mode, bins, wpc, max_steps, project;
     double rtol, atolY, atolT, h0;
+    uint64_t ann_gen;
     bool operator<(const GraphKey &o) const {
         return std::tie(n, T, p, Y, st, ns, dt, mode, bins, wpc, max_steps, project, rtol, atolY,
-                        atolT, h0) < std::tie(o.n, o.T, o.p, o.Y, o.st, o.ns, o.dt, o.mode, o.bins,
-                                              o.wpc, o.max_steps, o.project, o.rtol, o.atolY,
-                                              o.atolT, o.h0);
+                        atolT, h0, ann_gen) < std::tie(o.n, o.T, o.p, o.Y, o.st, o.ns, o.dt, o.mode,
+                                                       o.bins, o.wpc, o.max_steps, o.project, o.rtol,
+                                                       o.atolY, o.atolT, o.h0, o.ann_gen);
     }
 };
 
@@ -172,6 +176,7 @@ struct chemk_ctx {
     int *bin = nullptr, *queue = nullptr;
     int *small = nullptr;                 // [0] counter, [1] n_items, [2..] hist/offs
     unsigned long long *stats = nullptr;  // [0] routed, [1] steps, [2] failed
+    unsigned long long *last_stats = nullptr;   // where the last advance wrote its counters
     int tuned_bins = 0, tuned_wpc = 0;
     std::map<GraphKey, hipGraphExec_t> graphs;
     AnnState *ann = nullptr;
@@ -443,28 +448,38 @@ static void resolve_tuning(const chemk_ctx *c, const chemk_opts *o, int &bins, i
     wpc = o->waves_per_cu > 0 ? o->waves_per_cu : (c->tuned_wpc > 0 ? c->tuned_wpc : 8);
 }
 
+// Device scratch of one DI step: stiffness bins and queue [n], the small
+// counters (queue counter, item count, histogram, offsets) and statistics.
+struct DiScratch {
+    int *bin, *queue, *small;
+    unsigned long long *stats;
+};
+
+static DiScratch ctx_scratch(chemk_ctx *c) { return DiScratch{c->bin, c->queue, c->small, c->stats}; }
+
 // Enqueue the DI step over all n cells.  queue order from the stiffness bins.
-static int enqueue_di(chemk_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
-                      const chemk_opts *o, int bins, int wpc, int32_t *status, int32_t *nsteps,
-                      hipStream_t s) {
-    int *counter = c->small, *n_items = c->small + 1;
-    int *hist = c->small + 2, *offs = c->small + 2 + kMaxBins;
-    HIP_TRY(launch_zero_u64(c->stats, 4, s));
+static int enqueue_di(chemk_ctx *c, const DiScratch &w, int64_t n, double *T, const double *p, double *Y,
+                      double dt, const chemk_opts *o, int bins, int wpc, int32_t *status, int32_t *nsteps,
+                      hipStream_t s, bool timed = true) {
+    int *counter = w.small, *n_items = w.small + 1;
+    int *hist = w.small + 2, *offs = w.small + 2 + kMaxBins;
+    HIP_TRY(launch_zero_u64(w.stats, 4, s));
     HIP_TRY(launch_zero_ints(counter, 1, s));
     HIP_TRY(launch_set_int(n_items, (int)n, s));
     const int *queue = nullptr;
     if (bins > 1) {
-        c->timer.begin(CHEMK_PHASE_BINNING, s);
-        HIP_TRY(launch_binning(c->dm, (int)n, T, p, Y, dt, bins, c->bin, hist, offs, c->queue, s));
-        c->timer.end(CHEMK_PHASE_BINNING, s);
-        queue = c->queue;
+        if (timed) c->timer.begin(CHEMK_PHASE_BINNING, s);
+        HIP_TRY(launch_binning(c->dm, (int)n, T, p, Y, dt, bins, w.bin, hist, offs, w.queue, s));
+        if (timed) c->timer.end(CHEMK_PHASE_BINNING, s);
+        queue = w.queue;
     }
     const int64_t grid64 = std::min<int64_t>(n, (int64_t)c->cu_count * wpc);
-    c->timer.begin(CHEMK_PHASE_DI, s);
+    if (timed) c->timer.begin(CHEMK_PHASE_DI, s);
     HIP_TRY(launch_di(c->dm, (int)grid64, n_items, queue, counter, T, p, Y, dt, o->rtol,
                       o->atol_Y, o->atol_T, o->h0_frac, o->max_steps, o->project, status, nsteps,
-                      c->stats, 0, s));
-    c->timer.end(CHEMK_PHASE_DI, s);
+                      w.stats, 0, s));
+    if (timed) c->timer.end(CHEMK_PHASE_DI, s);
+    c->last_stats = w.stats;
     return CHEMK_OK;
 }
 
@@ -490,24 +505,41 @@ extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p
     hipStream_t s = (hipStream_t)stream;
     int bins, wpc;
     resolve_tuning(c, o, bins, wpc);
+    c->last_stats = c->stats;
 
     auto enqueue = [&]() -> int {
         if (o->mode == CHEMK_MODE_DI)
-            return enqueue_di(c, n, T, p, Y, dt, o, bins, wpc, status, nsteps, s);
+            return enqueue_di(c, ctx_scratch(c), n, T, p, Y, dt, o, bins, wpc, status, nsteps, s);
         AnnStepArgs a{n, T, p, Y, dt, o->rtol, o->atol_Y, o->atol_T, o->h0_frac, o->max_steps,
                       o->project, status, nsteps, c->cu_count * wpc, c->queue, c->small,
                       c->small + 1, c->stats, &c->dm, &c->timer};
         hipError_t e = ann_enqueue_step(c->ann, a, s);
         if (e != hipSuccess)
             return fail(CHEMK_E_HIP, "ANN step: %s", hipGetErrorString(e));
+        c->last_stats = c->stats;
         return CHEMK_OK;
     };
+    if (o->mode == CHEMK_MODE_ANN) {
+        // buffers and tables first: nothing is allocated inside a capture
+        hipError_t e = ann_prepare(c->ann, c->dm, n, s);
+        if (e != hipSuccess) return fail(CHEMK_E_HIP, "ANN step set-up: %s", hipGetErrorString(e));
+    }
     if (!o->use_graph || c->timer.on) return enqueue();
 
+    const uint64_t gen = o->mode == CHEMK_MODE_ANN ? ann_generation(c->ann) : 0;
     GraphKey key{n, T, p, Y, status, nsteps, dt, o->mode, bins, wpc, o->max_steps, o->project,
-                 o->rtol, o->atol_Y, o->atol_T, o->h0_frac};
+                 o->rtol, o->atol_Y, o->atol_T, o->h0_frac, gen};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
+        // graphs of an earlier network state can never be replayed again
+        for (auto g = c->graphs.begin(); g != c->graphs.end();) {
+            if (g->first.mode == CHEMK_MODE_ANN && g->first.ann_gen != gen) {
+                hipGraphExecDestroy(g->second);
+                g = c->graphs.erase(g);
+            } else {
+                ++g;
+            }
+        }
         hipStream_t cs = s;
         hipStream_t own = nullptr;
         if (!cs) {   // capture needs a non-default stream
@@ -542,7 +574,8 @@ extern "C" int chemk_last_counters(chemk_ctx *c, int64_t out[3], void *stream) {
     if (!c || !out) return fail(CHEMK_E_ARG, "null argument");
     if (int r = set_device(c)) return r;
     unsigned long long h[4];
-    HIP_TRY(hipMemcpyAsync(h, c->stats, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipMemcpyAsync(h, c->last_stats ? c->last_stats : c->stats, sizeof h, hipMemcpyDeviceToHost,
+                           (hipStream_t)stream));
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     for (int i = 0; i < 3; ++i) out[i] = (int64_t)h[i];
     return CHEMK_OK;
@@ -618,7 +651,7 @@ extern "C" int chemk_autotune(chemk_ctx *c, int64_t n, const double *T, const do
                 goto done;
             }
             hipEventRecord(e0, s);
-            if ((rc = enqueue_di(c, n, Tc, p, Yc, dt, &oo, b, w, st, nullptr, s))) goto done;
+            if ((rc = enqueue_di(c, ctx_scratch(c), n, Tc, p, Yc, dt, &oo, b, w, st, nullptr, s))) goto done;
             hipEventRecord(e1, s);
             if (hipEventSynchronize(e1) != hipSuccess) {
                 rc = fail(CHEMK_E_HIP, "autotune sync");

@@ -25,11 +25,22 @@ struct GemmArgs {
     int ldcb;
     const float *Zin;
     int ldz;
+    // split K over gridDim.y > 1 slices (launch_gemm_splitk): slice z takes
+    // K rows [z K, (z + 1) K) of both operands and writes its partial product
+    // to Cf + z * split_stride
+    long long split_stride;
 };
 
 // Any K >= 1 and leading dimensions; operands in whole, 16-byte aligned
 // chunks of 8 (K, lda, ldb and the chunked extents multiples of 8) take the
 // buffer-load path, others an element-by-element one.  Operands below 2 GiB.
 hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s);
+
+// C = A^T B with both operands K-major rows (A [K x M], B [K x N], the
+// weight-gradient product of training), FP32 result, K split into `split`
+// slices whose partial products go to work [split][M][N] (contiguous, N
+// fastest) and are summed in slice order into C (ldc = N).  K must be a
+// multiple of split.
+hipError_t launch_gemm_splitk(const GemmArgs &g, int split, float *work, hipStream_t s);
 
 }  // namespace chemk

@@ -30,6 +30,8 @@
 // accumulations in flight for the same rate.  The first layer's time is the
 // VALU work of its GELU epilogue, hence the reciprocal-free GELU below.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "gemm.h"
@@ -354,6 +356,12 @@ __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16_t (&a
 template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC>
 __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     constexpr int PD = 2;   // K slabs in flight in registers ahead of the one multiplied
+    if (gridDim.y > 1) {   // split K: this slice's rows of both operands, its own partial C
+        const long long z = blockIdx.y;
+        g.A += z * g.K * (AK ? 1 : g.lda);
+        g.B += z * g.K * (BKc ? 1 : g.ldb);
+        g.Cf += z * g.split_stride;
+    }
     constexpr int TM = BM / 64, TN = BN / 64, LDS_LD = lds_ld<BK>();
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDS_LD];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDS_LD];
@@ -625,6 +633,40 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
         GEMM_LAUNCH(true);
     }
 #undef GEMM_LAUNCH
+    return hipGetLastError();
+}
+
+// C[i] = sum_z work[z][i], z in slice order (deterministic)
+__global__ void splitk_reduce_kernel(const float *__restrict__ work, int split, long long count, float *C) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int z = 0; z < split; ++z) acc += work[z * count + i];
+        C[i] = acc;
+    }
+}
+
+hipError_t launch_gemm_splitk(const GemmArgs &g0, int split, float *work, hipStream_t s) {
+    if (g0.M <= 0 || g0.N <= 0) return hipSuccess;
+    if (split < 1 || g0.K % split != 0 || g0.ldc != g0.N) return hipErrorInvalidValue;
+    if (split == 1) return launch_gemm(g0, false, false, EPI_STORE_F32, s);
+    GemmArgs g = g0;
+    g.K = g0.K / split;
+    g.Cf = work;
+    g.split_stride = (long long)g.M * g.N;
+    const int64_t bytesA = 2ll * g.lda * g0.K, bytesB = 2ll * g.ldb * g0.K;
+    if (bytesA >= (1ll << 31) || bytesB >= (1ll << 31)) return hipErrorInvalidValue;
+    const bool vec = g.lda % 8 == 0 && g.M % 8 == 0 && g.ldb % 8 == 0 && g.N % 8 == 0;
+    constexpr int TB = 128, TK = 64;
+    const int tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);
+    const dim3 grid(((tiles + 7) / 8) * 8, split);
+    if (vec) hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, false, false, EPI_STORE_F32, true>), grid,
+                                dim3(NTHREADS), 0, s, g);
+    else hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, false, false, EPI_STORE_F32, false>), grid,
+                            dim3(NTHREADS), 0, s, g);
+    const long long count = (long long)g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)std::min<long long>(2048, (count + 255) / 256)),
+                       dim3(256), 0, s, work, split, count, g0.Cf);
     return hipGetLastError();
 }
 

@@ -54,7 +54,8 @@ def _advance(ctx, T, P, Y, dt, st, max_steps=100000):
 
 def generate_pairs(ctx, mech, dt, n_pairs, seed=3001, frac_traj=0.6, frac_mix=0.1,
                    n_rec=200, t_end=2.5, log=print):
-    """Returns host arrays (T, p, Y, Y_next, kind) of n_pairs DI-labelled pairs."""
+    """Returns host arrays (T, p, Y, Y_next, kind, T_next) of n_pairs DI-labelled
+    pairs."""
     import torch
 
     from synth import workload as sw
@@ -123,16 +124,53 @@ def generate_pairs(ctx, mech, dt, n_pairs, seed=3001, frac_traj=0.6, frac_mix=0.
     log(f"train data: {Tin.size} DI labels in {time.time() - t1:.1f} s "
         f"({(~good).sum()} failed, dropped)")
     return (Tin[good], pin[good], np.ascontiguousarray(Yin[good]), Yg.cpu().numpy()[good],
-            kind[good])
+            kind[good], Tg.cpu().numpy()[good])
+
+
+def element_ratio_windows(mech):
+    """Element-ratio windows of the input envelope, after the paper's filters on
+    its training states (Sec. II.B: windows on the molar H/C and O/N ratios and
+    on the equivalence ratio), as coefficients over the element mass fractions
+    (a molar amount is a mass fraction over the atomic mass): H/C, O/N and the
+    elemental equivalence ratio (2 n_C + n_H / 2) / n_O, each where the
+    mechanism has the elements.  The bounds are placeholders until
+    chemk_ann_fit_envelope fits them to the training states."""
+    el = list(mech.elements)
+    A = np.asarray(mech.element_mass, np.float64)
+
+    def vec(**c):
+        v = np.zeros(len(el))
+        for e, x in c.items():
+            if e in el:
+                v[el.index(e)] = x / A[el.index(e)]
+        return v
+
+    out = []
+    if "H" in el and "C" in el:
+        out.append((vec(H=1.0), vec(C=1.0), 0.0, 0.0))
+    if "O" in el and "N" in el:
+        out.append((vec(O=1.0), vec(N=1.0), 0.0, 0.0))
+    if "O" in el and ("C" in el or "H" in el):
+        out.append((vec(C=2.0, H=0.5), vec(O=1.0), 0.0, 0.0))
+    return out
+
+
+# Defaults of the ANN path's admissibility checks (see chemk_ann_checks).
+ENV_Q = 1e-3          # envelope from the 0.1 % and 99.9 % quantiles of the training states
+ENV_WIDEN = 0.02      # ... widened by 2 % of that range on each side
+ADJ_MAX = 3.0         # largest accepted correction, in units of the training spread of dY
+NEG_TOL = 1e-6
 
 
 def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001,
-                  holdout=0.1, log=print):
-    """Fits the network on the DI pairs; returns a history dict."""
+                  holdout=0.1, log=print, mech=None, adj_max=ADJ_MAX, env_q=ENV_Q):
+    """Fits the network on the DI pairs; returns a history dict.  With `mech`
+    the input envelope gets the element-ratio windows; its box, those windows
+    and the dT window are fitted to the training split."""
     import torch
 
     dev = "cuda:0"
-    T, p, Y, Yn, kind = data
+    T, p, Y, Yn, kind, Tn = data
     n = T.size
     rng = np.random.default_rng(seed)
     perm = rng.permutation(n)
@@ -145,31 +183,32 @@ def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed
     ctx.ann_reset_optimizer()
     Td = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
           (("T", T[tr]), ("p", p[tr]), ("Y", Y[tr]), ("Yn", Yn[tr]))}
-    ctx.ann_fit_norm(Td["T"], Td["p"], Td["Y"], Td["Yn"], dt)
+    ctx.ann_fit_norm(Td["T"], Td["p"], Td["Y"], Td["Yn"], dt, neg_tol=NEG_TOL)
+    ctx.ann_set_checks(adj_max=adj_max, ratios=element_ratio_windows(mech) if mech is not None else ())
+    Tn_tr = torch.from_numpy(np.ascontiguousarray(Tn[tr])).to(dev)
+    ctx.ann_fit_envelope(Td["T"], Td["p"], Td["Y"], Tn_tr, q=env_q, widen=ENV_WIDEN)
+    del Tn_tr
     ntr = tr.size
     X = torch.empty((ntr, 64), dtype=torch.int16, device=dev)
     Z = torch.empty((ntr, K), dtype=torch.float32, device=dev)
     ctx.ann_pack(Td["T"], Td["p"], Td["Y"], Td["Yn"], X, Z)
-    steps_per_epoch = ntr // batch
-    total = steps_per_epoch * epochs
-    loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    hist = {"loss": [], "epochs": epochs, "batch": batch, "n_train": int(ntr),
-            "n_holdout": int(n_hold)}
+    Hd = [torch.from_numpy(np.ascontiguousarray(v[hold])).to(dev) for v in (T, p, Y, Yn)]
+    Xh = torch.empty((n_hold, 64), dtype=torch.int16, device=dev)
+    Zh = torch.empty((n_hold, K), dtype=torch.float32, device=dev)
+    if n_hold:
+        ctx.ann_pack(*Hd, Xh, Zh)
+    hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "n_holdout": int(n_hold)}
+    torch.cuda.synchronize()
     t0 = time.time()
-    step = 0
-    for ep in range(epochs):
-        order = torch.from_numpy(rng.permutation(ntr).astype(np.int32)).to(dev)
-        for b in range(steps_per_epoch):
-            lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * step / max(total, 1)))
-            idx = order[b * batch:(b + 1) * batch]
-            ctx.ann_train_step(idx, X, Z, lr, update=True, loss=loss if b == steps_per_epoch - 1
-                               else None)
-            step += 1
-        torch.cuda.synchronize()
-        hist["loss"].append(float(loss.item()))
-        if ep % 10 == 0 or ep == epochs - 1:
-            log(f"train: epoch {ep + 1}/{epochs} loss {hist['loss'][-1]:.4e} "
-                f"({time.time() - t0:.1f} s)")
+    # the whole loop (per-epoch device-side shuffles, cosine schedule, Adam,
+    # held-out loss) runs in the library: chemk_ann_train
+    el, hl = ctx.ann_train(X, Z, epochs, batch=batch, lr0=lr0, lr1=lr1, seed=seed,
+                           X_hold=Xh if n_hold else None, Z_hold=Zh if n_hold else None)
+    hist["loss"] = [float(v) for v in el]
+    hist["hold_loss"] = [float(v) for v in hl]
+    for ep in list(range(0, epochs, 10)) + [epochs - 1]:
+        log(f"train: epoch {ep + 1}/{epochs} loss {el[ep]:.4e} held-out {hl[ep]:.4e}")
+    step = (ntr // batch) * epochs
     hist["train_s"] = time.time() - t0
     hist["steps"] = step
     hist["holdout_index"] = hold
@@ -205,12 +244,27 @@ def evaluate(ctx, T, p, Y, Yn_ref):
 WEIGHTS = os.path.join(HERE, "weights", "mlp_medium.npz")
 
 
+def weights_path(mech):
+    """Stored network of a mechanism: mlp_medium.npz for the 32-species one,
+    mlp_large.npz for the 53-species one."""
+    name = {32: "medium", 53: "large"}.get(mech.K, f"K{mech.K}")
+    return os.path.join(HERE, "weights", f"mlp_{name}.npz")
+
+
 def save(ctx, path=WEIGHTS, extra=None):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     mx, sx, my, sy, dt = ctx.ann_get_norm()
     lo, hi, neg_tol = ctx.ann_get_envelope()
+    ck = ctx.ann_get_checks()
+    E = ctx.mech.E
+    rat = ck["ratios"]
     np.savez(path, params=ctx.ann_get_weights(), dims=np.array(ctx.dims), mu_x=mx, sd_x=sx,
-             mu_y=my, sd_y=sy, dt=dt, env_lo=lo, env_hi=hi, neg_tol=neg_tol, **(extra or {}))
+             mu_y=my, sd_y=sy, dt=dt, env_lo=lo, env_hi=hi, neg_tol=neg_tol,
+             ck_adj_max=ck["adj_max"], ck_dT=np.array(ck["dT"]),
+             ck_num=np.array([r[0] for r in rat]).reshape(len(rat), E),
+             ck_den=np.array([r[1] for r in rat]).reshape(len(rat), E),
+             ck_lo=np.array([r[2] for r in rat]), ck_hi=np.array([r[3] for r in rat]),
+             **(extra or {}))
 
 
 def load(ctx, path=WEIGHTS, neg_tol=None):
@@ -221,6 +275,10 @@ def load(ctx, path=WEIGHTS, neg_tol=None):
     if "env_lo" in d.files:
         nt = float(d["neg_tol"]) if neg_tol is None else neg_tol
         ctx.ann_set_envelope(d["env_lo"], d["env_hi"], nt)
+    if "ck_adj_max" in d.files:
+        ctx.ann_set_checks(adj_max=float(d["ck_adj_max"]), dT=tuple(d["ck_dT"]),
+                           ratios=[(d["ck_num"][j], d["ck_den"][j], d["ck_lo"][j], d["ck_hi"][j])
+                                   for j in range(d["ck_lo"].size)])
     return d
 
 
@@ -236,7 +294,7 @@ def load_or_train(ctx, mech, dt, log=print, n_pairs=None, epochs=None, path=WEIG
     n_pairs = n_pairs or int(os.environ.get("CHEMK_TRAIN_PAIRS", 2_000_000))
     epochs = epochs or int(os.environ.get("CHEMK_TRAIN_EPOCHS", 50))
     data = generate_pairs(ctx, mech, dt, n_pairs, log=log)
-    hist = train_network(ctx, data, dt, epochs=epochs, log=log)
+    hist = train_network(ctx, data, dt, epochs=epochs, log=log, mech=mech)
     mx, sx, my, sy, _ = ctx.ann_get_norm()
     save(ctx, path, extra={"loss": np.array(hist["loss"])})
     return True
@@ -260,20 +318,22 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=50)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--dt", type=float, default=5e-7)
-    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--mech", default="medium", choices=["medium", "large"])
+    ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
 
-    mech = sm.mech_medium()
+    mech = sm.mech_medium() if a.mech == "medium" else sm.mech_large()
+    a.out = a.out or weights_path(mech)
     ctx = chemk.Context(mech)
     t0 = time.time()
     data = generate_pairs(ctx, mech, a.dt, a.pairs, log=log)
     t_data = time.time() - t0
-    hist = train_network(ctx, data, a.dt, epochs=a.epochs, batch=a.batch, log=log)
+    hist = train_network(ctx, data, a.dt, epochs=a.epochs, batch=a.batch, log=log, mech=mech)
     save(ctx, a.out, extra={"loss": np.array(hist["loss"])})
-    T, p, Y, Yn, _ = data
+    T, p, Y, Yn = data[:4]
     hold = hist["holdout_index"]
     ev = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold])
     torch.cuda.synchronize()

@@ -18,7 +18,7 @@ The check compiles a HIP source to optimized device LLVM IR (the same flags as
 the library build), marks every SSA value derived from the lane index, from a
 cross-lane exchange (whose result is not bitwise identical across lanes) or
 from a load at a lane-dependent address, and treats readlane / readfirstlane
-results as uniform.  It then reports natural loops with a tainted exit that
+broadcasts and ballot masks (the same bits on every lane) as uniform.  It then reports natural loops with a tainted exit that
 contain a cross-lane operation, and tainted branches whose region up to the
 immediate post-dominator contains one.
 
@@ -40,7 +40,7 @@ CROSS_LANE = re.compile(r"@llvm\.amdgcn\.(readfirstlane|readlane|ds\.bpermute|ds
                         r"update\.dpp|mov\.dpp|wave\.barrier|s\.barrier|ds\.swizzle|permlane)")
 LANE_SOURCE = re.compile(r"@llvm\.amdgcn\.(workitem\.id|mbcnt|ds\.bpermute|ds\.permute|update\.dpp|"
                          r"mov\.dpp|ds\.swizzle|permlane)")
-BROADCAST = re.compile(r"@llvm\.amdgcn\.(readfirstlane|readlane)")
+BROADCAST = re.compile(r"@llvm\.amdgcn\.(readfirstlane|readlane|ballot)")
 
 
 def emit_ir(src, out):

@@ -59,3 +59,16 @@ __global__ void __launch_bounds__(64) exit_on_broadcast(const double *a, double 
     }
     out[lane] = x;
 }
+
+// A loop over groups of lanes that leaves when no lane's predicate holds: the
+// ballot of the predicate is the same mask on every lane.
+__global__ void __launch_bounds__(64) exit_on_ballot(const double *a, double *out) {
+    const int lane = threadIdx.x & 63;
+    double x = a[lane];
+    for (int it = 0; it < 8; ++it) {
+        x = 0.5 * (x + butterfly(x) / 64.0);
+        const bool more = x > 1.0;
+        if (!__ballot(more)) break;
+    }
+    out[lane] = x;
+}

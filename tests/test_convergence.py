@@ -32,6 +32,7 @@ def test_checker_flags_known_bad_shapes(tmp_path):
     assert not found("claim_all_lanes"), found("claim_all_lanes")
     assert found("exit_on_butterfly"), "loop exiting on a butterfly sum not flagged"
     assert not found("exit_on_broadcast"), found("exit_on_broadcast")
+    assert not found("exit_on_ballot"), found("exit_on_ballot")
 
 
 def test_library_kernels_keep_waves_converged(tmp_path):
