@@ -163,6 +163,25 @@ int chemk_advance(chemk_ctx *ctx, int64_t n, double *T, const double *p, double 
                   double dt, const chemk_opts *opts, int32_t *status, int32_t *nsteps,
                   void *stream);
 
+/* The advance for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * chemk_advance in DI mode, with the step's stiffness bins, queue and
+ * counters in a fixed device array of the library instead of the context's
+ * buffers.  The array (about 2 MiB) exists once per GPU and is held until the
+ * process ends; its address is looked up when a context is created.  The call
+ * allocates nothing: no hipMalloc/hipFree, no graph, no timing events
+ * (use_graph and phase timing are ignored; the step is enqueued eagerly).
+ * opts->mode must be CHEMK_MODE_DI and n at most CHEMK_NOALLOC_MAX_CELLS,
+ * else CHEMK_E_ARG.  Results equal chemk_advance's.  Every call on one GPU,
+ * from any context or thread, shares that GPU's array, which keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, threads)
+ * race, so the caller serialises them.  chemk_last_counters then reports this
+ * call's counters.                                                         */
+#define CHEMK_NOALLOC_MAX_CELLS 262144
+int chemk_advance_noalloc(chemk_ctx *ctx, int64_t n, double *T, const double *p, double *Y,
+                          double dt, const chemk_opts *opts, int32_t *status, int32_t *nsteps,
+                          void *stream);
+
 /* Stiffness-batching autotuner (the "bins / tile shape" choice of the DI
  * path): runs DI on COPIES of the n given cells for a small grid of
  * (stiffness bins, persistent waves per CU), times each with HIP events on

@@ -75,6 +75,8 @@ _SIGS = {
     "chemk_opts_default": (None, [C.POINTER(Opts)]),
     "chemk_advance": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts), _vp,
                                 _vp, _vp]),
+    "chemk_advance_noalloc": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts), _vp,
+                                        _vp, _vp]),
     "chemk_autotune": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts),
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp]),
     "chemk_last_counters": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp]),
@@ -230,6 +232,13 @@ class Context:
         n = T.numel() if n is None else n
         _check(lib.chemk_advance(self.handle, n, _ptr(T), _ptr(p), _ptr(Y), float(dt),
                                  C.byref(o), _ptr(status), _ptr(nsteps), _stream(stream)))
+
+    def advance_noalloc(self, T, p, Y, dt, status, nsteps=None, opts=None, stream=None, n=None):
+        """chemk_advance_noalloc: DI mode with the library's fixed scratch."""
+        o = opts if opts is not None else default_opts()
+        n = T.numel() if n is None else n
+        _check(lib.chemk_advance_noalloc(self.handle, n, _ptr(T), _ptr(p), _ptr(Y), float(dt),
+                                         C.byref(o), _ptr(status), _ptr(nsteps), _stream(stream)))
 
     def autotune(self, T, p, Y, dt, opts=None, stream=None):
         o = opts if opts is not None else default_opts()

@@ -10,6 +10,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -177,6 +178,7 @@ struct chemk_ctx {
     int *small = nullptr;                 // [0] counter, [1] n_items, [2..] hist/offs
     unsigned long long *stats = nullptr;  // [0] routed, [1] steps, [2] failed
     unsigned long long *last_stats = nullptr;   // where the last advance wrote its counters
+    void *noalloc = nullptr;              // this device's copy of the no-allocation scratch
     int tuned_bins = 0, tuned_wpc = 0;
     std::map<GraphKey, hipGraphExec_t> graphs;
     AnnState *ann = nullptr;
@@ -196,6 +198,36 @@ static int set_device(chemk_ctx *c) {
     HIP_TRY(hipSetDevice(c->device));
     return CHEMK_OK;
 }
+
+// ---------------------------------------------------------------------------
+// the DI advance without allocation: its scratch in a static device array
+// ---------------------------------------------------------------------------
+// Layout (bytes): statistics [4 u64] at 0, counters/histogram/offsets
+// [2 + 2 kMaxBins int] at kNaSmall, bins and queue [CHEMK_NOALLOC_MAX_CELLS
+// int each] after them.  Every GPU holds its own copy until the process ends.
+constexpr size_t kNaSmall = 256;
+constexpr size_t kNaBin = kNaSmall + ((sizeof(int) * (2 + 2 * kMaxBins) + 255) & ~size_t(255));
+constexpr size_t kNaQueue = kNaBin + sizeof(int) * CHEMK_NOALLOC_MAX_CELLS;
+constexpr size_t kNaBytes = kNaQueue + sizeof(int) * CHEMK_NOALLOC_MAX_CELLS;
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// The device address of this GPU's `scratch`, looked up once per device with
+// that device current (the array's name in host code is not a device address).
+static int noalloc_address(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    if (device < 0 || device >= 64) return fail(CHEMK_E_UNSUPPORTED, "device %d >= 64", device);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(CHEMK_E_HIP, "hipGetSymbolAddress returned a null address");
+        addr[device] = ptr;
+    }
+    *out = addr[device];
+    return CHEMK_OK;
+}
+
 
 extern "C" int chemk_ctx_create(int device, const chemk_mech *m, chemk_ctx **out) {
     g_err.clear();
@@ -315,6 +347,7 @@ extern "C" int chemk_ctx_create(int device, const chemk_mech *m, chemk_ctx **out
     dm.inc_nu = (const double *)(b + pcs[8].off);
     dm.Emat = (const double *)(b + pcs[9].off);
 
+    if (int r = noalloc_address(device, &c->noalloc)) return r;
     if (hipMalloc(&c->small, sizeof(int) * (2 + 2 * kMaxBins)) != hipSuccess ||
         hipMalloc(&c->stats, sizeof(unsigned long long) * 4) != hipSuccess)
         return fail(CHEMK_E_OOM, "hipMalloc of context counters failed");
@@ -567,6 +600,30 @@ extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p
     }
     HIP_TRY(hipGraphLaunch(it->second, s));
     return CHEMK_OK;
+}
+
+extern "C" int chemk_advance_noalloc(chemk_ctx *c, int64_t n, double *T, const double *p, double *Y,
+                                     double dt, const chemk_opts *o, int32_t *status, int32_t *nsteps,
+                                     void *stream) {
+    g_err.clear();
+    if (!c) return fail(CHEMK_E_ARG, "null context");
+    if (int r = check_n(n)) return r;
+    if (n > CHEMK_NOALLOC_MAX_CELLS)
+        return fail(CHEMK_E_ARG, "n=%lld above CHEMK_NOALLOC_MAX_CELLS=%d of the no-allocation advance",
+                    (long long)n, CHEMK_NOALLOC_MAX_CELLS);
+    if (int r = check_opts(o)) return r;
+    if (o->mode != CHEMK_MODE_DI) return fail(CHEMK_E_ARG, "the no-allocation advance is DI mode only");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEMK_E_ARG, "dt must be finite and > 0");
+    if (n == 0) return CHEMK_OK;
+    if (!T || !p || !Y || !status) return fail(CHEMK_E_ARG, "null array");
+    if (!c->noalloc) return fail(CHEMK_E_STATE, "no-allocation scratch not set up");
+    if (int r = set_device(c)) return r;
+    int bins, wpc;
+    resolve_tuning(c, o, bins, wpc);
+    unsigned char *base = static_cast<unsigned char *>(c->noalloc);
+    DiScratch w{reinterpret_cast<int *>(base + kNaBin), reinterpret_cast<int *>(base + kNaQueue),
+                reinterpret_cast<int *>(base + kNaSmall), reinterpret_cast<unsigned long long *>(base)};
+    return enqueue_di(c, w, n, T, p, Y, dt, o, bins, wpc, status, nsteps, (hipStream_t)stream, false);
 }
 
 extern "C" int chemk_last_counters(chemk_ctx *c, int64_t out[3], void *stream) {
