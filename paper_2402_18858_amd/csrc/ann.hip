@@ -760,9 +760,14 @@ constexpr int COLSUM_ROWS = 64;
 __global__ void colsum_part_kernel(const uint16_t *__restrict__ dZ, int B, int N, float *part) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= N) return;
-    const int b0 = blockIdx.y * COLSUM_ROWS, b1 = min(B, b0 + COLSUM_ROWS);
+    const int b0 = blockIdx.y * COLSUM_ROWS;
+    // a fixed trip count: the loads are issued back to back, then summed in order
+    float v[COLSUM_ROWS];
+#pragma unroll
+    for (int i = 0; i < COLSUM_ROWS; ++i) v[i] = b0 + i < B ? bf2f(dZ[(size_t)(b0 + i) * N + o]) : 0.f;
     float s = 0.f;
-    for (int b = b0; b < b1; ++b) s += bf2f(dZ[(size_t)b * N + o]);
+#pragma unroll
+    for (int i = 0; i < COLSUM_ROWS; ++i) s += v[i];
     part[(size_t)blockIdx.y * N + o] = s;
 }
 
@@ -770,6 +775,7 @@ __global__ void colsum_final_kernel(const float *__restrict__ part, int P, int N
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= N) return;
     float s = 0.f;
+#pragma unroll 16
     for (int y = 0; y < P; ++y) s += part[(size_t)y * N + o];
     db[o] = s;
 }
@@ -1329,9 +1335,18 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     if (tm) tm->begin(CHEMK_PHASE_POST, s);
     if ((e = launch_post(a, x, tp, s)) != hipSuccess) return e;
     if (tm) tm->end(CHEMK_PHASE_POST, s);
-    // DI on the routed cells
+    // DI on the routed cells, the most active stiffness bins first (the
+    // ingest's route flags are spent by now: their array takes the ordered
+    // queue)
     if (tm) tm->begin(CHEMK_PHASE_FALLBACK, s);
-    e = launch_di(m, x.di_grid, x.n_routed, x.queue, x.counter, x.T, x.p, x.Y, x.dt, x.rtol, x.atolY,
+    const int *dq = x.queue;
+    if (x.bins > 1) {
+        if ((e = launch_binning_list(m, n, x.n_routed, x.queue, x.T, x.p, x.Y, x.dt, x.bins, x.bin, x.hist,
+                                     x.offs, a->route, s)) != hipSuccess)
+            return e;
+        dq = a->route;
+    }
+    e = launch_di(m, x.di_grid, x.n_routed, dq, x.counter, x.T, x.p, x.Y, x.dt, x.rtol, x.atolY,
                   x.atolT, x.h0_frac, x.max_steps, x.project, x.status, x.nsteps, x.stats,
                   CHEMK_CELL_ROUTED_DI, s);
     if (tm) tm->end(CHEMK_PHASE_FALLBACK, s);

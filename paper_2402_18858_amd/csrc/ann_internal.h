@@ -24,6 +24,8 @@ struct AnnStepArgs {
     unsigned long long *stats;
     const chemk::DevMech *dm;
     chemk::PhaseTimer *timer;
+    int bins;                    // stiffness bins of the routed cells (<= 1: queue order)
+    int *bin, *hist, *offs;      // binning scratch: [n], [bins], [bins]
 };
 
 void ann_destroy(AnnState *a);

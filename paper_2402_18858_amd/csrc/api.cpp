@@ -545,7 +545,8 @@ extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p
             return enqueue_di(c, ctx_scratch(c), n, T, p, Y, dt, o, bins, wpc, status, nsteps, s);
         AnnStepArgs a{n, T, p, Y, dt, o->rtol, o->atol_Y, o->atol_T, o->h0_frac, o->max_steps,
                       o->project, status, nsteps, c->cu_count * wpc, c->queue, c->small,
-                      c->small + 1, c->stats, &c->dm, &c->timer};
+                      c->small + 1, c->stats, &c->dm, &c->timer, bins, c->bin, c->small + 2,
+                      c->small + 2 + kMaxBins};
         hipError_t e = ann_enqueue_step(c->ann, a, s);
         if (e != hipSuccess)
             return fail(CHEMK_E_HIP, "ANN step: %s", hipGetErrorString(e));

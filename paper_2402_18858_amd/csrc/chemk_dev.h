@@ -159,16 +159,14 @@ __device__ __forceinline__ void sp_cp_h(const double *a, double T, double invT, 
 struct Lds {
     double *C, *gRT, *hRT, *cpR;   // [64] each
     double *u, *tcol, *hs;         // [64] Jacobian assembly vectors
-    double *prow;                  // [64] pivot-row broadcast
+    double *w;                     // [64] net production rates (accumulated per reaction)
     int *piv;                      // [64]
-    double *q;                     // [R]
     double *J;                     // [ld * ld] Jacobian rows, leading dimension ld
     int ld;
 };
 
 __host__ __device__ inline int lds_doubles_per_wave(int K, int R, int ld) {
-    int r = (R + 1) & ~1;
-    return 8 * 64 + 32 + r + ld * ld;
+    return 8 * 64 + 32 + ld * ld;
 }
 
 __device__ __forceinline__ Lds carve_lds(double *base, int K, int R, int ld) {
@@ -180,10 +178,9 @@ __device__ __forceinline__ Lds carve_lds(double *base, int K, int R, int ld) {
     L.u = base + 256;
     L.tcol = base + 320;
     L.hs = base + 384;
-    L.prow = base + 448;
+    L.w = base + 448;
     L.piv = reinterpret_cast<int *>(base + 512);
-    L.q = base + 544;
-    L.J = L.q + ((R + 1) & ~1);
+    L.J = base + 544;
     L.ld = ld;
     return L;
 }
@@ -260,20 +257,23 @@ __device__ __forceinline__ double wave_rhs(const DevMech &m, const Lds &L, doubl
         L.C[lane] = c.rho * Yk * iw;
         L.gRT[lane] = t.hRT - t.sR;
     }
+    L.w[lane] = 0.0;
     wave_sync();
     const double lnPref = log(P0_CGS * c.invT / RU_CGS);
+    // each reaction adds its net rate to its participants' production rates
+    // (LDS atomics in a fixed lane and loop order)
 #pragma unroll 1
     for (int r = lane; r < m.R; r += WAVE) {
-        RxnEval e = rxn_eval(m, L, r, c, lnPref, m.rsp[r], m.rpar[r], m.rflag[r], false);
-        L.q[r] = e.qf - e.qr;
+        const int4 s4 = m.rsp[r];
+        RxnEval e = rxn_eval(m, L, r, c, lnPref, s4, m.rpar[r], m.rflag[r], false);
+        const double q = e.qf - e.qr;
+        atomicAdd(&L.w[s4.x], -q);
+        if (s4.y >= 0) atomicAdd(&L.w[s4.y], -q);
+        if (s4.z >= 0) atomicAdd(&L.w[s4.z], q);
+        if (s4.w >= 0) atomicAdd(&L.w[s4.w], q);
     }
     wave_sync();
-    double wk = 0.0;
-    if (sp) {
-        const int b = m.inc_start[lane], en = m.inc_start[lane + 1];
-#pragma unroll 4
-        for (int i = b; i < en; ++i) wk += m.inc_nu[i] * L.q[m.inc_r[i]];
-    }
+    const double wk = sp ? L.w[lane] : 0.0;
     const double chat = wave_sum(Yk * cpR * iw);     // sum_k Y_k (cp_k/R) / W_k
     const double Q = wave_sum(hRT * wk);             // sum_k (h_k/RT) omega_k
     wave_sync();
@@ -310,6 +310,7 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
         L.u[lane] = 0.0;
         L.tcol[lane] = 0.0;
         L.hs[lane] = 0.0;
+        L.w[lane] = 0.0;
 #pragma unroll 1
         for (int j = 0; j < K; ++j) L.J[lane * ld + j] = 0.0;
     }
@@ -321,7 +322,11 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
         const double4 pr = m.rpar[r];
         const int4 fl = m.rflag[r];
         RxnEval e = rxn_eval(m, L, r, c, lnPref, s4, pr, fl, true);
-        L.q[r] = e.qf - e.qr;
+        const double q = e.qf - e.qr;
+        atomicAdd(&L.w[s4.x], -q);
+        if (s4.y >= 0) atomicAdd(&L.w[s4.y], -q);
+        if (s4.z >= 0) atomicAdd(&L.w[s4.z], q);
+        if (s4.w >= 0) atomicAdd(&L.w[s4.w], q);
         const double dlnkf = (pr.y + pr.z * c.invT) * c.invT;
         const double dlnM = fl.x ? -c.invT : 0.0;
         const double dqdT = e.qf * (dlnkf + dlnM) - e.qr * (dlnkf - e.dlnKc_T + dlnM);
@@ -357,12 +362,7 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
         }
     }
     wave_sync();
-    double wk = 0.0;
-    if (sp) {
-        const int b = m.inc_start[lane], en = m.inc_start[lane + 1];
-#pragma unroll 4
-        for (int i = b; i < en; ++i) wk += m.inc_nu[i] * L.q[m.inc_r[i]];
-    }
+    const double wk = sp ? L.w[lane] : 0.0;
     const double uk = sp ? L.u[lane] : 0.0;
     const double tk = sp ? L.tcol[lane] : 0.0;
     const double chat = wave_sum(Yk * t.cpR * iw);

@@ -73,6 +73,11 @@ hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *
 hipError_t launch_binning(const DevMech &m, int n, const double *T, const double *p,
                           const double *Y, double dt, int bins, int *bin, int *hist, int *offs,
                           int *queue, hipStream_t s);
+// Binning of the cells idx[0 .. *count) (count on the device, at most n_max):
+// queue receives them ordered by the stiffness key, most active bin first.
+hipError_t launch_binning_list(const DevMech &m, int n_max, const int *count, const int *idx,
+                               const double *T, const double *p, const double *Y, double dt, int bins,
+                               int *bin, int *hist, int *offs, int *queue, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_set_int(int *p, int v, hipStream_t s);

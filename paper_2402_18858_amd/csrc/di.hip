@@ -494,6 +494,36 @@ __global__ void __launch_bounds__(64) stiffness_key_kernel(DevMech m, int n, con
     }
 }
 
+// The same key for the cells of a list: item i < *count is cell idx[i]
+// (the DI fallback's routed cells, whose number only the device knows).
+__global__ void __launch_bounds__(64) stiffness_key_list_kernel(DevMech m, const int *count, const int *idx,
+                                                                const double *T, const double *p,
+                                                                const double *Y, double dt, int bins,
+                                                                int *bin_out) {
+    extern __shared__ double lds[];
+    const Lds L = carve_lds(lds, m.K, m.R, 1);
+    const int lane = lane_id();
+    const int K = m.K;
+    const int cnt = uniform(*count);
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int c = uniform(idx[i]);
+        double y = 0.0;
+        if (lane < K) y = Y[(size_t)c * K + lane];
+        else if (lane == K) y = T[c];
+        const double f = wave_rhs(m, L, p[c] * PA_TO_CGS, y);
+        double act = lane < K ? fabs(f) * dt / (fabs(y) + 1e-8) : 0.0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) act = fmax(act, __shfl_xor(act, off, WAVE));
+        if (lane == 0) {
+            double lg = isfinite(act) ? log10(act + 1e-30) : 6.0;
+            double x = (6.0 - lg) / 12.0 * bins;
+            int b = (int)floor(x);
+            b = b < 0 ? 0 : (b >= bins ? bins - 1 : b);
+            bin_out[i] = b;
+        }
+    }
+}
+
 __global__ void zero_ints_kernel(int *p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -523,6 +553,27 @@ __global__ void scan_kernel(const int *hist, int bins, int *offs) {
             offs[b] = acc;
             acc += hist[b];
         }
+    }
+}
+
+__global__ void histogram_list_kernel(const int *bin, const int *count, int bins, int *hist) {
+    __shared__ int h[256];
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int n = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&h[bin[i]], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__global__ void scatter_list_kernel(const int *bin, const int *count, int *offs, const int *idx,
+                                    int *queue) {
+    const int n = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int pos = atomicAdd(&offs[bin[i]], 1);
+        queue[pos] = idx[i];
     }
 }
 
@@ -571,6 +622,22 @@ hipError_t launch_binning(const DevMech &m, int n, const double *T, const double
     hipLaunchKernelGGL(histogram_kernel, dim3(g), dim3(256), 0, s, bin, n, bins, hist);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, s, hist, bins, offs);
     hipLaunchKernelGGL(scatter_kernel, dim3(g), dim3(256), 0, s, bin, n, offs, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_binning_list(const DevMech &m, int n_max, const int *count, const int *idx,
+                               const double *T, const double *p, const double *Y, double dt, int bins,
+                               int *bin, int *hist, int *offs, int *queue, hipStream_t s) {
+    if (n_max <= 0) return hipSuccess;
+    const size_t lds = di_lds_bytes(m.K, m.R, 1);
+    const int grid_key = n_max < 8192 ? n_max : 8192;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, s, hist, bins);
+    hipLaunchKernelGGL(stiffness_key_list_kernel, dim3(grid_key), dim3(64), lds, s, m, count, idx, T, p, Y,
+                       dt, bins, bin);
+    const int g = (n_max + 255) / 256 < 1024 ? (n_max + 255) / 256 : 1024;
+    hipLaunchKernelGGL(histogram_list_kernel, dim3(g), dim3(256), 0, s, bin, count, bins, hist);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, s, hist, bins, offs);
+    hipLaunchKernelGGL(scatter_list_kernel, dim3(g), dim3(256), 0, s, bin, count, offs, idx, queue);
     return hipGetLastError();
 }
 

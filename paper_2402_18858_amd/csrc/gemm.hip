@@ -641,6 +641,7 @@ __global__ void splitk_reduce_kernel(const float *__restrict__ work, int split, 
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
          i += (long long)gridDim.x * blockDim.x) {
         float acc = 0.f;
+#pragma unroll 8
         for (int z = 0; z < split; ++z) acc += work[z * count + i];
         C[i] = acc;
     }
