@@ -51,10 +51,11 @@ def di_flops_per_step(K, R):
     return 6 * rhs + jac + 2.0 * N ** 3 / 3.0 + 6 * 2.0 * N * N
 
 
-def measured_traffic(key):
+def measured_traffic(key, routed=None):
     """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE
     runs summarised in profiles/traffic.json (scaled by the copy calibration),
-    or None when the kernel's sources changed since those counters were taken."""
+    or None when the kernel's sources changed since those counters were taken
+    (or, for the routed DI launch, when this run routes another number of cells)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -62,8 +63,11 @@ def measured_traffic(key):
     entry = json.load(open(path)).get(key)
     if not entry:
         return None
-    srcs = {"di_kernel": ("di.hip", "chemk_dev.h"), "gemm_layer2": ("gemm.hip",),
-            "mlp_forward": ("gemm.hip",)}[key]
+    if routed is not None and entry.get("routed_cells") != routed:
+        return None
+    srcs = {"di_kernel": ("di.hip", "chemk_dev.h"), "di_kernel_routed": ("di.hip", "chemk_dev.h"),
+            "gemm_layer2": ("gemm.hip",), "post_kernel": ("ann.hip",),
+            "ingest_kernel": ("ann.hip",)}[key]
     h = hashlib.sha1()
     for f in srcs:
         with open(os.path.join(ROOT, "paper_2402_18858_amd", "csrc", f), "rb") as fh:
@@ -186,6 +190,8 @@ def main():
     ap.add_argument("--envelope-sweep", action="store_true",
                     help="also refit the envelope for several quantiles q on regenerated training "
                          "data and report routed cells, step time and error for each")
+    ap.add_argument("--weights", default=None,
+                    help="network weights to load (train.py --out); default: the workload's stock file")
     ap.add_argument("--bins", type=int, default=0, help="fixed stiffness bins (skips the autotuner)")
     ap.add_argument("--wpc", type=int, default=0, help="fixed DI waves per CU (with --bins)")
     args = ap.parse_args()
@@ -217,7 +223,7 @@ def main():
     else:
         di_idx = np.arange(n)
     nd = di_idx.size
-    stock_counters = args.workload == "medium"      # the block the stored counters were taken on
+    stock_counters = args.workload == "medium" and not args.weights   # the run the stored counters were taken on
     Tin = torch.from_numpy(T0).to(dev)
     Yin = torch.from_numpy(Y0).to(dev)
     P = torch.from_numpy(p0).to(dev)
@@ -230,7 +236,12 @@ def main():
     if mode in ("auto", "ann"):
         try:
             from paper_2402_18858_amd import train
-            have_ann = train.load_or_train(ctx, mech, dt, log=log, path=train.weights_path(mech))
+            if args.weights:
+                train.load(ctx, args.weights)
+                log(f"ann: loaded {args.weights}")
+                have_ann = True
+            else:
+                have_ann = train.load_or_train(ctx, mech, dt, log=log, path=train.weights_path(mech))
         except Exception as e:  # noqa: BLE001 - reported, DI remains measurable
             log(f"ANN path unavailable ({e})")
             if mode == "ann":
@@ -316,6 +327,8 @@ def main():
               "unit": "cell-updates/s"}
     cfg = {"workload": f"{n} cells ({wl['nx']}^3 flame block) x {K} species / {mech.R} reactions, "
                        f"dt={dt:g} s", "cells": n, "species": K, "reactions": mech.R}
+    if args.weights:
+        cfg["weights"] = os.path.basename(args.weights)
     if mode == "di":
         result.update({"value": di_cups, "ms_per_step": 1e3 * wall_di / args.di_steps,
                        "steps": args.di_steps, "dtype": "f64",
@@ -379,7 +392,9 @@ def main():
         if fb_ms > mlp_ms and fb_steps > 0:
             fb_tf = fl_step * routed_ns.sum() / (fb_ms * 1e-3) / 1e12
             roof = {"bound": "alu", "achieved": fb_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": fb_tf / PEAK_FP64_TFLOPS, "traffic": None,
+                    "frac": fb_tf / PEAK_FP64_TFLOPS,
+                    "traffic": (measured_traffic("di_kernel_routed", int(routed_all.sum()))
+                                if stock_counters else None),
                     "kernel": f"di_kernel (N = {K + 1}) on the {int(routed_all.sum())} routed cells",
                     "flops_per_rodas_step": fl_step, "rodas_steps": float(routed_ns.sum()),
                     "mlp": roof_mlp}
