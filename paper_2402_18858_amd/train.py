@@ -56,41 +56,17 @@ def generate_pairs(ctx, mech, dt, n_pairs, seed=3001, frac_traj=0.6, frac_mix=0.
                    n_rec=200, t_end=2.5, log=print):
     """Returns host arrays (T, p, Y, Y_next, kind, T_next) of n_pairs DI-labelled
     pairs."""
-    import torch
-
     from synth import workload as sw
 
-    dev = "cuda:0"
     rng = np.random.default_rng(seed)
     n_traj_states = int(n_pairs * frac_traj)
     n_mix = int(n_pairs * frac_mix)
     n_blk = n_pairs - n_traj_states - n_mix
     n_traj = max(1, int(math.ceil(n_traj_states / n_rec)))
-    t0 = time.time()
-    # --- ignition trajectories (DI on the GPU) ---
-    T0, p0, Y0, phi = sw.ignition_initial_states(mech, n_traj, seed + 1)
-    T = torch.from_numpy(T0).to(dev)
-    Y = torch.from_numpy(Y0).to(dev)
-    P = torch.from_numpy(p0).to(dev)
-    st = torch.zeros(n_traj, dtype=torch.int32, device=dev)
-    times = np.geomspace(1e-6, t_end, n_rec)
-    recT, recY = [], []
-    t_prev = 0.0
-    for t in times:
-        _advance(ctx, T, P, Y, t - t_prev, st)
-        t_prev = t
-        recT.append(T.clone())
-        recY.append(Y.clone())
-    torch.cuda.synchronize()
-    TT = torch.stack(recT, 1).reshape(-1).cpu().numpy()
-    YY = torch.stack(recY, 1).reshape(-1, mech.K).cpu().numpy()
-    ok = np.repeat(st.cpu().numpy() == 0, n_rec)
+    TT, YY, ok, p0, _, burnt_T, burnt_Y = _trajectories(ctx, mech, n_traj, n_rec, t_end, seed, log)
     sel = rng.choice(np.nonzero(ok)[0], n_traj_states, replace=n_traj_states > ok.sum())
     Tt, Yt = sw.perturb_states(TT[sel], YY[sel], seed + 2)
-    log(f"train data: {n_traj} trajectories x {n_rec} records in {time.time() - t0:.1f} s")
     # --- mixing lines: cold fuel/air <-> burnt trajectory end states ---
-    burnt_T = recT[-1].cpu().numpy()
-    burnt_Y = recY[-1].cpu().numpy()
     j = rng.integers(0, n_traj, n_mix)
     Tc, _, Yc, _ = sw.ignition_initial_states(mech, n_mix, seed + 3, T0_range=(300.0, 600.0))
     c = rng.uniform(0.0, 1.0, n_mix)
@@ -112,11 +88,51 @@ def generate_pairs(ctx, mech, dt, n_pairs, seed=3001, frac_traj=0.6, frac_mix=0.
     kind = np.concatenate([np.zeros(len(Tt), np.int8), np.ones(n_mix, np.int8),
                            np.full(n_blk, 2, np.int8)])
     pin = np.full(Tin.size, p0[0])
-    # --- labels: DI over dt ---
+    return _label(ctx, dt, Tin, pin, Yin, kind, log)
+
+
+def _trajectories(ctx, mech, n_traj, n_rec, t_end, seed, log):
+    """0-D constant-pressure ignition trajectories from fuel/air (phi ~ U[0.5,
+    1.5], T0 ~ U[900, 1500] K) integrated by DI on the GPU and recorded on a
+    geometric time grid.  Returns the records flattened (T, Y), a mask of the
+    records of trajectories that finished, p0, phi, and the end states."""
+    import torch
+
+    from synth import workload as sw
+
+    dev = "cuda:0"
+    t0 = time.time()
+    T0, p0, Y0, phi = sw.ignition_initial_states(mech, n_traj, seed + 1)
+    T = torch.from_numpy(T0).to(dev)
+    Y = torch.from_numpy(Y0).to(dev)
+    P = torch.from_numpy(p0).to(dev)
+    st = torch.zeros(n_traj, dtype=torch.int32, device=dev)
+    times = np.geomspace(1e-6, t_end, n_rec)
+    recT, recY = [], []
+    t_prev = 0.0
+    for t in times:
+        _advance(ctx, T, P, Y, t - t_prev, st)
+        t_prev = t
+        recT.append(T.clone())
+        recY.append(Y.clone())
+    torch.cuda.synchronize()
+    TT = torch.stack(recT, 1).reshape(-1).cpu().numpy()
+    YY = torch.stack(recY, 1).reshape(-1, mech.K).cpu().numpy()
+    ok = np.repeat(st.cpu().numpy() == 0, n_rec)
+    log(f"train data: {n_traj} trajectories x {n_rec} records in {time.time() - t0:.1f} s")
+    return TT, YY, ok, p0, phi, recT[-1].cpu().numpy(), recY[-1].cpu().numpy()
+
+
+def _label(ctx, dt, Tin, pin, Yin, kind, log):
+    """DI over dt on the GPU for every state; failed cells are dropped.
+    Returns (T, p, Y, Y_next, kind, T_next)."""
+    import torch
+
+    dev = "cuda:0"
     t1 = time.time()
-    Tg = torch.from_numpy(Tin).to(dev)
+    Tg = torch.from_numpy(np.ascontiguousarray(Tin)).to(dev)
     Yg = torch.from_numpy(np.ascontiguousarray(Yin)).to(dev)
-    Pg = torch.from_numpy(pin).to(dev)
+    Pg = torch.from_numpy(np.ascontiguousarray(pin)).to(dev)
     stg = torch.zeros(Tin.size, dtype=torch.int32, device=dev)
     _advance(ctx, Tg, Pg, Yg, dt, stg)
     torch.cuda.synchronize()
@@ -125,6 +141,67 @@ def generate_pairs(ctx, mech, dt, n_pairs, seed=3001, frac_traj=0.6, frac_mix=0.
         f"({(~good).sum()} failed, dropped)")
     return (Tin[good], pin[good], np.ascontiguousarray(Yin[good]), Yg.cpu().numpy()[good],
             kind[good], Tg.cpu().numpy()[good])
+
+
+# Constraint windows of the paper's recipe for methane/air (Sec. II.B): molar
+# H/C and O/N of the perturbed states and their equivalence ratio.
+HFRD_HC = (2.65, 4.67)
+HFRD_ON = (0.254, 0.320)
+HFRD_PHI = (0.20, 1.15)
+
+
+def hfrd_windows(mech, phi_base):
+    """The recipe's windows for this mechanism: H/C and O/N as the paper gives
+    them for methane/air (the synthetic mechanisms burn CH4 in air; H/C only
+    where the mechanism has carbon), and the equivalence-ratio window widened
+    to the base states' range where that is wider (these trajectories reach
+    phi = 1.5, richer than the paper's flames)."""
+    el = list(mech.elements)
+    hc = HFRD_HC if ("C" in el and "H" in el) else None
+    phi = (min(HFRD_PHI[0], float(np.min(phi_base))), max(HFRD_PHI[1], float(np.max(phi_base))))
+    return [hc, HFRD_ON, phi]
+
+
+def generate_pairs_hfrd(ctx, mech, dt, n_pairs, seed=3001, frac_mix=0.1, n_rec=200, t_end=2.5,
+                        log=print):
+    """DI-labelled pairs by the paper's hybrid flamelet/random recipe (Sec.
+    II.B), with 0-D ignition trajectories standing in for the flamelet
+    solutions (no 1-D flame solver here):
+      * base states: the trajectory records (the same trajectories as
+        generate_pairs);
+      * perturbed states, 1 - frac_mix of the pairs: Eqs. 3-6 with alpha =
+        0.125, beta = 10, theta = 0.1, kept inside the H/C, O/N and
+        equivalence-ratio windows (hfrd_windows) and 300-3000 K;
+      * mixing line, frac_mix of the pairs: linear interpolation in T and Y
+        between the equilibrium end states of the leanest 1 % of the
+        trajectories and ambient air at 300 K (the paper's remedy for the
+        lean, air-diluted states of its flames);
+      * labels: DI over dt.
+    Returns the same tuple as generate_pairs (kind 0 perturbed, 1 mixing line)."""
+    from synth import workload as sw
+
+    rng = np.random.default_rng(seed + 7)
+    n_mix = int(n_pairs * frac_mix)
+    n_pert = n_pairs - n_mix
+    n_traj = max(1, int(math.ceil(0.6 * n_pairs / n_rec)))
+    TT, YY, ok, p0, phi, burnt_T, burnt_Y = _trajectories(ctx, mech, n_traj, n_rec, t_end, seed, log)
+    base = np.nonzero(ok)[0]
+    win = hfrd_windows(mech, phi)
+    t0 = time.time()
+    Tp, Pp, Yp, _ = sw.hfrd_states(mech, TT[base], np.repeat(p0, n_rec)[base], YY[base], n_pert,
+                                   seed + 8, win)
+    log(f"train data: {n_pert} perturbed states (windows {win}) in {time.time() - t0:.1f} s")
+    lean = np.argsort(phi)[:max(1, n_traj // 100)]
+    j = lean[rng.integers(0, lean.size, n_mix)]
+    Ta, Pa, Ya = sw.air_states(mech, n_mix, p=float(p0[0]))
+    c = rng.uniform(0.0, 1.0, n_mix)
+    Tm = (1 - c) * Ta + c * burnt_T[j]
+    Ym = (1 - c)[:, None] * Ya + c[:, None] * burnt_Y[j]
+    Tin = np.concatenate([Tp, Tm])
+    Yin = np.concatenate([Yp, Ym])
+    pin = np.concatenate([Pp, Pa])
+    kind = np.concatenate([np.zeros(n_pert, np.int8), np.ones(n_mix, np.int8)])
+    return _label(ctx, dt, Tin, pin, Yin, kind, log)
 
 
 def element_ratio_windows(mech):
@@ -320,6 +397,9 @@ def main(argv=None):
     ap.add_argument("--dt", type=float, default=5e-7)
     ap.add_argument("--mech", default="medium", choices=["medium", "large"])
     ap.add_argument("--out", default=None)
+    ap.add_argument("--recipe", default="cfg4", choices=["cfg4", "hfrd"],
+                    help="cfg4: noisy trajectories + mixing lines + flame-block states; "
+                         "hfrd: the paper's perturbation recipe (generate_pairs_hfrd)")
     a = ap.parse_args(argv)
 
     def log(m):
@@ -329,7 +409,8 @@ def main(argv=None):
     a.out = a.out or weights_path(mech)
     ctx = chemk.Context(mech)
     t0 = time.time()
-    data = generate_pairs(ctx, mech, a.dt, a.pairs, log=log)
+    gen = generate_pairs_hfrd if a.recipe == "hfrd" else generate_pairs
+    data = gen(ctx, mech, a.dt, a.pairs, log=log)
     t_data = time.time() - t0
     hist = train_network(ctx, data, a.dt, epochs=a.epochs, batch=a.batch, log=log, mech=mech)
     save(ctx, a.out, extra={"loss": np.array(hist["loss"])})
@@ -338,7 +419,7 @@ def main(argv=None):
     ev = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold])
     torch.cuda.synchronize()
     fl = 3 * mlp_flops_per_cell(ctx.dims) * a.batch * hist["steps"]
-    rep = {"pairs": int(T.size), "n_train": hist["n_train"], "n_holdout": hist["n_holdout"],
+    rep = {"recipe": a.recipe, "pairs": int(T.size), "n_train": hist["n_train"], "n_holdout": hist["n_holdout"],
            "epochs": a.epochs, "batch": a.batch, "data_s": t_data, "train_s": hist["train_s"],
            "train_tflops_wall": fl / hist["train_s"] / 1e12,
            "loss_first": hist["loss"][0], "loss_last": hist["loss"][-1],

@@ -180,3 +180,69 @@ def perturb_states(T, Y, seed, y_rel=0.05, t_abs=20.0):
     Yp = np.maximum(Y * (1.0 + y_rel * rng.standard_normal(Y.shape)), 0.0)
     Yp /= Yp.sum(1, keepdims=True)
     return T + t_abs * rng.standard_normal(T.shape), Yp
+
+
+def element_ratios(mech: Mechanism, Y):
+    """Molar H/C, O/N and elemental equivalence ratio (2 n_C + n_H / 2) / n_O of
+    mass fractions Y (n, K); a ratio whose elements the mechanism lacks is NaN."""
+    E = list(mech.elements)
+    n = (np.asarray(Y, np.float64) / mech.W[None, :]) @ mech.composition.astype(np.float64)
+    col = {e: n[:, E.index(e)] if e in E else np.zeros(len(n)) for e in ("C", "H", "O", "N")}
+    with np.errstate(divide="ignore", invalid="ignore"):
+        hc = col["H"] / col["C"] if "C" in E else np.full(len(n), np.nan)
+        on = col["O"] / col["N"]
+        phi = (2.0 * col["C"] + 0.5 * col["H"]) / col["O"]
+    return np.stack([hc, on, phi], 1)
+
+
+def hfrd_states(mech: Mechanism, T, p, Y, n, seed, windows, alpha=0.125, beta=10.0, theta=0.1,
+                T_range=(300.0, 3000.0), max_rounds=200):
+    """Random compositions around base states (T, p, Y) by the perturbation of
+    the hybrid flamelet/random data recipe (paper Sec. II.B, Eqs. 3-6), each
+    gamma ~ U[-1, 1] drawn per variable and state:
+        T' = T + alpha gamma (T_max - T_min)
+        p' = p + beta gamma (p_max - p_min)
+        Y'_N2 = Y_N2 + alpha gamma (Y_N2,max - Y_N2,min)
+        Y'_j = Y_j^(1 + theta gamma)   (every other species)
+    with the extremes taken over the base states; the mass fractions are then
+    normalised to unit sum.  A state is kept when its H/C, O/N and equivalence
+    ratio lie in ``windows`` (three (lo, hi) pairs, None to skip one; see
+    element_ratios) and T' in T_range; the rest are drawn again.  Returns
+    (T, p, Y) of n states and the indices of their base states."""
+    rng = np.random.default_rng(seed)
+    n2 = _species_vec_index(mech, N=2)
+    T, p, Y = np.asarray(T, np.float64), np.asarray(p, np.float64), np.asarray(Y, np.float64)
+    dT, dp, dn2 = T.max() - T.min(), p.max() - p.min(), Y[:, n2].max() - Y[:, n2].min()
+    outT, outP, outY, outB = [], [], [], []
+    got = 0
+    for _ in range(max_rounds):
+        if got >= n:
+            break
+        m = 2 * (n - got) + 64
+        b = rng.integers(0, T.size, m)
+        g = rng.uniform(-1.0, 1.0, (m, 3))
+        Tn = T[b] + alpha * g[:, 0] * dT
+        pn = p[b] + beta * g[:, 1] * dp
+        gy = rng.uniform(-1.0, 1.0, (m, mech.K))
+        Yn = np.power(np.maximum(Y[b], 0.0), 1.0 + theta * gy)
+        Yn[:, n2] = np.maximum(Y[b, n2] + alpha * g[:, 2] * dn2, 0.0)
+        Yn /= Yn.sum(1, keepdims=True)
+        r = element_ratios(mech, Yn)
+        ok = (Tn >= T_range[0]) & (Tn <= T_range[1])
+        for j, w in enumerate(windows):
+            if w is not None:
+                ok &= (r[:, j] >= w[0]) & (r[:, j] <= w[1])
+        outT.append(Tn[ok]); outP.append(pn[ok]); outY.append(Yn[ok]); outB.append(b[ok])
+        got += int(ok.sum())
+    if got < n:
+        raise RuntimeError(f"hfrd_states: {got} of {n} states inside the windows after {max_rounds} rounds")
+    T2, P2, Y2, B2 = (np.concatenate(a)[:n] for a in (outT, outP, outY, outB))
+    return T2, P2, np.ascontiguousarray(Y2), B2
+
+
+def air_states(mech: Mechanism, n, T=300.0, p=P_ATM):
+    """Ambient air (O2 + 3.76 N2 by moles) at temperature T."""
+    X = np.zeros((n, mech.K))
+    X[:, _species_vec_index(mech, O=2)] = 1.0
+    X[:, _species_vec_index(mech, N=2)] = 3.76
+    return np.full(n, T), np.full(n, p), _mole_to_mass(X, mech.W)
