@@ -99,8 +99,9 @@ def ann_vs_di(mech, sd_y, Y0, T_a, Y_a, st_a, T_d, Y_d, routed_bit):
             "max_norm_all_species": float(np.abs(e).max()),
             "rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(e * e, 0))],
             "max_norm": [round(float(v), 4) for v in np.abs(e).max(0)],
-            "network_cells_rms_norm": [round(float(v), 5) for v in np.sqrt(np.mean(en * en, 0))],
-            "network_cells_max_norm": [round(float(v), 4) for v in np.abs(en).max(0)],
+            "network_cells_rms_norm": ([round(float(v), 5) for v in np.sqrt(np.mean(en * en, 0))]
+                                       if en.size else None),
+            "network_cells_max_norm": [round(float(v), 4) for v in np.abs(en).max(0)] if en.size else None,
             "rms_abs": [float(f"{v:.3e}") for v in np.sqrt(np.mean((Y_a - Y_d) ** 2, 0))],
             "sd_dY_train": [float(f"{v:.3e}") for v in sd_y],
             "max_abs_T_K": float(np.abs(dT).max()),
@@ -192,6 +193,8 @@ def main():
                          "data and report routed cells, step time and error for each")
     ap.add_argument("--weights", default=None,
                     help="network weights to load (train.py --out); default: the workload's stock file")
+    ap.add_argument("--di-kernel", type=int, default=0, choices=[0, 1, 2],
+                    help="DI factorisation: 0 automatic, 1 LDS LU, 2 register LU")
     ap.add_argument("--bins", type=int, default=0, help="fixed stiffness bins (skips the autotuner)")
     ap.add_argument("--wpc", type=int, default=0, help="fixed DI waves per CU (with --bins)")
     args = ap.parse_args()
@@ -252,7 +255,7 @@ def main():
     if args.bins > 0:
         best_bins, best_wpc, tune_ms = args.bins, args.wpc or 8, 0.0
     else:
-        best_bins, best_wpc, tune_ms = ctx.autotune(TinD, PD, YinD, dt, chemk.default_opts(rtol=wl["rtol"]))
+        best_bins, best_wpc, tune_ms = ctx.autotune(TinD, PD, YinD, dt, chemk.default_opts(rtol=wl["rtol"], di_kernel=args.di_kernel))
     log(f"DI autotune -> bins={best_bins} waves/CU={best_wpc} ({tune_ms:.1f} ms)")
 
     def first_step(Ti, Pi, Yi, opts, k=1):
@@ -295,8 +298,9 @@ def main():
         return wall
 
     # ---- DI path -------------------------------------------------------------
-    o_di = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc, rtol=wl["rtol"])
-    o_di_g = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc, use_graph=1, rtol=wl["rtol"])
+    o_di = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc, rtol=wl["rtol"], di_kernel=args.di_kernel)
+    o_di_g = chemk.default_opts(bins=best_bins, waves_per_cu=best_wpc, use_graph=1, rtol=wl["rtol"],
+                                di_kernel=args.di_kernel)
     T_di, Y_di, st_di, ns_di, ph_di = first_step(TinD, PD, YinD, o_di)
     steps_total = float(ns_di.sum())
     di_kernel_ms = ph_di["di"][0] / max(ph_di["di"][1], 1)
@@ -311,7 +315,8 @@ def main():
                                                     float(np.percentile(ns_di, 99)), int(ns_di.max())],
                "kernel_ms": di_kernel_ms,
                "binning_ms": ph_di["binning"][0],
-               "tuning": {"bins": best_bins, "waves_per_cu": best_wpc},
+               "tuning": {"bins": best_bins, "waves_per_cu": best_wpc,
+                          "di_kernel": ["auto", "lds_lu", "reg_lu"][args.di_kernel]},
                "rtol": o_di.rtol, "atol_Y": o_di.atol_Y}
     roof_di = {"bound": "alu", "achieved": di_tflops, "peak": PEAK_FP64_TFLOPS,
                "unit": "TFLOP/s", "frac": di_tflops / PEAK_FP64_TFLOPS,
@@ -336,8 +341,10 @@ def main():
                        "roofline": roof_di, "di": di_info})
     else:
         o_ann = chemk.default_opts(mode=chemk.MODE_ANN, bins=best_bins, waves_per_cu=best_wpc,
+                                   di_kernel=args.di_kernel,
                                    rtol=wl["rtol"])
         o_ann_g = chemk.default_opts(mode=chemk.MODE_ANN, bins=best_bins, waves_per_cu=best_wpc,
+                                     di_kernel=args.di_kernel,
                                      use_graph=1, rtol=wl["rtol"])
         nsp = 5
         T_a, Y_a, st_a, ns_a, ph_a = first_step(Tin, P, Yin, o_ann, nsp)

@@ -144,7 +144,15 @@ typedef struct {
     int32_t waves_per_cu;    /* persistent DI residency; 0 = autotuned / default   */
     int32_t use_graph;       /* 1 = capture the whole step in a hipGraph and replay */
     int32_t project;         /* 1 = FP64 element projection of the output (default) */
+    int32_t di_kernel;       /* DI factorisation: CHEMK_DI_AUTO (default), CHEMK_DI_LDS_LU or
+                                CHEMK_DI_REG_LU; both give the same numbers            */
 } chemk_opts;
+
+/* DI kernel variants.  The LDS LU keeps the iteration matrix in the wave's
+ * LDS slice and handles any N = K + 1 <= 64; the register LU keeps each row in
+ * registers and exists for N = 10, 33 and 54 (CHEMK_DI_REG_LU on another N is
+ * CHEMK_E_ARG).  CHEMK_DI_AUTO takes the register LU where it exists.       */
+enum { CHEMK_DI_AUTO = 0, CHEMK_DI_LDS_LU = 1, CHEMK_DI_REG_LU = 2 };
 
 void chemk_opts_default(chemk_opts *opts);
 

@@ -19,6 +19,7 @@ OK, E_ARG, E_MECH, E_HIP, E_DT, E_OOM, E_STATE, E_UNSUPPORTED = range(8)
 CELL_OK, CELL_MAX_STEPS, CELL_T_RANGE, CELL_NONFINITE, CELL_NEWTON = 0, 1, 2, 3, 4
 CELL_SINGULAR, CELL_ROUTED_DI = 6, 8
 MODE_DI, MODE_ANN = 0, 1
+DI_AUTO, DI_LDS_LU, DI_REG_LU = 0, 1, 2
 
 
 class ChemkError(RuntimeError):
@@ -39,7 +40,7 @@ class Opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_steps", C.c_int32), ("rtol", C.c_double),
                 ("atol_Y", C.c_double), ("atol_T", C.c_double), ("h0_frac", C.c_double),
                 ("bins", C.c_int32), ("waves_per_cu", C.c_int32), ("use_graph", C.c_int32),
-                ("project", C.c_int32)]
+                ("project", C.c_int32), ("di_kernel", C.c_int32)]
 
 
 MAX_RATIOS, MAX_ELEMENTS = 4, 8

@@ -1348,7 +1348,7 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     }
     e = launch_di(m, x.di_grid, x.n_routed, dq, x.counter, x.T, x.p, x.Y, x.dt, x.rtol, x.atolY,
                   x.atolT, x.h0_frac, x.max_steps, x.project, x.status, x.nsteps, x.stats,
-                  CHEMK_CELL_ROUTED_DI, s);
+                  CHEMK_CELL_ROUTED_DI, x.di_kernel, s);
     if (tm) tm->end(CHEMK_PHASE_FALLBACK, s);
     return e;
 }

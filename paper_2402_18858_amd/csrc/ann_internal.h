@@ -16,7 +16,7 @@ struct AnnStepArgs {
     const double *p;
     double *Y;
     double dt, rtol, atolY, atolT, h0_frac;
-    int max_steps, project;
+    int max_steps, project, di_kernel;
     int32_t *status, *nsteps;
     int di_grid;
     int *queue;              // [n] routed cells

@@ -461,7 +461,7 @@ extern "C" void chemk_opts_default(chemk_opts *o) {
     o->project = 1;
 }
 
-static int check_opts(const chemk_opts *o) {
+static int check_opts(const chemk_ctx *c, const chemk_opts *o) {
     if (!o) return fail(CHEMK_E_ARG, "null options");
     if (o->mode != CHEMK_MODE_DI && o->mode != CHEMK_MODE_ANN)
         return fail(CHEMK_E_ARG, "mode=%d unknown", o->mode);
@@ -473,6 +473,10 @@ static int check_opts(const chemk_opts *o) {
         return fail(CHEMK_E_ARG, "bins=%d outside [0, %d]", o->bins, kMaxBins);
     if (o->waves_per_cu < 0 || o->waves_per_cu > 32)
         return fail(CHEMK_E_ARG, "waves_per_cu=%d outside [0, 32]", o->waves_per_cu);
+    if (o->di_kernel != CHEMK_DI_AUTO && o->di_kernel != CHEMK_DI_LDS_LU && o->di_kernel != CHEMK_DI_REG_LU)
+        return fail(CHEMK_E_ARG, "di_kernel=%d unknown", o->di_kernel);
+    if (o->di_kernel == CHEMK_DI_REG_LU && !di_has_reg_lu(c->dm.N))
+        return fail(CHEMK_E_ARG, "no register-LU DI kernel for N = %d (it exists for 10, 33, 54)", c->dm.N);
     return CHEMK_OK;
 }
 
@@ -510,7 +514,7 @@ static int enqueue_di(chemk_ctx *c, const DiScratch &w, int64_t n, double *T, co
     if (timed) c->timer.begin(CHEMK_PHASE_DI, s);
     HIP_TRY(launch_di(c->dm, (int)grid64, n_items, queue, counter, T, p, Y, dt, o->rtol,
                       o->atol_Y, o->atol_T, o->h0_frac, o->max_steps, o->project, status, nsteps,
-                      w.stats, 0, s));
+                      w.stats, 0, o->di_kernel, s));
     if (timed) c->timer.end(CHEMK_PHASE_DI, s);
     c->last_stats = w.stats;
     return CHEMK_OK;
@@ -522,7 +526,7 @@ extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p
     g_err.clear();
     if (!c) return fail(CHEMK_E_ARG, "null context");
     if (int r = check_n(n)) return r;
-    if (int r = check_opts(o)) return r;
+    if (int r = check_opts(c, o)) return r;
     if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEMK_E_ARG, "dt must be finite and > 0");
     if (n == 0) return CHEMK_OK;
     if (!T || !p || !Y || !status) return fail(CHEMK_E_ARG, "null array");
@@ -544,7 +548,7 @@ extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p
         if (o->mode == CHEMK_MODE_DI)
             return enqueue_di(c, ctx_scratch(c), n, T, p, Y, dt, o, bins, wpc, status, nsteps, s);
         AnnStepArgs a{n, T, p, Y, dt, o->rtol, o->atol_Y, o->atol_T, o->h0_frac, o->max_steps,
-                      o->project, status, nsteps, c->cu_count * wpc, c->queue, c->small,
+                      o->project, o->di_kernel, status, nsteps, c->cu_count * wpc, c->queue, c->small,
                       c->small + 1, c->stats, &c->dm, &c->timer, bins, c->bin, c->small + 2,
                       c->small + 2 + kMaxBins};
         hipError_t e = ann_enqueue_step(c->ann, a, s);
@@ -612,7 +616,7 @@ extern "C" int chemk_advance_noalloc(chemk_ctx *c, int64_t n, double *T, const d
     if (n > CHEMK_NOALLOC_MAX_CELLS)
         return fail(CHEMK_E_ARG, "n=%lld above CHEMK_NOALLOC_MAX_CELLS=%d of the no-allocation advance",
                     (long long)n, CHEMK_NOALLOC_MAX_CELLS);
-    if (int r = check_opts(o)) return r;
+    if (int r = check_opts(c, o)) return r;
     if (o->mode != CHEMK_MODE_DI) return fail(CHEMK_E_ARG, "the no-allocation advance is DI mode only");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEMK_E_ARG, "dt must be finite and > 0");
     if (n == 0) return CHEMK_OK;
@@ -675,7 +679,7 @@ extern "C" int chemk_autotune(chemk_ctx *c, int64_t n, const double *T, const do
     g_err.clear();
     if (!c || !best) return fail(CHEMK_E_ARG, "null argument");
     if (int r = check_n(n)) return r;
-    if (int r = check_opts(o)) return r;
+    if (int r = check_opts(c, o)) return r;
     if (n == 0 || !T || !p || !Y) return fail(CHEMK_E_ARG, "autotune needs cells");
     if (int r = set_device(c)) return r;
     if (int r = ensure_capacity(c, n)) return r;

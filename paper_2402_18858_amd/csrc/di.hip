@@ -152,6 +152,101 @@ __device__ __forceinline__ double wave_solve(const Lds &L, int n, int src, doubl
     return in ? z : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident LU for a system of fixed size NT (instantiated for the
+// sizes of the shipped mechanisms).  The rows stay in place (implicit partial
+// pivoting, as above) but lane p keeps row p in NT registers: the loops over
+// columns are unrolled, so every column index is a register index and the
+// elimination reads only the pivot row from LDS (one broadcast read per two
+// columns).  At step k the pivot lane writes its U row (columns > k) into its
+// LDS row, which was cleared beforehand.  Afterwards each lane keeps its L
+// multipliers (columns < its step) in registers and zeros elsewhere, and its
+// LDS row holds U strictly right of the diagonal and zeros elsewhere, so the
+// forward and backward sweeps need no lane masks.  The matrix factorised is
+// A = J - fac I, the negated iteration matrix: the multipliers and pivots
+// are exactly those of the LDS LU of fac I - J, with signs flipped where
+// they enter, so both paths give the same numbers.
+// ---------------------------------------------------------------------------
+template <int NT>
+struct RegLU {
+    double a[NT];    // L multipliers of this lane's row (columns < its step), else 0
+    double rdiag;    // 1 / U diagonal of this lane's row (lanes < NT)
+    int pk[NT];      // lane of the row chosen at step k (wave-uniform)
+    int src;         // lane of the row chosen at step `lane` (lanes < NT)
+};
+
+template <int NT>
+__device__ __forceinline__ bool reg_lu(const Lds &L, double fac, RegLU<NT> &f) {
+    const int lane = lane_id();
+    const bool in = lane < NT;
+    double *row = L.J + (in ? lane : 0) * L.ld;
+    if (in) {
+        row[lane] -= fac;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) f.a[c] = row[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NT; ++c) f.a[c] = 0.0;
+    }
+    wave_sync();
+    if (in) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c) row[c] = 0.0;
+    }
+    wave_sync();
+    double *diag = L.tcol;   // free between the Jacobian and the next one
+    int mystep = in ? NT : -1;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int p = wave_argmax(fabs(f.a[k]), mystep == NT);
+        f.pk[k] = p;
+        const double pv = bcast(f.a[k], p);
+        if (pv == 0.0) ok = false;
+        if (lane == p) {
+            mystep = k;
+            diag[lane] = pv;
+            L.piv[k] = lane;
+#pragma unroll
+            for (int c = k + 1; c < NT; ++c) row[c] = f.a[c];
+        }
+        wave_sync();
+        if (mystep == NT) {
+            const double *prow = L.J + p * L.ld;
+            const double l = f.a[k] / pv;
+            f.a[k] = l;
+#pragma unroll
+            for (int c = k + 1; c < NT; ++c) f.a[c] = f.a[c] - l * prow[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+        if (c >= mystep) f.a[c] = 0.0;
+    f.rdiag = in ? 1.0 / diag[lane] : 0.0;
+    f.src = in ? L.piv[lane] : 0;
+    wave_sync();
+    return ok;
+}
+
+// Solve (fac I - J) x = b with the factors of reg_lu; b is this lane's
+// component, x_i is returned in lane i.
+template <int NT>
+__device__ __forceinline__ double reg_solve(const Lds &L, const RegLU<NT> &f, double b) {
+    const int lane = lane_id();
+    const bool in = lane < NT;
+    double acc = in ? -b : 0.0;
+    // forward (L y = P(-b)): lane p accumulates until its own step broadcasts it
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc = acc - f.a[k] * bcast(acc, f.pk[k]);
+    // backward (U x = y): U rows from LDS, zero left of and on the diagonal
+    const double *row = L.J + (in ? lane : 0) * L.ld;
+#pragma unroll
+    for (int k = NT - 1; k >= 0; --k) acc = acc - row[k] * bcast(acc * f.rdiag, f.pk[k]);
+    const double x = acc * f.rdiag;   // the unknown of this lane's step
+    const double r = __shfl(x, f.src, WAVE);
+    return in ? r : 0.0;
+}
+
 struct DIParams {
     double rtol, atolY, atolT, h0_frac;
     int max_steps, project;
@@ -278,10 +373,14 @@ __device__ __forceinline__ int wave_T_from_h(const DevMech &m, double h0R, doubl
 }
 
 // Integrate one cell over dt.  y: this lane's component (in/out).  Returns the
-// cell status; nsteps receives the number of attempted steps.
-// Integrate one cell over dt.  y: this lane's component (in/out).  Returns the
 // cell status; nsteps receives the number of attempted steps.  All loop
 // control (t, h, error, counters) is wave-uniform by construction.
+// NT > 0 factorises with the register-resident LU of size NT (= K + 1), NT = 0
+// with the LDS LU of any size; both give the same numbers.  The six stages
+// run as one loop (one copy of the right-hand side and of the solve in the
+// code), the stage sums taken over all earlier stages with the published
+// coefficients (zero past the stage's own).
+template <int NT>
 __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, double dt,
                        const DIParams &o, int &nsteps) {
     const int lane = lane_id();
@@ -293,12 +392,12 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
     double h0R, cdummy;
     wave_h_cp(m, bcast(y, K), lane < K ? y : 0.0, h0R, cdummy);
 
-    double u0, u1, u2, u3, u4, u5;
     double f0 = 0.0;
     double t = 0.0, h = o.h0_frac * dt;
-    bool need_jac = true, rejected = false;
+    bool rejected = false;
     int nst = 0, status = 0;
     int mystep = -1;
+    RegLU<(NT > 0 ? NT : 1)> f;
 #pragma unroll 1
     for (int guard = 0; guard <= o.max_steps; ++guard) {
         if (!(t < dt)) break;
@@ -315,52 +414,70 @@ __device__ int di_cell(const DevMech &m, const Lds &L, double p_cgs, double &y, 
             status = CHEMK_CELL_MAX_STEPS;
             break;
         }
-        if (need_jac) {
-            f0 = wave_f_jac(m, L, p_cgs, y);
-            need_jac = false;
-        }
+        // the Jacobian at y (a rejected step re-evaluates it, as the method's
+        // order conditions assume the exact J at the step's start)
+        f0 = wave_f_jac(m, L, p_cgs, y);
         ++nst;
-        // iteration matrix fac I - J in place of J (a rejected step re-evaluates J)
         const double fac = 1.0 / (h * kGamma);
-        if (act) {
-            double *row = L.J + lane * L.ld;
-            row[lane] = fac - row[lane];
+        int src = 0;
+        double rdiag = 0.0;
+        if constexpr (NT > 0) {
+            if (!reg_lu<NT>(L, fac, f)) {
+                status = CHEMK_CELL_SINGULAR;
+                break;
+            }
+        } else {
+            // iteration matrix fac I - J in place of J
+            if (act) {
+                double *row = L.J + lane * L.ld;
+                row[lane] = fac - row[lane];
 #pragma unroll 1
-            for (int j = 0; j < Na; ++j)
-                if (j != lane) row[j] = -row[j];
+                for (int j = 0; j < Na; ++j)
+                    if (j != lane) row[j] = -row[j];
+            }
+            wave_sync();
+            if (!wave_lu(L, Na, mystep)) {
+                status = CHEMK_CELL_SINGULAR;
+                break;
+            }
+            // lanes past the system read row 0 (in the slice; their results are unused)
+            src = act ? L.piv[lane] : 0;
+            rdiag = act ? 1.0 / L.J[src * L.ld + lane] : 0.0;
         }
-        wave_sync();
-        need_jac = true;
-        if (!wave_lu(L, Na, mystep)) {
-            status = CHEMK_CELL_SINGULAR;
-            break;
-        }
-        // lanes past the system read row 0 (in the slice; their results are unused)
-        const int src = act ? L.piv[lane] : 0;
-        const double rdiag = act ? 1.0 / L.J[src * L.ld + lane] : 0.0;
         const double ih = 1.0 / h;
-        u0 = wave_solve(L, Na, src, rdiag, f0);
-        double yt = y + kA[1][0] * u0;
-        double fs = wave_rhs(m, L, p_cgs, yt);
-        u1 = wave_solve(L, Na, src, rdiag, fs + kC[1][0] * ih * u0);
-        yt = y + kA[2][0] * u0 + kA[2][1] * u1;
-        fs = wave_rhs(m, L, p_cgs, yt);
-        u2 = wave_solve(L, Na, src, rdiag, fs + ih * (kC[2][0] * u0 + kC[2][1] * u1));
-        yt = y + kA[3][0] * u0 + kA[3][1] * u1 + kA[3][2] * u2;
-        fs = wave_rhs(m, L, p_cgs, yt);
-        u3 = wave_solve(L, Na, src, rdiag,
-                        fs + ih * (kC[3][0] * u0 + kC[3][1] * u1 + kC[3][2] * u2));
-        yt = y + kA[4][0] * u0 + kA[4][1] * u1 + kA[4][2] * u2 + kA[4][3] * u3;
-        fs = wave_rhs(m, L, p_cgs, yt);
-        u4 = wave_solve(
-            L, Na, src, rdiag,
-            fs + ih * (kC[4][0] * u0 + kC[4][1] * u1 + kC[4][2] * u2 + kC[4][3] * u3));
-        yt = yt + u4;   // embedded (order 3) solution
-        fs = wave_rhs(m, L, p_cgs, yt);
-        u5 = wave_solve(L, Na, src, rdiag,
-                        fs + ih * (kC[5][0] * u0 + kC[5][1] * u1 + kC[5][2] * u2 +
-                                   kC[5][3] * u3 + kC[5][4] * u4));
-        const double ynew = yt + u5;
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0, u4 = 0.0, u5 = 0.0;
+        double yt = y;
+#pragma unroll 1
+        for (int s = 0; s < 6; ++s) {
+            double rhs = f0;
+            if (s > 0) {
+                yt = y;
+                yt += kA[s][0] * u0;
+                yt += kA[s][1] * u1;
+                yt += kA[s][2] * u2;
+                yt += kA[s][3] * u3;
+                yt += kA[s][4] * u4;
+                const double fs = wave_rhs(m, L, p_cgs, yt);
+                double cs = kC[s][0] * u0;
+                cs += kC[s][1] * u1;
+                cs += kC[s][2] * u2;
+                cs += kC[s][3] * u3;
+                cs += kC[s][4] * u4;
+                rhs = fs + ih * cs;
+            }
+            double us;
+            if constexpr (NT > 0) us = reg_solve<NT>(L, f, rhs);
+            else us = wave_solve(L, Na, src, rdiag, rhs);
+            switch (s) {
+                case 0: u0 = us; break;
+                case 1: u1 = us; break;
+                case 2: u2 = us; break;
+                case 3: u3 = us; break;
+                case 4: u4 = us; break;
+                default: u5 = us; break;
+            }
+        }
+        const double ynew = yt + u5;   // yt: the embedded (order 3) solution of the last stage
         const double sc = atol + o.rtol * fmax(fabs(y), fabs(ynew));
         const double e = act ? u5 / sc : 0.0;
         const double err = uniform_d(sqrt(wave_sum(e * e) / Na));
@@ -417,6 +534,8 @@ __host__ __device__ inline int di_slice_doubles(int K, int R) {
 }
 
 // Persistent DI kernel: waves pull items from the queue until it is drained.
+// NT: the register-resident LU's size (K + 1), or 0 for the LDS LU.
+template <int NT>
 __global__ void __launch_bounds__(64 * kDiWavesPerBlock) di_kernel(DevMech m, const int *__restrict__ n_items_p,
                                                 const int *__restrict__ queue, int *counter,
                                                 double *T, const double *p, double *Y,
@@ -450,7 +569,7 @@ __global__ void __launch_bounds__(64 * kDiWavesPerBlock) di_kernel(DevMech m, co
         if (lane < K) y = Y[(size_t)c * K + lane];
         else if (lane == K) y = T[c];
         int ns = 0;
-        const int st = di_cell(m, L, p[c] * PA_TO_CGS, y, dt, o, ns);
+        const int st = di_cell<NT>(m, L, p[c] * PA_TO_CGS, y, dt, o, ns);
         if (lane < K) Y[(size_t)c * K + lane] = y;
         else if (lane == K) T[c] = y;
         if (lane == 0) {
@@ -589,6 +708,10 @@ __global__ void scatter_kernel(const int *bin, int n, int *offs, int *queue) {
 // ---------------------------------------------------------------------------
 int di_template_N(int Nreal) { return Nreal >= 2 && Nreal <= 64 ? Nreal : -1; }
 
+// System sizes with a register-resident LU instance (N = K + 1 of the 9-, 32-
+// and 53-species mechanisms).
+bool di_has_reg_lu(int N) { return N == 10 || N == 33 || N == 54; }
+
 size_t di_block_lds_bytes(int K, int R) {
     return sizeof(double) * (size_t)di_slice_doubles(K, R) * kDiWavesPerBlock;
 }
@@ -601,12 +724,20 @@ hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *
                      int *counter, double *T, const double *p, double *Y, double dt,
                      double rtol, double atolY, double atolT, double h0_frac, int max_steps,
                      int project, int *status, int *nsteps, unsigned long long *stats,
-                     int status_or, hipStream_t s) {
+                     int status_or, int variant, hipStream_t s) {
     DIParams o{rtol, atolY, atolT, h0_frac, max_steps, project};
     const size_t lds = di_block_lds_bytes(m.K, m.R);
     const int blocks = (grid + kDiWavesPerBlock - 1) / kDiWavesPerBlock;
-    hipLaunchKernelGGL(di_kernel, dim3(blocks), dim3(64 * kDiWavesPerBlock), lds, s, m, n_items,
-                       queue, counter, T, p, Y, dt, o, status, nsteps, stats, status_or);
+    const bool reg = variant != CHEMK_DI_LDS_LU && di_has_reg_lu(m.N);
+    if (variant == CHEMK_DI_REG_LU && !reg) return hipErrorInvalidValue;
+#define CHEMK_LAUNCH_DI(NT)                                                                    \
+    hipLaunchKernelGGL(di_kernel<NT>, dim3(blocks), dim3(64 * kDiWavesPerBlock), lds, s, m,    \
+                       n_items, queue, counter, T, p, Y, dt, o, status, nsteps, stats, status_or)
+    if (!reg) CHEMK_LAUNCH_DI(0);
+    else if (m.N == 10) CHEMK_LAUNCH_DI(10);
+    else if (m.N == 33) CHEMK_LAUNCH_DI(33);
+    else CHEMK_LAUNCH_DI(54);
+#undef CHEMK_LAUNCH_DI
     return hipGetLastError();
 }
 

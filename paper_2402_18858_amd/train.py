@@ -162,13 +162,17 @@ def hfrd_windows(mech, phi_base):
     return [hc, HFRD_ON, phi]
 
 
-def generate_pairs_hfrd(ctx, mech, dt, n_pairs, seed=3001, frac_mix=0.1, n_rec=200, t_end=2.5,
-                        log=print):
+def generate_pairs_hfrd(ctx, mech, dt, n_pairs, seed=3001, frac_mix=0.1, frac_block=0.3, n_rec=200,
+                        t_end=2.5, log=print):
     """DI-labelled pairs by the paper's hybrid flamelet/random recipe (Sec.
     II.B), with 0-D ignition trajectories standing in for the flamelet
     solutions (no 1-D flame solver here):
       * base states: the trajectory records (the same trajectories as
-        generate_pairs);
+        generate_pairs) and, for the preheat zone of a flamelet, each
+        trajectory's fresh mixture at temperatures between 300 K and its
+        initial temperature (a quarter as many states as records), and
+        frac_block * n_pairs flame-block states drawn with generate_pairs'
+        seeds;
       * perturbed states, 1 - frac_mix of the pairs: Eqs. 3-6 with alpha =
         0.125, beta = 10, theta = 0.1, kept inside the H/C, O/N and
         equivalence-ratio windows (hfrd_windows) and 300-3000 K;
@@ -186,10 +190,31 @@ def generate_pairs_hfrd(ctx, mech, dt, n_pairs, seed=3001, frac_mix=0.1, n_rec=2
     n_traj = max(1, int(math.ceil(0.6 * n_pairs / n_rec)))
     TT, YY, ok, p0, phi, burnt_T, burnt_Y = _trajectories(ctx, mech, n_traj, n_rec, t_end, seed, log)
     base = np.nonzero(ok)[0]
+    # the preheat side of a premixed flamelet, which the ignition records lack:
+    # the fresh mixture of each trajectory between 300 K and its initial T
+    n_pre = n_rec // 4
+    T0 = TT.reshape(n_traj, n_rec)[:, 0]
+    Y0 = YY.reshape(n_traj, n_rec, -1)[:, 0]
+    Tpre = 300.0 + (T0 - 300.0)[:, None] * rng.uniform(0.0, 1.0, (n_traj, n_pre))
+    # flame-block states with the seeds generate_pairs uses: the synthetic
+    # counterpart of the paper's flamelet solutions, which come from the same
+    # flames as the states to be predicted (here the block's cold, front and
+    # burnt cells and their minor-species content)
+    n_blk = int(frac_block * n_pairs)
+    Tb_l, Yb_l = [], []
+    got, s_ = 0, seed + 100
+    while got < n_blk:
+        Tb, _, Yb, _ = sw.flame_block(mech, 32, s_)
+        Tb_l.append(Tb)
+        Yb_l.append(Yb)
+        got += Tb.size
+        s_ += 1
+    bT = np.concatenate([TT[base], Tpre.reshape(-1)] + Tb_l)[:base.size + Tpre.size + n_blk]
+    bY = np.concatenate([YY[base], np.repeat(Y0, n_pre, 0)] + Yb_l)[:bT.size]
+    bP = np.full(bT.size, float(p0[0]))
     win = hfrd_windows(mech, phi)
     t0 = time.time()
-    Tp, Pp, Yp, _ = sw.hfrd_states(mech, TT[base], np.repeat(p0, n_rec)[base], YY[base], n_pert,
-                                   seed + 8, win)
+    Tp, Pp, Yp, _ = sw.hfrd_states(mech, bT, bP, bY, n_pert, seed + 8, win)
     log(f"train data: {n_pert} perturbed states (windows {win}) in {time.time() - t0:.1f} s")
     lean = np.argsort(phi)[:max(1, n_traj // 100)]
     j = lean[rng.integers(0, lean.size, n_mix)]

@@ -175,3 +175,52 @@ def test_di_medium_block_parity_at_full_size():
     announce(f"medium: max rel Y {ry:.3e}, |dT| {dT:.3e} K, mean steps {ns.mean():.1f}")
     assert ry < 1e-6 and dT < 1e-4
     assert _conservation(mech, Y, Yg) < 1e-12
+
+
+@pytest.mark.parametrize("which", ["small", "medium", "large"])
+def test_di_register_lu_equals_lds_lu(which):
+    """The register-resident LU (N = 10, 33, 54) and the LDS LU factorise the
+    same matrix with the same operations: the advance must agree bitwise,
+    step counts and status included."""
+    from paper_2402_18858_amd import chemk
+    mech = getattr(sm, f"mech_{which}")()
+    ctx = chemk.Context(mech)
+    if which == "small":
+        T, p, Y = sw.uniform_cells(mech, 300, 79)
+        dt = 1e-6
+    else:
+        T, p, Y, region = sw.flame_block(mech, 16, 2003 if which == "medium" else 2006)
+        keep = np.concatenate([np.nonzero(region == r)[0][:100 if which == "large" else 400]
+                               for r in range(3)])
+        T, p, Y = T[keep], p[keep], np.ascontiguousarray(Y[keep])
+        dt = 5e-7
+    announce(f"register LU vs LDS LU: {which}, {T.size} cells")
+    a = _run(ctx, T, p, Y, dt, di_kernel=chemk.DI_LDS_LU)
+    b = _run(ctx, T, p, Y, dt, di_kernel=chemk.DI_REG_LU)
+    c = _run(ctx, T, p, Y, dt)
+    assert (a[2] == 0).all(), np.unique(a[2], return_counts=True)
+    for x, y_ in zip(a, b):
+        assert np.array_equal(x, y_)
+    for x, y_ in zip(b, c):
+        assert np.array_equal(x, y_)
+    announce(f"register LU vs LDS LU: {which} bitwise equal, mean steps {a[3].mean():.1f}")
+
+
+def test_di_register_lu_unavailable_size_is_an_argument_error():
+    """A mechanism whose N has no register instance: auto falls back to the
+    LDS LU, an explicit request is CHEMK_E_ARG."""
+    from paper_2402_18858_amd import chemk
+    from tests import mechs
+    mech = mechs.tiny_hox()
+    ctx = chemk.Context(mech)
+    n = 8
+    T = np.full(n, 1500.0)
+    p = np.full(n, 101325.0)
+    Y = np.full((n, mech.K), 1.0 / mech.K)
+    a = _run(ctx, T, p, Y, 1e-7, di_kernel=chemk.DI_LDS_LU)
+    b = _run(ctx, T, p, Y, 1e-7)
+    for x, y_ in zip(a, b):
+        assert np.array_equal(x, y_)
+    with pytest.raises(chemk.ChemkError) as e:
+        _run(ctx, T, p, Y, 1e-7, di_kernel=chemk.DI_REG_LU)
+    assert e.value.code == chemk.E_ARG
