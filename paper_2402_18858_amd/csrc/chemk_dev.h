@@ -19,6 +19,7 @@ constexpr double RU_SI = 8.31446261815324;           // J/(mol K)
 constexpr double RC_CAL = 8.31446261815324 / 4.184;  // cal/(mol K)
 constexpr double P0_CGS = 101325.0 * 10.0;           // standard pressure, dyn/cm^2
 constexpr double PA_TO_CGS = 10.0;                   // Pa -> dyn/cm^2
+constexpr double LN_P0_RU = -4.407418589020958141;   // ln(P0_CGS / RU_CGS)
 
 // Mechanism tables in device memory.
 struct DevMech {
@@ -169,18 +170,21 @@ __host__ __device__ inline int lds_doubles_per_wave(int K, int R, int ld) {
     return 8 * 64 + 32 + ld * ld;
 }
 
+// The matrix comes first, so that a row's columns sit within the short
+// immediate offsets of the LDS instructions from the row's address.
 __device__ __forceinline__ Lds carve_lds(double *base, int K, int R, int ld) {
     Lds L;
-    L.C = base;
-    L.gRT = base + 64;
-    L.hRT = base + 128;
-    L.cpR = base + 192;
-    L.u = base + 256;
-    L.tcol = base + 320;
-    L.hs = base + 384;
-    L.w = base + 448;
-    L.piv = reinterpret_cast<int *>(base + 512);
-    L.J = base + 544;
+    L.J = base;
+    double *v = base + ld * ld;
+    L.C = v;
+    L.gRT = v + 64;
+    L.hRT = v + 128;
+    L.cpR = v + 192;
+    L.u = v + 256;
+    L.tcol = v + 320;
+    L.hs = v + 384;
+    L.w = v + 448;
+    L.piv = reinterpret_cast<int *>(v + 512);
     L.ld = ld;
     return L;
 }
@@ -259,7 +263,7 @@ __device__ __forceinline__ double wave_rhs(const DevMech &m, const Lds &L, doubl
     }
     L.w[lane] = 0.0;
     wave_sync();
-    const double lnPref = log(P0_CGS * c.invT / RU_CGS);
+    const double lnPref = LN_P0_RU - c.lnT;   // ln(p0 / (R T))
     // each reaction adds its net rate to its participants' production rates
     // (LDS atomics in a fixed lane and loop order)
 #pragma unroll 1
@@ -315,7 +319,7 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
         for (int j = 0; j < K; ++j) L.J[lane * ld + j] = 0.0;
     }
     wave_sync();
-    const double lnPref = log(P0_CGS * c.invT / RU_CGS);
+    const double lnPref = LN_P0_RU - c.lnT;   // ln(p0 / (R T))
 #pragma unroll 1
     for (int r = lane; r < m.R; r += WAVE) {
         const int4 s4 = m.rsp[r];
@@ -383,11 +387,13 @@ __device__ __forceinline__ double wave_f_jac(const DevMech &m, const Lds &L, dou
         L.J[lane * ld + K] = (Wk / c.rho) * (tk - uk * c.invT) + f * c.invT;
     } else if (lane == K) {
         f = fT;
-        const double a1 = -c.T / chat;
+        const double ichat = 1.0 / chat;
+        const double a1 = -c.T * ichat;
         const double a2 = c.T * c.Wbar * Hu / (c.rho * chat);
+        const double a3 = fT * ichat;
         for (int j = 0; j < K; ++j) {
             const double ij = m.invW[j];
-            L.J[K * ld + j] = ij * (a1 * L.hs[j] + a2 - fT * (L.cpR[j] - chat * c.Wbar) / chat);
+            L.J[K * ld + j] = ij * (a1 * L.hs[j] + a2 - a3 * (L.cpR[j] - chat * c.Wbar));
         }
         L.J[K * ld + K] = -2.0 * Q / (c.rho * chat) - c.T * Qp / (c.rho * chat) +
                           c.T * Q * chatp / (c.rho * chat * chat);

@@ -158,22 +158,75 @@ __device__ __forceinline__ double wave_solve(const Lds &L, int n, int src, doubl
 // pivoting, as above) but lane p keeps row p in NT registers: the loops over
 // columns are unrolled, so every column index is a register index and the
 // elimination reads only the pivot row from LDS (one broadcast read per two
-// columns).  At step k the pivot lane writes its U row (columns > k) into its
-// LDS row, which was cleared beforehand.  Afterwards each lane keeps its L
-// multipliers (columns < its step) in registers and zeros elsewhere, and its
-// LDS row holds U strictly right of the diagonal and zeros elsewhere, so the
-// forward and backward sweeps need no lane masks.  The matrix factorised is
+// columns).  At step k every lane writes its columns right of k into its LDS
+// row (one store per two columns for the whole wave, with no branch on the
+// pivot lane), and the open rows read the pivot row from there.  Afterwards
+// each lane keeps its L multipliers (columns < its step) in registers and
+// zeros elsewhere, and its LDS row holds U strictly right of the diagonal and
+// zeros elsewhere, so the forward and backward sweeps need no lane masks.  The matrix factorised is
 // A = J - fac I, the negated iteration matrix: the multipliers and pivots
 // are exactly those of the LDS LU of fac I - J, with signs flipped where
 // they enter, so both paths give the same numbers.
 // ---------------------------------------------------------------------------
 template <int NT>
 struct RegLU {
-    double a[NT];    // L multipliers of this lane's row (columns < its step), else 0
-    double rdiag;    // 1 / U diagonal of this lane's row (lanes < NT)
-    int pk[NT];      // lane of the row chosen at step k (wave-uniform)
-    int src;         // lane of the row chosen at step `lane` (lanes < NT)
+    double a[NT];                 // L multipliers of this lane's row (columns < its step), else 0
+    double rdiag;                 // 1 / U diagonal of this lane's row (lanes < NT)
+    unsigned pkp[(NT + 4) / 5];   // lane of the row chosen at step k, 6 bits each, 5 per word
+    int src;                      // lane of the row chosen at step `lane` (lanes < NT)
+    // the pivot lane of step k (k a compile-time index: scalar shifts only)
+    __device__ __forceinline__ int pk(int k) const { return (int)((pkp[k / 5] >> (6 * (k % 5))) & 63u); }
 };
+
+// Stores a[C..NT-1] of this lane's row at LDS byte address ra + 8 c, two
+// columns per instruction.  Inline asm keeps the data in the row's own
+// registers (compiler-generated stores first copy them, two moves per
+// column); lds_wait() follows before any of those registers is written again.
+template <int C, int NT>
+__device__ __forceinline__ void publish_row(unsigned ra, const double (&a)[NT]) {
+    if constexpr (C + 1 < NT) {
+        asm volatile("ds_write2_b64 %0, %1, %2 offset0:%3 offset1:%4"
+                     :
+                     : "v"(ra), "v"(a[C]), "v"(a[C + 1]), "i"(C), "i"(C + 1)
+                     : "memory");
+        publish_row<C + 2, NT>(ra, a);
+    } else if constexpr (C < NT) {
+        asm volatile("ds_write_b64 %0, %1 offset:%2" : : "v"(ra), "v"(a[C]), "i"(8 * C) : "memory");
+    }
+}
+
+__device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" : : : "memory"); }
+
+// Step K of the factorisation (and, recursively, the steps after it).
+template <int K, int NT>
+__device__ __forceinline__ void reg_lu_steps(const Lds &L, RegLU<NT> &f, double *row, unsigned ra, bool in,
+                                             int &mystep, bool &ok) {
+    if constexpr (K < NT) {
+        const int lane = lane_id();
+        const int p = wave_argmax(fabs(f.a[K]), mystep == NT);
+        f.pkp[K / 5] |= (unsigned)p << (6 * (K % 5));
+        const double pv = bcast(f.a[K], p);
+        if (pv == 0.0) ok = false;
+        if (lane == p) {
+            mystep = K;
+            L.tcol[lane] = pv;   // the diagonal (L.tcol is free until the next Jacobian)
+            L.piv[K] = lane;
+        }
+        // every row publishes its columns right of K (closed rows republish
+        // what they already hold); the pivot row is read from there
+        if (in) publish_row<K + 1, NT>(ra, f.a);
+        lds_wait();
+        wave_sync();
+        if (mystep == NT) {
+            const double *prow = L.J + p * L.ld;
+            const double l = f.a[K] / pv;
+            f.a[K] = l;
+#pragma unroll
+            for (int c = K + 1; c < NT; ++c) f.a[c] = f.a[c] - l * prow[c];
+        }
+        reg_lu_steps<K + 1, NT>(L, f, row, ra, in, mystep, ok);
+    }
+}
 
 template <int NT>
 __device__ __forceinline__ bool reg_lu(const Lds &L, double fac, RegLU<NT> &f) {
@@ -188,41 +241,22 @@ __device__ __forceinline__ bool reg_lu(const Lds &L, double fac, RegLU<NT> &f) {
 #pragma unroll
         for (int c = 0; c < NT; ++c) f.a[c] = 0.0;
     }
-    wave_sync();
-    if (in) {
-#pragma unroll
-        for (int c = 0; c < NT; ++c) row[c] = 0.0;
-    }
-    wave_sync();
-    double *diag = L.tcol;   // free between the Jacobian and the next one
     int mystep = in ? NT : -1;
     bool ok = true;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        const int p = wave_argmax(fabs(f.a[k]), mystep == NT);
-        f.pk[k] = p;
-        const double pv = bcast(f.a[k], p);
-        if (pv == 0.0) ok = false;
-        if (lane == p) {
-            mystep = k;
-            diag[lane] = pv;
-            L.piv[k] = lane;
+    for (int w = 0; w < (NT + 4) / 5; ++w) f.pkp[w] = 0u;
+    // (the loads above complete before the first publish: in-order LDS queue
+    // per wave, and the publish waits for the queue to drain)
+    reg_lu_steps<0, NT>(L, f, row, (unsigned)(uintptr_t)row, in, mystep, ok);
+    // registers: L strictly left of the lane's step; LDS row: U strictly right
+    if (in) {
 #pragma unroll
-            for (int c = k + 1; c < NT; ++c) row[c] = f.a[c];
-        }
-        wave_sync();
-        if (mystep == NT) {
-            const double *prow = L.J + p * L.ld;
-            const double l = f.a[k] / pv;
-            f.a[k] = l;
-#pragma unroll
-            for (int c = k + 1; c < NT; ++c) f.a[c] = f.a[c] - l * prow[c];
+        for (int c = 0; c < NT; ++c) {
+            row[c] = c > mystep ? f.a[c] : 0.0;
+            if (c >= mystep) f.a[c] = 0.0;
         }
     }
-#pragma unroll
-    for (int c = 0; c < NT; ++c)
-        if (c >= mystep) f.a[c] = 0.0;
-    f.rdiag = in ? 1.0 / diag[lane] : 0.0;
+    f.rdiag = in ? 1.0 / L.tcol[lane] : 0.0;
     f.src = in ? L.piv[lane] : 0;
     wave_sync();
     return ok;
@@ -237,11 +271,11 @@ __device__ __forceinline__ double reg_solve(const Lds &L, const RegLU<NT> &f, do
     double acc = in ? -b : 0.0;
     // forward (L y = P(-b)): lane p accumulates until its own step broadcasts it
 #pragma unroll
-    for (int k = 0; k < NT; ++k) acc = acc - f.a[k] * bcast(acc, f.pk[k]);
+    for (int k = 0; k < NT; ++k) acc = acc - f.a[k] * bcast(acc, f.pk(k));
     // backward (U x = y): U rows from LDS, zero left of and on the diagonal
     const double *row = L.J + (in ? lane : 0) * L.ld;
 #pragma unroll
-    for (int k = NT - 1; k >= 0; --k) acc = acc - row[k] * bcast(acc * f.rdiag, f.pk[k]);
+    for (int k = NT - 1; k >= 0; --k) acc = acc - row[k] * bcast(acc * f.rdiag, f.pk(k));
     const double x = acc * f.rdiag;   // the unknown of this lane's step
     const double r = __shfl(x, f.src, WAVE);
     return in ? r : 0.0;
