@@ -150,7 +150,7 @@ typedef struct {
 
 /* DI kernel variants.  The LDS LU keeps the iteration matrix in the wave's
  * LDS slice and handles any N = K + 1 <= 64; the register LU keeps each row in
- * registers and exists for N = 10, 33 and 54 (CHEMK_DI_REG_LU on another N is
+ * registers and exists for N = 10 and 33 (CHEMK_DI_REG_LU on another N is
  * CHEMK_E_ARG).  CHEMK_DI_AUTO takes the register LU where it exists.       */
 enum { CHEMK_DI_AUTO = 0, CHEMK_DI_LDS_LU = 1, CHEMK_DI_REG_LU = 2 };
 
@@ -319,15 +319,38 @@ int chemk_ann_pack(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
 int chemk_ann_forward_packed(chemk_ctx *ctx, int64_t n, const uint16_t *X, float *out,
                              void *stream);
 
+/* Per-row weights of the heat-release loss (Sec. II.B, Eq. 10) for n
+ * training pairs: HRR = -(rho / dt) sum_k h_k(T) dY_k [W/m^3] over the step,
+ * h_k the species enthalpy per unit mass at the input T (NASA-7), rho the
+ * input density.  With sigma_k the stored sd of dY (chemk_ann_set_norm) and
+ * s the scale, G [n, K] FP32 (device) receives
+ *     G_ik = -(rho_i / dt) h_k(T_i) sigma_k / s,
+ * so that sum_k G_ik (out_ik - z_ik) = (HRR*_i - HRR_i) / s for the network's
+ * z-scored prediction out and target z.  scale_in > 0 fixes s (the training
+ * set's, for a held-out set); scale_in = 0 takes s = RMS of the DI label
+ * HRR_i over the n rows (Y_next - Y the label).  *scale_out (host, may be
+ * NULL) receives s.  Synchronises `stream`.                                  */
+int chemk_ann_hrr_weights(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
+                          const double *Y, const double *Y_next, double dt, double scale_in,
+                          float *G, double *scale_out, void *stream);
+
 /* One training step on rows idx[0..B-1] of (X, Z): forward with saved
- * activations, MSE on the z-scored outputs (Eq. 8), backward, Adam (beta1 0.9,
- * beta2 0.999, eps 1e-8, step counter kept in the context) with learning rate
- * lr.  loss (device FP32 scalar, may be NULL) receives the batch loss before
- * the update.  grads (device FP32 [param_count], may be NULL) receives the
- * gradient; with update = 0 the weights are left unchanged.                   */
+ * activations, the loss, backward, Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ * step counter kept in the context) with learning rate lr.  The loss is
+ * Eq. 11 with W1 = 1 on the z-scored outputs out (Eq. 8: mean of
+ * (out - z)^2 over the B K values) plus
+ *   w_mass * mean_i |sum_k (mu_k + sigma_k out_ik)| / sum_k sigma_k
+ *     (Eq. 9: the predicted Y(t+dt) sums to one plus sum_k dY*_k, the
+ *     inputs summing to one; scaled by the spread of dY),
+ *   w_hrr * mean_i (sum_k G_ik (out_ik - z_ik))^2
+ *     (Eq. 10 in units of the scale of chemk_ann_hrr_weights),
+ * with G [rows of X, K] the weights of chemk_ann_hrr_weights (NULL allowed
+ * when w_hrr = 0).  loss (device FP32 scalar, may be NULL) receives the batch
+ * loss before the update.  grads (device FP32 [param_count], may be NULL)
+ * receives the gradient; with update = 0 the weights are left unchanged.     */
 int chemk_ann_train_step(chemk_ctx *ctx, const int32_t *idx, int32_t B, const uint16_t *X,
-                         const float *Z, float lr, int32_t update, float *loss, float *grads,
-                         void *stream);
+                         const float *Z, const float *G, float w_mass, float w_hrr, float lr,
+                         int32_t update, float *loss, float *grads, void *stream);
 
 /* The training loop (Sec. II.B: Adam on the loss of Eq. 8), on the device.
  * Rows of the packed training set (X [n, 64] BF16 bits, 16-byte aligned; Z
@@ -336,11 +359,11 @@ int chemk_ann_train_step(chemk_ctx *ctx, const int32_t *idx, int32_t B, const ui
  * perm_e(b * batch + r), perm_e a four-round Feistel permutation of [0, n)
  * (cycle walking; round function SplitMix64's mixer) keyed by `seed` and e,
  * so each epoch takes floor(n / batch) batches of distinct rows.  Each step is
- * chemk_ann_train_step with the learning rate of a cosine schedule from lr0
- * to lr1 over all steps, lr1 + (lr0 - lr1)(1 + cos(pi s / S)) / 2 at step s
+ * chemk_ann_train_step (with opts' loss weights and G) with the learning
+ * rate of a cosine schedule from lr0 to lr1 over all steps, lr1 + (lr0 - lr1)(1 + cos(pi s / S)) / 2 at step s
  * of S; the Adam step count continues from the context's.  With use_graph = 1
  * one step is captured in a hipGraph and replayed.  After each epoch the mean
- * squared error over the n_hold held-out rows (X_hold, Z_hold; n_hold = 0
+ * squared error (the data loss alone) over the n_hold held-out rows (X_hold, Z_hold; n_hold = 0
  * skips it) is evaluated.  epoch_loss and hold_loss (HOST arrays [epochs],
  * NULL allowed) receive the epoch's mean batch loss and the held-out loss.
  * Synchronises `stream`.                                                    */
@@ -350,6 +373,9 @@ typedef struct {
     float lr0, lr1;          /* cosine learning-rate schedule, first -> last     */
     uint64_t seed;           /* key of the per-epoch permutations                 */
     int32_t use_graph;       /* 1 = replay one captured training step            */
+    float w_mass, w_hrr;     /* weights of the mass and heat-release losses (W2, W3
+                                of Eq. 11, chemk_ann_train_step); 0 = data loss only */
+    const float *G;          /* [n, K] heat-release weights (w_hrr > 0), device  */
 } chemk_train_opts;
 int chemk_ann_train(chemk_ctx *ctx, int64_t n, const uint16_t *X, const float *Z,
                     const uint16_t *X_hold, const float *Z_hold, int64_t n_hold,

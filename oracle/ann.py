@@ -17,6 +17,10 @@ layers use GELU and the parameters are fitted with Adam on the data loss
   the backward pass rounds the output gradient and every pre-activation
   gradient.  Sums are accumulated in float64 here.
 * Adam follows Kingma & Ba (2015), Algorithm 1.
+* The physics losses (Eqs. 9-11) act on the z-scored outputs: Eq. 9 as the
+  mean absolute deviation of the predicted mass fractions' sum from one,
+  divided by the summed spread of dY; Eq. 10 on the heat release over the
+  step, -(rho/dt) sum_k h_k(T) dY_k, divided by the RMS of the labels'.
 """
 from __future__ import annotations
 
@@ -117,6 +121,62 @@ def mse_loss(out, target):
     """Eq. 8 on normalised outputs: mean over samples and outputs."""
     d = out - target
     return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def hrr_label_weights(species_thermo, W_g, T, p, Y, Y_next, dt, sd_y, scale=None):
+    """Heat-release loss of Sec. II.B (Eq. 10), in the form the training uses.
+
+    HRR = -(rho / dt) sum_k h_k(T) dY_k over the step, h_k the enthalpy per
+    unit mass of species k at the input T [J/kg] (NASA-7: (h/RT) R_u T / W_k),
+    rho = p Wbar / (R_u T) the input density [kg/m^3], dY = Y_next - Y the DI
+    label.  Returns (G, s, hrr): G_ik = -(rho_i/dt) h_k(T_i) sd_k / s, the
+    scale s (RMS of the label HRR over the rows unless given) and the label
+    HRR itself.  species_thermo(T) -> (cp/R, h/RT, s/R) per species."""
+    RU = 8.31446261815324
+    T = np.asarray(T, np.float64)
+    n, K = np.asarray(Y).shape
+    Wkg = np.asarray(W_g, np.float64) * 1e-3
+    h = np.empty((n, K))
+    for i in range(n):
+        _, hRT, _ = species_thermo(T[i])
+        h[i] = np.asarray(hRT) * RU * T[i] / Wkg
+    Y = np.asarray(Y, np.float64)
+    Wbar = 1.0 / (Y / Wkg[None, :]).sum(1)
+    rho = np.asarray(p, np.float64) * Wbar / (RU * T)
+    hrr = -(rho / dt) * (h * (np.asarray(Y_next, np.float64) - Y)).sum(1)
+    if scale is None:
+        scale = float(np.sqrt(np.mean(hrr * hrr)))
+    G = -(rho / dt)[:, None] * h * np.asarray(sd_y, np.float64)[None, :] / scale
+    return G, scale, hrr
+
+
+def phys_loss(out, target, mu_y, sd_y, G, w_mass, w_hrr):
+    """Eq. 11 with W1 = 1 on z-scored outputs: the data loss of Eq. 8 plus
+    w_mass times Eq. 9 and w_hrr times Eq. 10, and d(loss)/d(out).
+
+    Eq. 9: the predicted Y(t+dt) = Y + mu + sd out sums to one plus
+    m_i = sum_k (mu_k + sd_k out_ik) (the inputs sum to one); the term is
+    mean_i |m_i| / sum_k sd_k (scaled by the spread of dY so that it is of the
+    order of the data loss).  Eq. 10: e_i = sum_k G_ik (out_ik - target_ik) is
+    (HRR* - HRR) / s (hrr_label_weights); the term is mean_i e_i^2."""
+    out = np.asarray(out, np.float64)
+    target = np.asarray(target, np.float64)
+    B = out.shape[0]
+    d = out - target
+    loss = float(np.mean(d * d))
+    grad = 2.0 * d / d.size
+    mu_y = np.asarray(mu_y, np.float64)
+    sd_y = np.asarray(sd_y, np.float64)
+    if w_mass:
+        m = (mu_y[None, :] + sd_y[None, :] * out).sum(1)
+        S = sd_y.sum()
+        loss += w_mass * float(np.mean(np.abs(m))) / S
+        grad = grad + w_mass * np.sign(m)[:, None] * sd_y[None, :] / (S * B)
+    if w_hrr:
+        e = (np.asarray(G, np.float64) * d).sum(1)
+        loss += w_hrr * float(np.mean(e * e))
+        grad = grad + w_hrr * 2.0 * e[:, None] * np.asarray(G, np.float64) / B
+    return loss, grad
 
 
 def backward(Ws, bs, cache, dout, quantize=True):

@@ -56,7 +56,8 @@ class AnnChecks(C.Structure):
 
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr0", C.c_float), ("lr1", C.c_float),
-                ("seed", C.c_uint64), ("use_graph", C.c_int32)]
+                ("seed", C.c_uint64), ("use_graph", C.c_int32), ("w_mass", C.c_float),
+                ("w_hrr", C.c_float), ("G", C.c_void_p)]
 
 
 _vp = C.c_void_p
@@ -99,8 +100,10 @@ _SIGS = {
                                      C.c_double, _vp]),
     "chemk_ann_pack": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "chemk_ann_forward_packed": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
-    "chemk_ann_train_step": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, C.c_float, C.c_int32,
-                                       _vp, _vp, _vp]),
+    "chemk_ann_train_step": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp, C.c_float, C.c_float,
+                                       C.c_float, C.c_int32, _vp, _vp, _vp]),
+    "chemk_ann_hrr_weights": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp,
+                                        C.POINTER(C.c_double), _vp]),
     "chemk_ann_train": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(TrainOpts), _vp, _vp,
                                   _vp]),
     "chemk_ann_reset_optimizer": (C.c_int, [_vp]),
@@ -353,15 +356,24 @@ class Context:
         n = X.shape[0] if n is None else n
         _check(lib.chemk_ann_forward_packed(self.handle, n, _ptr(X), _ptr(out), _stream(stream)))
 
-    def ann_train_step(self, idx, X, Z, lr, update=True, loss=None, grads=None, stream=None):
-        _check(lib.chemk_ann_train_step(self.handle, _ptr(idx), idx.numel(), _ptr(X), _ptr(Z),
-                                        float(lr), int(bool(update)), _ptr(loss), _ptr(grads),
-                                        _stream(stream)))
+    def ann_train_step(self, idx, X, Z, lr, update=True, loss=None, grads=None, stream=None,
+                       G=None, w_mass=0.0, w_hrr=0.0):
+        _check(lib.chemk_ann_train_step(self.handle, _ptr(idx), idx.numel(), _ptr(X), _ptr(Z), _ptr(G),
+                                        float(w_mass), float(w_hrr), float(lr), int(bool(update)),
+                                        _ptr(loss), _ptr(grads), _stream(stream)))
+
+    def ann_hrr_weights(self, T, P, Y, Y_next, dt, G, scale=0.0, stream=None):
+        """Heat-release loss weights into G [n, K] (device float32); returns the scale."""
+        out = C.c_double(0.0)
+        _check(lib.chemk_ann_hrr_weights(self.handle, T.shape[0], _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_next),
+                                         float(dt), float(scale), _ptr(G), C.byref(out), _stream(stream)))
+        return out.value
 
     def ann_train(self, X, Z, epochs, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001, X_hold=None,
-                  Z_hold=None, use_graph=True, stream=None):
+                  Z_hold=None, use_graph=True, stream=None, G=None, w_mass=0.0, w_hrr=0.0):
         """Returns (epoch_loss, hold_loss) as host arrays [epochs]."""
-        o = TrainOpts(int(batch), int(epochs), float(lr0), float(lr1), int(seed), int(bool(use_graph)))
+        o = TrainOpts(int(batch), int(epochs), float(lr0), float(lr1), int(seed), int(bool(use_graph)),
+                      float(w_mass), float(w_hrr), _ptr(G))
         el = np.zeros(epochs, np.float32)
         hl = np.zeros(epochs, np.float32)
         nh = 0 if X_hold is None else X_hold.shape[0]

@@ -638,6 +638,83 @@ __global__ void mse_kernel(const float *__restrict__ out, const float *__restric
     }
 }
 
+// The loss of Eq. 11 with the physics terms (chemk_ann_train_step): one thread
+// per row.  d = out - tgt; data term mean(d^2) over the B K values; mass term
+// w_mass |m| / S with m = sum_k (mu_k + sd_k out_k) and S = sum_k sd_k; heat
+// release term w_hrr e^2 with e = sum_k G_k d_k; both averaged over rows.
+// dOut = bf16 of the gradient of the total, rounded once.
+__global__ void phys_loss_kernel(const float *__restrict__ out, const float *__restrict__ tgt,
+                                 const float *__restrict__ G, int B, int K, const double *__restrict__ mu,
+                                 const double *__restrict__ sd, float inv_S, float w_mass, float w_hrr,
+                                 uint16_t *dout, LossSink sink) {
+    __shared__ float red[256];
+    float s = 0.f;
+    const float sc = 2.0f / (float)(B * K), rb = 1.0f / (float)B;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x) {
+        const float *o = out + (size_t)i * K, *t = tgt + (size_t)i * K;
+        const float *g = G ? G + (size_t)i * K : nullptr;
+        float dd = 0.f, m = 0.f, e = 0.f;
+        for (int k = 0; k < K; ++k) {
+            const float d = o[k] - t[k];
+            dd += d * d;
+            m += (float)mu[k] + (float)sd[k] * o[k];
+            if (g) e += g[k] * d;
+        }
+        s += dd / (float)(B * K) + w_mass * fabsf(m) * inv_S * rb + (g ? w_hrr * e * e * rb : 0.f);
+        const float cm = w_mass * (m > 0.f ? 1.f : (m < 0.f ? -1.f : 0.f)) * inv_S * rb;
+        const float ce = g ? 2.0f * w_hrr * e * rb : 0.f;
+        for (int k = 0; k < K; ++k) {
+            const float gr = (o[k] - t[k]) * sc + cm * (float)sd[k] + (g ? ce * g[k] : 0.f);
+            dout[(size_t)i * K + k] = f2bf(gr);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o2 = blockDim.x / 2; o2 > 0; o2 >>= 1) {
+        if ((int)threadIdx.x < o2) red[threadIdx.x] += red[threadIdx.x + o2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sink.acc) {
+        float *dst = sink.ctl ? sink.acc + sink.ctl[0] / sink.spe : sink.acc;
+        atomicAdd(dst, red[0] * sink.scale);
+    }
+}
+
+// Rows idx[0..B-1] of G [., K] into Gb [B, K].
+__global__ void gather_g_kernel(const int *__restrict__ idx, int B, const float *__restrict__ G, int K,
+                                float *Gb) {
+    const int r = blockIdx.x;
+    if (r >= B) return;
+    const int src = idx[r];
+    for (int k = threadIdx.x; k < K; k += blockDim.x) Gb[(size_t)r * K + k] = G[(size_t)src * K + k];
+}
+
+// Heat release over the step of row i (chemk_ann_hrr_weights): the label
+// HRR_i = -(rho/dt) sum_k h_k dY_k, its square added to *sum2; with scale > 0
+// also the row of weights G_ik = -(rho/dt) h_k sd_k / scale.  One thread per row.
+__global__ void hrr_weights_kernel(DevMech m, int n, const double *__restrict__ T, const double *__restrict__ p,
+                                   const double *__restrict__ Y, const double *__restrict__ Yn, double dt,
+                                   const double *__restrict__ sd, double scale, float *G, double *sum2) {
+    const int K = m.K;
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double Ti = T[i], invT = 1.0 / Ti;
+        double ws = 0.0, q = 0.0;
+        for (int k = 0; k < K; ++k) ws += Y[(size_t)i * K + k] * m.invW[k];
+        // rho [kg/m^3] = p Wbar / (R T) with Wbar in kg/mol
+        const double rdt = p[i] * 1e-3 / (ws * RU_SI * Ti) / dt;
+        for (int k = 0; k < K; ++k) {
+            double cpR, hRT;
+            sp_cp_h(m.nasa + 7 * k, Ti, invT, cpR, hRT);
+            const double hk = hRT * RU_SI * Ti * 1e3 * m.invW[k];   // J/kg
+            if (Yn) q -= rdt * hk * (Yn[(size_t)i * K + k] - Y[(size_t)i * K + k]);
+            if (scale > 0.0) G[(size_t)i * K + k] = (float)(-rdt * hk * sd[k] / scale);
+        }
+        acc += q * q;
+    }
+    if (sum2) atomicAdd(sum2, acc);
+}
+
 // Sum over `count` values of (out - tgt)^2 / denom into *acc (held-out loss).
 __global__ void sq_err_kernel(const float *__restrict__ out, const float *__restrict__ tgt,
                               long long count, double denom, float *acc) {
@@ -1076,7 +1153,7 @@ struct AnnState {
     // training scratch
     int tB = 0;
     uint16_t *tX = nullptr, *tdZ[2] = {nullptr, nullptr};
-    float *tZt = nullptr, *tOut = nullptr, *tLoss = nullptr;
+    float *tZt = nullptr, *tOut = nullptr, *tLoss = nullptr, *tGt = nullptr;
     float *tWork = nullptr;   // split-K and column-sum partials
     size_t tWorkCap = 0;
     std::vector<float *> tZ;          // pre-activations per hidden layer
@@ -1117,6 +1194,7 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->tdZ[0]);
     (void)hipFree(a->tdZ[1]);
     (void)hipFree(a->tZt);
+    (void)hipFree(a->tGt);
     (void)hipFree(a->tOut);
     (void)hipFree(a->tLoss);
     (void)hipFree(a->tWork);
@@ -1833,6 +1911,7 @@ static hipError_t ensure_train(AnnState *a, int B) {
     (void)hipFree(a->tdZ[0]);
     (void)hipFree(a->tdZ[1]);
     (void)hipFree(a->tZt);
+    (void)hipFree(a->tGt);
     (void)hipFree(a->tOut);
     (void)hipFree(a->tLoss);
     (void)hipFree(a->tWork);
@@ -1849,6 +1928,7 @@ static hipError_t ensure_train(AnnState *a, int B) {
     if ((e = hipMalloc(&a->tdZ[0], 2 * (size_t)B * wmax)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tdZ[1], 2 * (size_t)B * wmax)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tZt, 4 * (size_t)B * a->K)) != hipSuccess) return e;
+    if ((e = hipMalloc(&a->tGt, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tOut, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tLoss, 4)) != hipSuccess) return e;
     // split-K partials of the largest weight gradient, then the column-sum partials
@@ -1874,16 +1954,34 @@ static hipError_t ensure_train(AnnState *a, int B) {
 
 // One training step's forward (saving Z and A), loss and backward on rows
 // idx[0..B-1] of (X, Z): the gradient lands in a->grad, the batch loss in sink.
+// Loss weights of the physics terms (Eq. 11's W2, W3) and the heat-release
+// weights G of the training rows (NULL when w_hrr = 0).
+struct PhysLoss {
+    const float *G;
+    float w_mass, w_hrr;
+};
+
 static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t *X, const float *Z,
-                          LossSink sink, hipStream_t s) {
+                          LossSink sink, hipStream_t s, PhysLoss ph = PhysLoss{nullptr, 0.f, 0.f}) {
     const int K = a->K, L = a->L;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(B), dim3(64), 0, s, idx, B, X, FPAD, Z, K, a->tX, a->tZt);
+    const bool hrr = ph.w_hrr != 0.f && ph.G;
+    if (hrr) hipLaunchKernelGGL(gather_g_kernel, dim3(B), dim3(64), 0, s, idx, B, ph.G, K, a->tGt);
     a->tA[0] = a->tX;
     hipError_t e;
     if ((e = mlp_forward(a, a->tX, B, a->tOut, nullptr, nullptr, s, a->tZ.data(), a->tA.data())) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(mse_kernel, dim3(std::min(1024, (B * K + 255) / 256)), dim3(256), 0, s, a->tOut,
-                       a->tZt, B * K, a->tdZ[0], sink);
+    if (ph.w_mass != 0.f || hrr) {
+        double S = 0.0;
+        for (int k = 0; k < K; ++k) S += a->sd_y[k];
+        const NormDev nd = norm_dev(a);
+        hipLaunchKernelGGL(phys_loss_kernel, dim3((B + 255) / 256), dim3(256), 0, s, a->tOut, a->tZt,
+                           hrr ? a->tGt : nullptr, B, K, nd.mu_y, nd.sd_y, (float)(1.0 / S), ph.w_mass,
+                           hrr ? ph.w_hrr : 0.f, a->tdZ[0], sink);
+    } else {
+        hipLaunchKernelGGL(mse_kernel, dim3(std::min(1024, (B * K + 255) / 256)), dim3(256), 0, s, a->tOut,
+                           a->tZt, B * K, a->tdZ[0], sink);
+    }
     int cur = 0;
     for (int l = L - 1; l >= 0; --l) {
         const int in = a->pd[l], out = a->pd[l + 1];
@@ -1925,8 +2023,8 @@ static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t
 }
 
 extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B, const uint16_t *X,
-                                    const float *Z, float lr, int32_t update, float *loss,
-                                    float *grads, void *stream) {
+                                    const float *Z, const float *G, float w_mass, float w_hrr, float lr,
+                                    int32_t update, float *loss, float *grads, void *stream) {
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
@@ -1934,11 +2032,14 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
     if (!idx || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null array");
     if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
     if (!(lr >= 0) || !std::isfinite(lr)) ANN_FAIL(CHEMK_E_ARG, "bad learning rate");
+    if (!(w_mass >= 0) || !(w_hrr >= 0) || !std::isfinite(w_mass) || !std::isfinite(w_hrr))
+        ANN_FAIL(CHEMK_E_ARG, "loss weights must be finite and >= 0");
+    if (w_hrr > 0 && !G) ANN_FAIL(CHEMK_E_ARG, "w_hrr > 0 needs the heat-release weights G");
     ANN_TRY(ensure_train(a, B));
     hipStream_t s = (hipStream_t)stream;
     const int L = a->L;
     hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, s, a->tLoss, 1);
-    ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s));
+    ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s, PhysLoss{G, w_mass, w_hrr}));
     if (loss) ANN_TRY(hipMemcpyAsync(loss, a->tLoss, 4, hipMemcpyDeviceToDevice, s));
     if (grads) {
         size_t p = 0;
@@ -1996,6 +2097,9 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
         ANN_FAIL(CHEMK_E_ARG, "bad learning rates");
     if (n_hold < 0 || n_hold > (1ll << 31) - 1 || (n_hold > 0 && (!X_hold || !Z_hold)))
         ANN_FAIL(CHEMK_E_ARG, "bad held-out set");
+    if (!(o->w_mass >= 0) || !(o->w_hrr >= 0) || !std::isfinite(o->w_mass) || !std::isfinite(o->w_hrr))
+        ANN_FAIL(CHEMK_E_ARG, "loss weights must be finite and >= 0");
+    if (o->w_hrr > 0 && !o->G) ANN_FAIL(CHEMK_E_ARG, "w_hrr > 0 needs the heat-release weights G");
     if (reinterpret_cast<uintptr_t>(X) % 16 || (X_hold && reinterpret_cast<uintptr_t>(X_hold) % 16))
         ANN_FAIL(CHEMK_E_ARG, "X must be 16-byte aligned");
     hipStream_t s0 = (hipStream_t)stream;
@@ -2040,7 +2144,8 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
         auto one_step = [&](hipStream_t st) -> hipError_t {
             hipLaunchKernelGGL(batch_index_kernel, dim3((B + 255) / 256), dim3(256), 0, st, ctl, B, spe,
                                (unsigned int)n, half, (unsigned long long)o->seed, idx);
-            hipError_t ee = fwd_bwd(a, idx, B, X, Z, LossSink{eloss, ctl, spe, 1.0f / (float)spe}, st);
+            hipError_t ee = fwd_bwd(a, idx, B, X, Z, LossSink{eloss, ctl, spe, 1.0f / (float)spe}, st,
+                                    PhysLoss{o->G, o->w_mass, o->w_hrr});
             if (ee != hipSuccess) return ee;
             hipLaunchKernelGGL(adam_sched_kernel, dim3(gadam), dim3(256), 0, st, a->master, a->grad, a->m1,
                                a->m2, (int64_t)a->nparam, ctl, (double)o->lr0, (double)o->lr1, total, 0.9,
@@ -2072,6 +2177,48 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
     a->step += total;
     if (epoch_loss) std::memcpy(epoch_loss, he.data(), 4 * (size_t)o->epochs);
     if (hold_loss) std::memcpy(hold_loss, hh.data(), 4 * (size_t)o->epochs);
+    return CHEMK_OK;
+}
+
+extern "C" int chemk_ann_hrr_weights(chemk_ctx *c, int64_t n, const double *T, const double *p,
+                                     const double *Y, const double *Yn, double dt, double scale_in, float *G,
+                                     double *scale_out, void *stream) {
+    ctx_set_error("");
+    AnnState *a;
+    if (int r = need_ann(c, &a)) return r;
+    if (!a->have_norm) ANN_FAIL(CHEMK_E_STATE, "normalisation not set");
+    if (n < 1 || n > (1ll << 31) - 1) ANN_FAIL(CHEMK_E_ARG, "bad n");
+    if (!T || !p || !Y || !G) ANN_FAIL(CHEMK_E_ARG, "null array");
+    if (!(dt > 0) || !std::isfinite(dt)) ANN_FAIL(CHEMK_E_ARG, "dt must be finite and > 0");
+    if (!(scale_in >= 0) || !std::isfinite(scale_in)) ANN_FAIL(CHEMK_E_ARG, "bad scale");
+    if (scale_in == 0 && !Yn) ANN_FAIL(CHEMK_E_ARG, "the scale from the labels needs Y_next");
+    hipStream_t s = (hipStream_t)stream;
+    const DevMech m = ctx_devmech(c);
+    const NormDev nd = norm_dev(a);
+    const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    double scale = scale_in;
+    if (scale == 0.0) {
+        double *sum2 = nullptr;
+        ANN_TRY(hipMalloc(&sum2, 8));
+        hipError_t e = hipMemsetAsync(sum2, 0, 8, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(hrr_weights_kernel, dim3(grid), dim3(256), 0, s, m, (int)n, T, p, Y, Yn, dt,
+                               nd.sd_y, 0.0, G, sum2);
+            e = hipGetLastError();
+        }
+        double h2 = 0.0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&h2, sum2, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(sum2);
+        ANN_TRY(e);
+        scale = std::sqrt(h2 / (double)n);
+        if (!(scale > 0) || !std::isfinite(scale)) ANN_FAIL(CHEMK_E_ARG, "the labels release no heat");
+    }
+    hipLaunchKernelGGL(hrr_weights_kernel, dim3(grid), dim3(256), 0, s, m, (int)n, T, p, Y, nullptr, dt, nd.sd_y,
+                       scale, G, nullptr);
+    ANN_TRY(hipGetLastError());
+    ANN_TRY(hipStreamSynchronize(s));
+    if (scale_out) *scale_out = scale;
     return CHEMK_OK;
 }
 

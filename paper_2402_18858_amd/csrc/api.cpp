@@ -476,7 +476,7 @@ static int check_opts(const chemk_ctx *c, const chemk_opts *o) {
     if (o->di_kernel != CHEMK_DI_AUTO && o->di_kernel != CHEMK_DI_LDS_LU && o->di_kernel != CHEMK_DI_REG_LU)
         return fail(CHEMK_E_ARG, "di_kernel=%d unknown", o->di_kernel);
     if (o->di_kernel == CHEMK_DI_REG_LU && !di_has_reg_lu(c->dm.N))
-        return fail(CHEMK_E_ARG, "no register-LU DI kernel for N = %d (it exists for 10, 33, 54)", c->dm.N);
+        return fail(CHEMK_E_ARG, "no register-LU DI kernel for N = %d (it exists for 10 and 33)", c->dm.N);
     return CHEMK_OK;
 }
 

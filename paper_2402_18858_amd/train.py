@@ -265,10 +265,12 @@ NEG_TOL = 1e-6
 
 
 def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001,
-                  holdout=0.1, log=print, mech=None, adj_max=ADJ_MAX, env_q=ENV_Q):
+                  holdout=0.1, log=print, mech=None, adj_max=ADJ_MAX, env_q=ENV_Q, w_mass=0.0,
+                  w_hrr=0.0):
     """Fits the network on the DI pairs; returns a history dict.  With `mech`
     the input envelope gets the element-ratio windows; its box, those windows
-    and the dT window are fitted to the training split."""
+    and the dT window are fitted to the training split.  w_mass and w_hrr
+    weight the mass and heat-release losses (Eqs. 9-11; chemk_ann_train_step)."""
     import torch
 
     dev = "cuda:0"
@@ -299,13 +301,20 @@ def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed
     Zh = torch.empty((n_hold, K), dtype=torch.float32, device=dev)
     if n_hold:
         ctx.ann_pack(*Hd, Xh, Zh)
-    hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "n_holdout": int(n_hold)}
+    hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "n_holdout": int(n_hold),
+            "w_mass": w_mass, "w_hrr": w_hrr}
+    G = None
+    if w_hrr > 0:
+        G = torch.empty((ntr, K), dtype=torch.float32, device=dev)
+        hist["hrr_scale"] = ctx.ann_hrr_weights(Td["T"], Td["p"], Td["Y"], Td["Yn"], dt, G)
     torch.cuda.synchronize()
     t0 = time.time()
     # the whole loop (per-epoch device-side shuffles, cosine schedule, Adam,
     # held-out loss) runs in the library: chemk_ann_train
     el, hl = ctx.ann_train(X, Z, epochs, batch=batch, lr0=lr0, lr1=lr1, seed=seed,
-                           X_hold=Xh if n_hold else None, Z_hold=Zh if n_hold else None)
+                           X_hold=Xh if n_hold else None, Z_hold=Zh if n_hold else None,
+                           G=G, w_mass=w_mass, w_hrr=w_hrr)
+    del G
     hist["loss"] = [float(v) for v in el]
     hist["hold_loss"] = [float(v) for v in hl]
     for ep in list(range(0, epochs, 10)) + [epochs - 1]:
@@ -317,10 +326,12 @@ def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed
     return hist
 
 
-def evaluate(ctx, T, p, Y, Yn_ref):
+def evaluate(ctx, T, p, Y, Yn_ref, hrr_scale=None):
     """Per-species RMS and max of the normalised dY error of the network
     (no projection, no fallback) against reference dY, plus the frozen-
-    chemistry (dY = 0) error, on host arrays."""
+    chemistry (dY = 0) error, on host arrays; the raw prediction's mass
+    defect (mean |sum_k dY*_k|, Eq. 9) and, with the training set's
+    heat-release scale, the RMS heat-release error in that unit (Eq. 10)."""
     import torch
 
     dev = "cuda:0"
@@ -336,11 +347,24 @@ def evaluate(ctx, T, p, Y, Yn_ref):
     ref = Yn_ref - Y
     e = (pred - ref) / sy
     e0 = (0.0 - ref) / sy
-    return {"rms_norm": np.sqrt(np.mean(e * e, 0)), "max_norm": np.abs(e).max(0),
-            "rms_abs": np.sqrt(np.mean((pred - ref) ** 2, 0)),
-            "frozen_rms_norm": np.sqrt(np.mean(e0 * e0, 0)),
-            "rms_norm_all": float(np.sqrt(np.mean(e * e))),
-            "frozen_rms_norm_all": float(np.sqrt(np.mean(e0 * e0)))}
+    res = {"rms_norm": np.sqrt(np.mean(e * e, 0)), "max_norm": np.abs(e).max(0),
+           "rms_abs": np.sqrt(np.mean((pred - ref) ** 2, 0)),
+           "frozen_rms_norm": np.sqrt(np.mean(e0 * e0, 0)),
+           "rms_norm_all": float(np.sqrt(np.mean(e * e))),
+           "frozen_rms_norm_all": float(np.sqrt(np.mean(e0 * e0))),
+           "mass_defect_mean_abs": float(np.mean(np.abs(pred.sum(1)))),
+           "mass_defect_ref_mean_abs": float(np.mean(np.abs(ref.sum(1))))}
+    if hrr_scale:
+        G = torch.empty((n, K), dtype=torch.float32, device=dev)
+        ctx.ann_hrr_weights(Td[0], Td[1], Td[2], None, dt, G, scale=hrr_scale)
+        g = G.cpu().numpy().astype(np.float64)
+        z = ref / sy - my / sy
+        o = out.cpu().numpy().astype(np.float64)
+        eh = (g * (o - z)).sum(1)
+        eh0 = (g * (-my / sy - z)).sum(1)
+        res.update({"hrr_rms_err": float(np.sqrt(np.mean(eh * eh))),
+                    "hrr_frozen_rms_err": float(np.sqrt(np.mean(eh0 * eh0)))})
+    return res
 
 
 WEIGHTS = os.path.join(HERE, "weights", "mlp_medium.npz")
@@ -422,6 +446,8 @@ def main(argv=None):
     ap.add_argument("--dt", type=float, default=5e-7)
     ap.add_argument("--mech", default="medium", choices=["medium", "large"])
     ap.add_argument("--out", default=None)
+    ap.add_argument("--w-mass", type=float, default=0.0, help="weight of the mass loss (Eq. 9)")
+    ap.add_argument("--w-hrr", type=float, default=0.0, help="weight of the heat-release loss (Eq. 10)")
     ap.add_argument("--recipe", default="cfg4", choices=["cfg4", "hfrd"],
                     help="cfg4: noisy trajectories + mixing lines + flame-block states; "
                          "hfrd: the paper's perturbation recipe (generate_pairs_hfrd)")
@@ -437,14 +463,25 @@ def main(argv=None):
     gen = generate_pairs_hfrd if a.recipe == "hfrd" else generate_pairs
     data = gen(ctx, mech, a.dt, a.pairs, log=log)
     t_data = time.time() - t0
-    hist = train_network(ctx, data, a.dt, epochs=a.epochs, batch=a.batch, log=log, mech=mech)
+    hist = train_network(ctx, data, a.dt, epochs=a.epochs, batch=a.batch, log=log, mech=mech,
+                         w_mass=a.w_mass, w_hrr=a.w_hrr)
     save(ctx, a.out, extra={"loss": np.array(hist["loss"])})
     T, p, Y, Yn = data[:4]
     hold = hist["holdout_index"]
-    ev = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold])
+    # the heat-release unit of the report: RMS of the label HRR over all pairs
+    Tg = [torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0") for v in (T, p, Y, Yn)]
+    Gs = torch.empty((T.size, mech.K), dtype=torch.float32, device="cuda:0")
+    hrr_unit = ctx.ann_hrr_weights(*Tg, a.dt, Gs)
+    del Tg, Gs
+    ev = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold], hrr_scale=hrr_unit)
     torch.cuda.synchronize()
     fl = 3 * mlp_flops_per_cell(ctx.dims) * a.batch * hist["steps"]
-    rep = {"recipe": a.recipe, "pairs": int(T.size), "n_train": hist["n_train"], "n_holdout": hist["n_holdout"],
+    rep = {"recipe": a.recipe, "w_mass": a.w_mass, "w_hrr": a.w_hrr,
+           "holdout_mass_defect": ev["mass_defect_mean_abs"],
+           "holdout_mass_defect_ref": ev["mass_defect_ref_mean_abs"],
+           "holdout_hrr_rms_err": ev["hrr_rms_err"], "holdout_hrr_frozen_rms_err": ev["hrr_frozen_rms_err"],
+           "hrr_unit_W_m3": hrr_unit,
+           "pairs": int(T.size), "n_train": hist["n_train"], "n_holdout": hist["n_holdout"],
            "epochs": a.epochs, "batch": a.batch, "data_s": t_data, "train_s": hist["train_s"],
            "train_tflops_wall": fl / hist["train_s"] / 1e12,
            "loss_first": hist["loss"][0], "loss_last": hist["loss"][-1],

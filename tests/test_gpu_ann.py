@@ -156,6 +156,71 @@ def test_gradients_match_oracle():
         assert np.sqrt(np.mean((seg - r) ** 2)) < 2e-2 * np.sqrt(np.mean(r ** 2)), i
 
 
+def test_hrr_weights_match_oracle():
+    """Eq. 10's heat-release weights and scale computed on the device."""
+    import torch
+    import oracle
+    mech = sm.mech_medium()
+    ctx, dims, params = _ctx_small_net(mech, seed=10)
+    n = 300
+    T, p, Y = _states(mech, n, 46)
+    _set_norm(ctx, mech, T, p, Y)
+    rng = np.random.default_rng(11)
+    dY = rng.normal(0, 1e-4, Y.shape)
+    dY -= dY.mean(1, keepdims=True)
+    G = torch.zeros((n, mech.K), dtype=torch.float32, device="cuda:0")
+    s = ctx.ann_hrr_weights(dev(T), dev(p), dev(Y), dev(Y + dY), 5e-7, G)
+    om = oracle.OracleMech(mech)
+    Go, so, _ = oann.hrr_label_weights(om.species_thermo, om.W, T, p, Y, Y + dY, 5e-7, np.full(mech.K, 1e-3))
+    g = host(G).astype(np.float64)
+    announce(f"hrr weights: scale {s:.6e} (oracle {so:.6e}), max rel dG {np.abs(g - Go).max() / np.abs(Go).max():.2e}")
+    assert s == pytest.approx(so, rel=1e-10)
+    np.testing.assert_allclose(g, Go, rtol=1e-6, atol=1e-7 * np.abs(Go).max())
+    # a given scale is used as is
+    G2 = torch.zeros_like(G)
+    s2 = ctx.ann_hrr_weights(dev(T), dev(p), dev(Y), None, 5e-7, G2, scale=2.0 * so)
+    assert s2 == 2.0 * so
+    np.testing.assert_allclose(host(G2).astype(np.float64), Go / 2.0, rtol=1e-6, atol=1e-7 * np.abs(Go).max())
+
+
+def test_physics_loss_gradients_match_oracle():
+    """Eq. 11 with the mass (Eq. 9) and heat-release (Eq. 10) terms: loss and
+    gradients of one step against the oracle."""
+    import torch
+    mech = sm.mech_medium()
+    ctx, dims, params = _ctx_small_net(mech, seed=12)
+    B = 256
+    T, p, Y = _states(mech, B, 47)
+    mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
+    rng = np.random.default_rng(13)
+    Zt = rng.normal(0, 1, (B, mech.K)).astype(np.float32)
+    Gh = rng.normal(0, 0.3, (B, mech.K)).astype(np.float32)
+    X = torch.empty((B, 64), dtype=torch.int16, device="cuda:0")
+    ctx.ann_pack(dev(T), dev(p), dev(Y), None, X, None)
+    idx = dev(rng.permutation(B).astype(np.int32))
+    grads = torch.zeros(ctx.ann_param_count(), dtype=torch.float32, device="cuda:0")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    wm, wh = 0.5, 0.25
+    ctx.ann_train_step(idx, X, dev(Zt), 0.0, update=False, loss=loss, grads=grads, G=dev(Gh), w_mass=wm,
+                       w_hrr=wh)
+    gg = host(grads).astype(np.float64)
+    order = host(idx)
+    Ws, bs = _unpack(params, dims)
+    o, cache = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x)[order], quantize=True)
+    lo, dout = oann.phys_loss(o, Zt[order].astype(np.float64), np.zeros(mech.K), np.full(mech.K, 1e-3),
+                              Gh[order].astype(np.float64), wm, wh)
+    gW, gb = oann.backward(Ws, bs, cache, dout, quantize=True)
+    ref = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(gW, gb)])
+    rel = np.sqrt(np.mean((gg - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+    lo_data, _ = oann.mse_loss(o, Zt[order].astype(np.float64))
+    announce(f"physics-loss gradients: rel rms {rel:.2e}; loss gpu {host(loss)[0]:.6f} oracle {lo:.6f} "
+             f"(data term {lo_data:.6f})")
+    assert host(loss)[0] == pytest.approx(lo, rel=1e-3)
+    assert rel < 1e-2
+    with pytest.raises(Exception):
+        ctx.ann_train_step(idx, X, dev(Zt), 0.0, update=False, w_hrr=0.5)   # G missing
+
+
 def test_adam_step_matches_oracle():
     import torch
     mech = sm.mech_medium()

@@ -228,3 +228,89 @@ def test_forward_hand_computed_value_bf16():
     out, cache = ann.forward(Ws, bs, x, quantize=True)
     assert np.array_equal(cache["A"][1], [[0.83984375, -0.0155029296875]])
     assert out[0, 0] == 1.8201904296875
+
+
+# ---------------------------------------------------------------------------
+# physics losses (Eqs. 9-11)
+# ---------------------------------------------------------------------------
+def test_phys_loss_without_weights_is_the_data_loss():
+    rng = np.random.default_rng(1)
+    o, t = rng.normal(size=(7, 5)), rng.normal(size=(7, 5))
+    a, ga = ann.mse_loss(o, t)
+    b, gb = ann.phys_loss(o, t, np.zeros(5), np.ones(5), None, 0.0, 0.0)
+    assert a == b and np.array_equal(ga, gb)
+
+
+def test_phys_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(2)
+    B, K = 6, 4
+    o, t = rng.normal(size=(B, K)), rng.normal(size=(B, K))
+    mu, sd = rng.normal(0, 1e-3, K), rng.uniform(1e-3, 2e-3, K)
+    G = rng.normal(size=(B, K))
+    # keep every row's mass sum away from the kink of |m|
+    o += (0.5 - (mu + sd * o).sum(1) / sd.sum())[:, None]
+    f = lambda x: ann.phys_loss(x, t, mu, sd, G, 0.7, 0.3)[0]
+    _, g = ann.phys_loss(o, t, mu, sd, G, 0.7, 0.3)
+    h = 1e-6
+    fd = np.zeros_like(o)
+    for i in range(B):
+        for k in range(K):
+            e = np.zeros_like(o)
+            e[i, k] = h
+            fd[i, k] = (f(o + e) - f(o - e)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-9)
+
+
+def test_mass_loss_by_hand_and_zero_when_mass_is_conserved():
+    # two species, mu = (1e-3, -1e-3), sd = (1e-3, 2e-3): out = (1, 1) predicts
+    # dY = (2e-3, 1e-3), sum 3e-3; |m| / sum(sd) = 3e-3 / 3e-3 = 1
+    mu, sd = np.array([1e-3, -1e-3]), np.array([1e-3, 2e-3])
+    o = np.array([[1.0, 1.0]])
+    loss, _ = ann.phys_loss(o, o, mu, sd, None, 1.0, 0.0)
+    assert loss == pytest.approx(1.0, rel=1e-12)
+    # dY = (+d, -d) conserves mass: out = (d - mu) / sd per species
+    d = 4e-3
+    o2 = np.array([[(d - mu[0]) / sd[0], (-d - mu[1]) / sd[1]]])
+    loss2, _ = ann.phys_loss(o2, o2, mu, sd, None, 1.0, 0.0)
+    assert abs(loss2) < 1e-15
+
+
+def test_heat_release_from_heats_of_formation():
+    """At 298.15 K the species enthalpies are the heats of formation the
+    tiny H/O mechanism was built from: moving mass from H2 + O2 to OH releases
+    -sum_k h_f,k / W_k dY_k per unit mass."""
+    from tests import mechs
+    import oracle
+    mech = mechs.tiny_hox()
+    om = oracle.OracleMech(mech)
+    hf = np.array([218e3, 249e3, 0.0, 0.0, 39e3])          # J/mol, as in tests/mechs.py
+    W = om.W                                               # g/mol
+    T, p, dt = np.array([298.15]), np.array([101325.0]), 1e-6
+    Y = np.array([[0.0, 0.0, 0.2, 0.7, 0.1]])
+    dY = np.array([[0.0, 0.0, -0.01, -0.02, 0.03]])
+    G, s, hrr = ann.hrr_label_weights(om.species_thermo, W, T, p, Y, Y + dY, dt, np.ones(5))
+    Wbar = 1.0 / (Y[0] / (W * 1e-3)).sum()
+    rho = p[0] * Wbar / (8.31446261815324 * T[0])
+    ref = -(rho / dt) * np.sum(hf / (W * 1e-3) * dY[0])
+    assert hrr[0] == pytest.approx(ref, rel=1e-9)
+    assert s == pytest.approx(abs(ref), rel=1e-12)
+
+
+def test_heat_release_weights_identities():
+    """With the frozen-chemistry prediction (dY* = 0) the normalised error is
+    -HRR / s, and the labels' RMS is one in units of s."""
+    from synth import mechanism as sm, workload as sw
+    import oracle
+    mech = sm.mech_medium()
+    om = oracle.OracleMech(mech)
+    T, p, Y = sw.uniform_cells(mech, 40, 8, T_range=(900, 2400))
+    rng = np.random.default_rng(4)
+    dY = rng.normal(0, 1e-4, Y.shape)
+    dY -= dY.mean(1, keepdims=True)
+    mu, sd = rng.normal(0, 1e-5, mech.K), rng.uniform(5e-5, 2e-4, mech.K)
+    G, s, hrr = ann.hrr_label_weights(om.species_thermo, om.W, T, p, Y, Y + dY, 5e-7, sd)
+    z = (dY - mu) / sd
+    frozen = -mu / sd * np.ones_like(z)
+    e = (G * (frozen - z)).sum(1)
+    np.testing.assert_allclose(e, -hrr / s, rtol=1e-9, atol=1e-12)
+    assert np.sqrt(np.mean((hrr / s) ** 2)) == pytest.approx(1.0, rel=1e-12)
