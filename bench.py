@@ -380,9 +380,11 @@ def main():
                         "GB_per_s": post_b * n / (phases["post"]["ms_per_step"] * 1e-3) / 1e9},
                "peak_GB_per_s": PEAK_HBM_GBS}
         # the dominant kernel of the step: the DI fallback when it outweighs
-        # the network's GEMMs, else the GEMM layer with the most time
+        # the network's GEMMs, else the GEMM layer with the most work
         fb_ms = phases.get("fallback", {}).get("ms_per_step", 0.0)
-        dom = max(per_layer, key=lambda k_: per_layer[k_]["avg_launch_us"] * per_layer[k_]["launches"])
+        # (the layer with the most work: the phase timer's events inflate the
+        # short layer-1 launches, so measured time would misname it)
+        dom = max(per_layer, key=lambda k_: layer_fl[int(k_[-1]) - 1])
         roof_mlp = {"bound": "mfma", "achieved": per_layer[dom]["tflops"], "peak": PEAK_BF16_TFLOPS,
                     "unit": "TFLOP/s", "frac": per_layer[dom]["frac"],
                     "traffic": (measured_traffic("gemm_layer2") if (stock_counters and dom == "layer2")

@@ -192,14 +192,28 @@ int chemk_advance_noalloc(chemk_ctx *ctx, int64_t n, double *T, const double *p,
 
 /* Stiffness-batching autotuner (the "bins / tile shape" choice of the DI
  * path): runs DI on COPIES of the n given cells for a small grid of
- * (stiffness bins, persistent waves per CU), times each with HIP events on
- * `stream`, stores the fastest in the context (used whenever opts->bins or
- * opts->waves_per_cu is 0) and returns it in best[0] = bins,
- * best[1] = waves_per_cu, best_ms[0] = its time.  Synchronises `stream`.
- * The state arrays are not modified.                                         */
+ * (stiffness bins, persistent waves per CU), then, where the register LU
+ * exists, the LDS LU at the best pair; times each with HIP events on
+ * `stream`, stores the fastest in the context (used whenever opts->bins,
+ * opts->waves_per_cu or opts->di_kernel is 0) and returns it in
+ * best[0] = bins, best[1] = waves_per_cu, best_ms[0] = its time.
+ * Results are cached for the process, keyed by (GPU architecture, compute
+ * units, K, R, E, floor(log2 n)): a later call with the same key takes the
+ * cached choice without running anything (best_ms = the time measured
+ * then).  With the environment variable CHEMK_TUNE_CACHE naming a file, the
+ * cache is read from it on first use and rewritten after each new entry
+ * (one entry per line).  Synchronises `stream` when it tunes.  The state
+ * arrays are not modified.                                                  */
 int chemk_autotune(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
                    const double *Y, double dt, const chemk_opts *opts, int32_t best[2],
                    double *best_ms, void *stream);
+
+/* The context's tuned choice: out[0] = bins, out[1] = waves per CU,
+ * out[2] = DI factorisation (CHEMK_DI_*); zeros before any tuning.          */
+int chemk_tuning(chemk_ctx *ctx, int32_t out[3]);
+
+/* Empties the process's autotuner cache (not the CHEMK_TUNE_CACHE file).    */
+void chemk_tune_cache_clear(void);
 
 /* Phase timing (profiling aid).  While enabled, chemk_advance runs eagerly
  * (use_graph is ignored) and brackets each phase's launches with HIP events

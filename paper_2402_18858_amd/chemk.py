@@ -79,6 +79,8 @@ _SIGS = {
                                 _vp, _vp]),
     "chemk_advance_noalloc": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts), _vp,
                                         _vp, _vp]),
+    "chemk_tuning": (C.c_int, [_vp, _vp]),
+    "chemk_tune_cache_clear": (None, []),
     "chemk_autotune": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts),
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp]),
     "chemk_last_counters": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp]),
@@ -252,6 +254,12 @@ class Context:
                                   C.byref(o), best, C.byref(ms), _stream(stream)))
         return int(best[0]), int(best[1]), ms.value
 
+    def tuning(self):
+        """(bins, waves per CU, DI factorisation) the context uses when opts leave them 0."""
+        out = (C.c_int32 * 3)()
+        _check(lib.chemk_tuning(self.handle, out))
+        return int(out[0]), int(out[1]), int(out[2])
+
     def last_counters(self, stream=None):
         out = (C.c_int64 * 3)()
         _check(lib.chemk_last_counters(self.handle, out, _stream(stream)))
@@ -383,3 +391,8 @@ class Context:
 
     def ann_reset_optimizer(self):
         _check(lib.chemk_ann_reset_optimizer(self.handle))
+
+
+def tune_cache_clear():
+    """Empties the process's autotuner cache."""
+    lib.chemk_tune_cache_clear()

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <limits>
 #include <map>
 #include <memory>
@@ -179,7 +181,8 @@ struct chemk_ctx {
     unsigned long long *stats = nullptr;  // [0] routed, [1] steps, [2] failed
     unsigned long long *last_stats = nullptr;   // where the last advance wrote its counters
     void *noalloc = nullptr;              // this device's copy of the no-allocation scratch
-    int tuned_bins = 0, tuned_wpc = 0;
+    int tuned_bins = 0, tuned_wpc = 0, tuned_variant = 0;
+    std::string arch;                     // gcnArchName of the device
     std::map<GraphKey, hipGraphExec_t> graphs;
     AnnState *ann = nullptr;
     PhaseTimer timer;
@@ -246,6 +249,7 @@ extern "C" int chemk_ctx_create(int device, const chemk_mech *m, chemk_ctx **out
     auto c = std::make_unique<chemk_ctx>();
     c->device = device;
     c->cu_count = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     c->K = m->K;
     c->R = m->R;
     c->E = m->E;
@@ -480,6 +484,11 @@ static int check_opts(const chemk_ctx *c, const chemk_opts *o) {
     return CHEMK_OK;
 }
 
+// The DI factorisation: the caller's, else the tuned one, else automatic.
+static int resolve_variant(const chemk_ctx *c, const chemk_opts *o) {
+    return o->di_kernel != CHEMK_DI_AUTO ? o->di_kernel : c->tuned_variant;
+}
+
 static void resolve_tuning(const chemk_ctx *c, const chemk_opts *o, int &bins, int &wpc) {
     bins = o->bins > 0 ? o->bins : (c->tuned_bins > 0 ? c->tuned_bins : 16);
     wpc = o->waves_per_cu > 0 ? o->waves_per_cu : (c->tuned_wpc > 0 ? c->tuned_wpc : 8);
@@ -514,7 +523,7 @@ static int enqueue_di(chemk_ctx *c, const DiScratch &w, int64_t n, double *T, co
     if (timed) c->timer.begin(CHEMK_PHASE_DI, s);
     HIP_TRY(launch_di(c->dm, (int)grid64, n_items, queue, counter, T, p, Y, dt, o->rtol,
                       o->atol_Y, o->atol_T, o->h0_frac, o->max_steps, o->project, status, nsteps,
-                      w.stats, 0, o->di_kernel, s));
+                      w.stats, 0, resolve_variant(c, o), s));
     if (timed) c->timer.end(CHEMK_PHASE_DI, s);
     c->last_stats = w.stats;
     return CHEMK_OK;
@@ -548,7 +557,7 @@ extern "C" int chemk_advance(chemk_ctx *c, int64_t n, double *T, const double *p
         if (o->mode == CHEMK_MODE_DI)
             return enqueue_di(c, ctx_scratch(c), n, T, p, Y, dt, o, bins, wpc, status, nsteps, s);
         AnnStepArgs a{n, T, p, Y, dt, o->rtol, o->atol_Y, o->atol_T, o->h0_frac, o->max_steps,
-                      o->project, o->di_kernel, status, nsteps, c->cu_count * wpc, c->queue, c->small,
+                      o->project, resolve_variant(c, o), status, nsteps, c->cu_count * wpc, c->queue, c->small,
                       c->small + 1, c->stats, &c->dm, &c->timer, bins, c->bin, c->small + 2,
                       c->small + 2 + kMaxBins};
         hipError_t e = ann_enqueue_step(c->ann, a, s);
@@ -671,8 +680,64 @@ extern "C" int chemk_timing_read(chemk_ctx *c, double ms[CHEMK_NUM_PHASES],
 }
 
 // ---------------------------------------------------------------------------
-// autotuner: grid over (bins, waves per CU) on copies of the state
+// autotuner: grid over (bins, waves per CU), then the DI factorisation, on
+// copies of the state; results cached per (arch, CUs, K, R, E, log2 n)
 // ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+    std::string arch;
+    int cu, K, R, E, nlog2;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(arch, cu, K, R, E, nlog2) < std::tie(o.arch, o.cu, o.K, o.R, o.E, o.nlog2);
+    }
+};
+struct TuneVal {
+    int bins, wpc, variant;
+    double ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+std::string g_tune_loaded;   // the CHEMK_TUNE_CACHE file read into g_tune
+
+// Cache file: one entry per line, "arch cu K R E nlog2 bins wpc variant ms".
+void tune_file_load(const std::string &path) {
+    std::ifstream f(path);
+    TuneKey k;
+    TuneVal v;
+    while (f >> k.arch >> k.cu >> k.K >> k.R >> k.E >> k.nlog2 >> v.bins >> v.wpc >> v.variant >> v.ms)
+        if (v.bins >= 1 && v.bins <= 256 && v.wpc >= 1 && v.wpc <= 32 && v.variant >= 0 && v.variant <= 2)
+            g_tune.emplace(k, v);
+}
+
+void tune_file_save(const std::string &path) {
+    std::ofstream f(path, std::ios::trunc);
+    for (const auto &kv : g_tune)
+        f << kv.first.arch << ' ' << kv.first.cu << ' ' << kv.first.K << ' ' << kv.first.R << ' ' << kv.first.E
+          << ' ' << kv.first.nlog2 << ' ' << kv.second.bins << ' ' << kv.second.wpc << ' ' << kv.second.variant
+          << ' ' << kv.second.ms << '\n';
+}
+
+std::string tune_file() {
+    const char *e = std::getenv("CHEMK_TUNE_CACHE");
+    return e ? std::string(e) : std::string();
+}
+}  // namespace
+
+extern "C" void chemk_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded.clear();
+}
+
+extern "C" int chemk_tuning(chemk_ctx *c, int32_t out[3]) {
+    g_err.clear();
+    if (!c || !out) return fail(CHEMK_E_ARG, "null argument");
+    out[0] = c->tuned_bins;
+    out[1] = c->tuned_wpc;
+    out[2] = c->tuned_variant;
+    return CHEMK_OK;
+}
+
 extern "C" int chemk_autotune(chemk_ctx *c, int64_t n, const double *T, const double *p,
                               const double *Y, double dt, const chemk_opts *o, int32_t best[2],
                               double *best_ms, void *stream) {
@@ -681,6 +746,27 @@ extern "C" int chemk_autotune(chemk_ctx *c, int64_t n, const double *T, const do
     if (int r = check_n(n)) return r;
     if (int r = check_opts(c, o)) return r;
     if (n == 0 || !T || !p || !Y) return fail(CHEMK_E_ARG, "autotune needs cells");
+    int nlog2 = 0;
+    while ((int64_t(1) << (nlog2 + 1)) <= n) ++nlog2;
+    const TuneKey key{c->arch, c->cu_count, c->K, c->R, c->E, nlog2};
+    const std::string path = tune_file();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!path.empty() && g_tune_loaded != path) {
+            tune_file_load(path);
+            g_tune_loaded = path;
+        }
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            c->tuned_bins = it->second.bins;
+            c->tuned_wpc = it->second.wpc;
+            c->tuned_variant = it->second.variant;
+            best[0] = it->second.bins;
+            best[1] = it->second.wpc;
+            if (best_ms) *best_ms = it->second.ms;
+            return CHEMK_OK;
+        }
+    }
     if (int r = set_device(c)) return r;
     if (int r = ensure_capacity(c, n)) return r;
     hipStream_t s = (hipStream_t)stream;
@@ -700,38 +786,61 @@ extern "C" int chemk_autotune(chemk_ctx *c, int64_t n, const double *T, const do
     const int bins_grid[] = {1, 8, 32};
     const int wpc_grid[] = {4, 8, 12};
     double bestt = 1e300;
-    int bb = 16, bw = 8;
+    int bb = 16, bw = 8, bv = CHEMK_DI_AUTO;
     chemk_opts oo = *o;
     oo.mode = CHEMK_MODE_DI;
     oo.use_graph = 0;
     int rc = CHEMK_OK;
+    // one timed DI advance of the copies; returns its milliseconds or < 0
+    auto trial = [&](int b, int w, int v) -> double {
+        if (hipMemcpyAsync(Tc, T, 8 * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(Yc, Y, 8 * n * K, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            rc = fail(CHEMK_E_HIP, "autotune copy");
+            return -1.0;
+        }
+        oo.di_kernel = v;
+        hipEventRecord(e0, s);
+        if ((rc = enqueue_di(c, ctx_scratch(c), n, Tc, p, Yc, dt, &oo, b, w, st, nullptr, s))) return -1.0;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(CHEMK_E_HIP, "autotune sync");
+            return -1.0;
+        }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    const int v0 = o->di_kernel;   // the caller's factorisation (automatic unless fixed)
     for (int b : bins_grid)
         for (int w : wpc_grid) {
-            if (hipMemcpyAsync(Tc, T, 8 * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(Yc, Y, 8 * n * K, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-                rc = fail(CHEMK_E_HIP, "autotune copy");
-                goto done;
-            }
-            hipEventRecord(e0, s);
-            if ((rc = enqueue_di(c, ctx_scratch(c), n, Tc, p, Yc, dt, &oo, b, w, st, nullptr, s))) goto done;
-            hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                rc = fail(CHEMK_E_HIP, "autotune sync");
-                goto done;
-            }
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
+            const double ms = trial(b, w, v0);
+            if (ms < 0) goto done;
             if (ms < bestt) {
                 bestt = ms;
                 bb = b;
                 bw = w;
+                bv = v0;
             }
         }
+    if (v0 == CHEMK_DI_AUTO && di_has_reg_lu(c->N)) {
+        const double ms = trial(bb, bw, CHEMK_DI_LDS_LU);
+        if (ms < 0) goto done;
+        if (ms < bestt) {
+            bestt = ms;
+            bv = CHEMK_DI_LDS_LU;
+        }
+    }
     c->tuned_bins = bb;
     c->tuned_wpc = bw;
+    c->tuned_variant = bv;
     best[0] = bb;
     best[1] = bw;
     if (best_ms) *best_ms = bestt;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = TuneVal{bb, bw, bv, bestt};
+        if (!path.empty()) tune_file_save(path);
+    }
 done:
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -226,3 +226,46 @@ def test_di_register_lu_unavailable_size_is_an_argument_error(which):
     with pytest.raises(chemk.ChemkError) as e:
         _run(ctx, T, p, Y, 1e-7, di_kernel=chemk.DI_REG_LU)
     assert e.value.code == chemk.E_ARG
+
+
+def test_autotune_cache_and_factorisation_axis(tmp_path, monkeypatch):
+    """The autotuner also chooses the factorisation, caches its choice per
+    (arch, CUs, K, R, E, log2 n) for the process and in CHEMK_TUNE_CACHE, and
+    a cached key is answered without running DI."""
+    import time
+    from paper_2402_18858_amd import chemk
+    mech = sm.mech_medium()
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("CHEMK_TUNE_CACHE", str(path))
+    chemk.tune_cache_clear()
+    T, p, Y, _ = sw.flame_block(mech, 16, 2004)
+    Td, pd, Yd = dev(T), dev(p), dev(Y)
+    ctx = chemk.Context(mech)
+    t0 = time.time()
+    b1 = ctx.autotune(Td, pd, Yd, 5e-7)
+    t1 = time.time() - t0
+    tun = ctx.tuning()
+    assert tun[:2] == b1[:2] and tun[2] in (chemk.DI_AUTO, chemk.DI_LDS_LU)
+    fields = path.read_text().split()
+    assert len(fields) == 10 and fields[0].startswith("gfx950")
+    assert [int(v) for v in fields[6:9]] == list(tun)
+    announce(f"autotune: bins {tun[0]}, waves/CU {tun[1]}, factorisation {tun[2]} in {t1:.2f} s")
+    ctx2 = chemk.Context(mech)
+    t0 = time.time()
+    b2 = ctx2.autotune(Td, pd, Yd, 5e-7)
+    t2 = time.time() - t0
+    assert b2 == b1 and ctx2.tuning() == tun
+    assert t2 < 0.5 * t1, (t1, t2)
+    # an emptied process cache is refilled from the file
+    chemk.tune_cache_clear()
+    ctx3 = chemk.Context(mech)
+    b3 = ctx3.autotune(Td, pd, Yd, 5e-7)
+    assert b3[:2] == b1[:2] and ctx3.tuning() == tun
+    # the tuned context's advance equals one with the choice spelled out
+    a = _run(ctx3, T, p, Y, 5e-7)
+    c = _run(ctx3, T, p, Y, 5e-7, bins=tun[0], waves_per_cu=tun[1],
+             di_kernel=tun[2] if tun[2] else chemk.DI_REG_LU)
+    for x, y_ in zip(a, c):
+        assert np.array_equal(x, y_)
+    monkeypatch.delenv("CHEMK_TUNE_CACHE")
+    chemk.tune_cache_clear()
