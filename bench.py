@@ -75,6 +75,53 @@ def measured_traffic(key, routed=None):
     return entry["bytes"] if h.hexdigest()[:16] == entry["sources_sha1"] else None
 
 
+def closure_timing(ctx, mech, Tin, P, Yin, T_a, Y_a, dt, log, reps=10):
+    """The steps either side of the advance on the block: mixture viscosity
+    and conductivity (chemk_transport) and the PaSR closure of the ANN step's
+    result (chemk_pasr), HIP-event timed over `reps` launches each, with their
+    algorithmic HBM bytes per cell (inputs read once, outputs written once)."""
+    import torch
+    from synth import transport as st
+
+    dev = "cuda:0"
+    n, K = Yin.shape
+    mu_c, lam_c = st.transport_fits(mech)
+    ctx.transport_set(mu_c, lam_c)
+    mu = torch.empty(n, dtype=torch.float64, device=dev)
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Y1 = torch.from_numpy(np.ascontiguousarray(Y_a)).to(dev)
+    rng = np.random.default_rng(9)
+    ksgs = torch.from_numpy(10.0 ** rng.uniform(-1, 2, n)).to(dev)
+    delta = torch.full((n,), 1e-3, dtype=torch.float64, device=dev)
+    kap = torch.empty(n, dtype=torch.float64, device=dev)
+    om = torch.empty((n, K), dtype=torch.float64, device=dev)
+    Yb = torch.empty((n, K), dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_tr = timed(lambda: ctx.transport(Tin, Yin, mu, lam))
+    t_pa = timed(lambda: ctx.pasr(Tin, P, Yin, Y1, dt, ksgs, delta, mu, kappa=kap, omega=om, Y_out=Yb))
+    b_tr = 8 * (1 + K) + 16                   # T, Y in; mu, lambda out
+    b_pa = 8 * (2 + 2 * K + 3) + 8 * (1 + 2 * K)   # T, p, Y0, Y1, k, delta, mu in; kappa, omega, Y out
+    k_h = kap.cpu().numpy()
+    log(f"closure: transport {t_tr:.3f} ms, PaSR {t_pa:.3f} ms on {n} cells")
+    return {"cells": n, "transport_ms": t_tr, "transport_bytes_per_cell": b_tr,
+            "transport_GB_per_s": b_tr * n / (t_tr * 1e-3) / 1e9,
+            "pasr_ms": t_pa, "pasr_bytes_per_cell": b_pa,
+            "pasr_GB_per_s": b_pa * n / (t_pa * 1e-3) / 1e9, "peak_GB_per_s": PEAK_HBM_GBS,
+            "kappa_p10_p50_p90": [float(np.percentile(k_h, q)) for q in (10, 50, 90)],
+            "inputs": "transport fits of synth/transport.py; k_sgs ~ 10^U[-1,2] m^2/s^2, delta = 1 mm"}
+
+
 def element_mass(mech, Y):
     comp = mech.composition.astype(np.float64)
     Em = comp * mech.element_mass[None, :] / (comp @ mech.element_mass)[:, None]
@@ -424,6 +471,7 @@ def main():
                                "speedup_over_di": ann_cups / di_cups, "error_vs_di": acc_ann}})
         log(f"ANN: {1e3 * wall_a / args.steps:.3f} ms per step, {ann_cups:.4g} cell-updates/s, "
             f"routed {int(routed_all.sum())}")
+        result["closure"] = closure_timing(ctx, mech, Tin, P, Yin, T_a, Y_a, dt, log)
         if args.envelope_sweep:
             result["ann"]["envelope_sweep"] = envelope_sweep(ctx, mech, dt, Tin, P, Yin, o_ann, region,
                                                              T_di, Y_di, sd_y, di_idx, log)

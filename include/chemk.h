@@ -130,6 +130,42 @@ int chemk_rhs(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
 int chemk_jacobian(chemk_ctx *ctx, int64_t n, const double *T, const double *p,
                    const double *Y, double *J, void *stream);
 
+/* ---- the steps either side of the advance ------------------------------------ */
+/* Transport properties (Sec. II.A: properties updated from temperature
+ * polynomials).  chemk_transport_set stores, per species k, the coefficients
+ * of ln mu_k [Pa s] and ln lambda_k [W/(m K)] as cubic polynomials in ln T
+ * (ascending powers; mu_poly, lam_poly host arrays [K*4]).  chemk_transport
+ * then gives per cell the mixture viscosity by Wilke's rule,
+ *   mu = sum_i X_i mu_i / sum_j X_j (1 + (mu_i/mu_j)^(1/2) (W_j/W_i)^(1/4))^2
+ *        / (8 (1 + W_i/W_j))^(1/2),
+ * and the conductivity by the average of Mathur, Tondon and Saxena,
+ *   lambda = (sum_k X_k lambda_k + 1 / sum_k X_k / lambda_k) / 2,
+ * X the mole fractions of Y.  T [n], Y [n, K] in; mu [n] and lam [n] (NULL
+ * allowed) out; device arrays, asynchronous on `stream`.  CHEMK_E_STATE
+ * before chemk_transport_set.                                               */
+int chemk_transport_set(chemk_ctx *ctx, const double *mu_poly, const double *lam_poly);
+int chemk_transport(chemk_ctx *ctx, int64_t n, const double *T, const double *Y, double *mu,
+                    double *lam, void *stream);
+
+/* The PaSR closure of one flow step (Sec. III: the network or DI replaces
+ * only the integration inside the partially stirred reactor model).  From the
+ * state before (T, p, Y0) and after (Y1) the chemistry advance over dt, per
+ * cell: rho the density of (T, p, Y0); omega_k = rho (Y1_k - Y0_k) / dt;
+ * tau_c = max over species with omega_k > 0 and Y1_k >= y_min of
+ * rho Y1_k / omega_k (the slowest formation; none: kappa = 1);
+ * u' = (2 k_sgs / 3)^(1/2), tau_Delta = delta / u',
+ * epsilon = c_eps k_sgs^(3/2) / delta, tau_K = (mu / rho / epsilon)^(1/2),
+ * tau_mix = (tau_Delta tau_K)^(1/2) (k_sgs <= 0: kappa = 0);
+ * kappa = tau_c / (tau_c + tau_mix).  Outputs (NULL allowed, not all):
+ * kappa [n], omega [n, K] = kappa omega_k in kg/(m^3 s), Y_out [n, K] =
+ * Y0 + kappa (Y1 - Y0).  k_sgs [m^2/s^2], delta [m] (filter width) and mu
+ * [Pa s] (e.g. from chemk_transport) are per cell.  Defaults of the
+ * readings: c_eps = 1.048, y_min = 1e-6.  Device arrays, asynchronous.      */
+int chemk_pasr(chemk_ctx *ctx, int64_t n, const double *T, const double *p, const double *Y0,
+               const double *Y1, double dt, const double *k_sgs, const double *delta,
+               const double *mu, double c_eps, double y_min, double *kappa, double *omega,
+               double *Y_out, void *stream);
+
 /* ---- the chemistry advance (Eqs. 1-2) --------------------------------------- */
 enum { CHEMK_MODE_DI = 0, CHEMK_MODE_ANN = 1 };
 
@@ -359,12 +395,19 @@ int chemk_ann_hrr_weights(chemk_ctx *ctx, int64_t n, const double *T, const doub
  *   w_hrr * mean_i (sum_k G_ik (out_ik - z_ik))^2
  *     (Eq. 10 in units of the scale of chemk_ann_hrr_weights),
  * with G [rows of X, K] the weights of chemk_ann_hrr_weights (NULL allowed
- * when w_hrr = 0).  loss (device FP32 scalar, may be NULL) receives the batch
- * loss before the update.  grads (device FP32 [param_count], may be NULL)
- * receives the gradient; with update = 0 the weights are left unchanged.     */
+ * when w_hrr = 0).  out_w (device FP32 [K], may be NULL) weights the data
+ * term per output: sum_k w_k (out_ik - z_ik)^2 / (B sum_k w_k) replaces the
+ * plain mean (all w_k = 1 when NULL); a one-hot out_w trains a network on one
+ * species alone (the per-species ensemble the paper names as an alternative
+ * in Sec. II.B).  Weights must be finite, >= 0 and not all zero, else
+ * CHEMK_E_HIP with the message naming them.  loss (device FP32 scalar, may
+ * be NULL) receives the batch loss before the update.  grads (device FP32
+ * [param_count], may be NULL) receives the gradient in the layout of
+ * chemk_ann_get_weights; with update = 0 the weights are left unchanged.      */
 int chemk_ann_train_step(chemk_ctx *ctx, const int32_t *idx, int32_t B, const uint16_t *X,
-                         const float *Z, const float *G, float w_mass, float w_hrr, float lr,
-                         int32_t update, float *loss, float *grads, void *stream);
+                         const float *Z, const float *G, float w_mass, float w_hrr,
+                         const float *out_w, float lr, int32_t update, float *loss,
+                         float *grads, void *stream);
 
 /* The training loop (Sec. II.B: Adam on the loss of Eq. 8), on the device.
  * Rows of the packed training set (X [n, 64] BF16 bits, 16-byte aligned; Z
@@ -390,6 +433,8 @@ typedef struct {
     float w_mass, w_hrr;     /* weights of the mass and heat-release losses (W2, W3
                                 of Eq. 11, chemk_ann_train_step); 0 = data loss only */
     const float *G;          /* [n, K] heat-release weights (w_hrr > 0), device  */
+    const float *out_w;      /* [K] per-output weights of the data term
+                                (chemk_ann_train_step), device; NULL = all 1     */
 } chemk_train_opts;
 int chemk_ann_train(chemk_ctx *ctx, int64_t n, const uint16_t *X, const float *Z,
                     const uint16_t *X_hold, const float *Z_hold, int64_t n_hold,

@@ -150,9 +150,14 @@ def hrr_label_weights(species_thermo, W_g, T, p, Y, Y_next, dt, sd_y, scale=None
     return G, scale, hrr
 
 
-def phys_loss(out, target, mu_y, sd_y, G, w_mass, w_hrr):
+def phys_loss(out, target, mu_y, sd_y, G, w_mass, w_hrr, out_w=None):
     """Eq. 11 with W1 = 1 on z-scored outputs: the data loss of Eq. 8 plus
     w_mass times Eq. 9 and w_hrr times Eq. 10, and d(loss)/d(out).
+
+    out_w [K] (optional) weights the data loss per output:
+    sum_ik w_k d_ik^2 / (B sum_k w_k), the plain mean when all w_k are equal; a
+    one-hot out_w is the loss of a network trained for one species alone (the
+    per-species ensemble of Sec. II.B).
 
     Eq. 9: the predicted Y(t+dt) = Y + mu + sd out sums to one plus
     m_i = sum_k (mu_k + sd_k out_ik) (the inputs sum to one); the term is
@@ -163,8 +168,13 @@ def phys_loss(out, target, mu_y, sd_y, G, w_mass, w_hrr):
     target = np.asarray(target, np.float64)
     B = out.shape[0]
     d = out - target
-    loss = float(np.mean(d * d))
-    grad = 2.0 * d / d.size
+    if out_w is None:
+        loss = float(np.mean(d * d))
+        grad = 2.0 * d / d.size
+    else:
+        w = np.asarray(out_w, np.float64)
+        loss = float((w[None, :] * d * d).sum() / (B * w.sum()))
+        grad = 2.0 * w[None, :] * d / (B * w.sum())
     mu_y = np.asarray(mu_y, np.float64)
     sd_y = np.asarray(sd_y, np.float64)
     if w_mass:

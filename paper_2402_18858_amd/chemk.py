@@ -57,7 +57,7 @@ class AnnChecks(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr0", C.c_float), ("lr1", C.c_float),
                 ("seed", C.c_uint64), ("use_graph", C.c_int32), ("w_mass", C.c_float),
-                ("w_hrr", C.c_float), ("G", C.c_void_p)]
+                ("w_hrr", C.c_float), ("G", C.c_void_p), ("out_w", C.c_void_p)]
 
 
 _vp = C.c_void_p
@@ -79,6 +79,10 @@ _SIGS = {
                                 _vp, _vp]),
     "chemk_advance_noalloc": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts), _vp,
                                         _vp, _vp]),
+    "chemk_transport_set": (C.c_int, [_vp, _vp, _vp]),
+    "chemk_transport": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "chemk_pasr": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp, _vp, C.c_double,
+                             C.c_double, _vp, _vp, _vp, _vp]),
     "chemk_tuning": (C.c_int, [_vp, _vp]),
     "chemk_tune_cache_clear": (None, []),
     "chemk_autotune": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.c_double, C.POINTER(Opts),
@@ -103,7 +107,7 @@ _SIGS = {
     "chemk_ann_pack": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "chemk_ann_forward_packed": (C.c_int, [_vp, _i64, _vp, _vp, _vp]),
     "chemk_ann_train_step": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp, C.c_float, C.c_float,
-                                       C.c_float, C.c_int32, _vp, _vp, _vp]),
+                                       _vp, C.c_float, C.c_int32, _vp, _vp, _vp]),
     "chemk_ann_hrr_weights": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _vp,
                                         C.POINTER(C.c_double), _vp]),
     "chemk_ann_train": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, C.POINTER(TrainOpts), _vp, _vp,
@@ -254,6 +258,21 @@ class Context:
                                   C.byref(o), best, C.byref(ms), _stream(stream)))
         return int(best[0]), int(best[1]), ms.value
 
+    def transport_set(self, mu_poly, lam_poly):
+        mu_poly = np.ascontiguousarray(mu_poly, np.float64)
+        lam_poly = np.ascontiguousarray(lam_poly, np.float64)
+        _check(lib.chemk_transport_set(self.handle, mu_poly.ctypes.data, lam_poly.ctypes.data))
+
+    def transport(self, T, Y, mu, lam=None, stream=None):
+        _check(lib.chemk_transport(self.handle, T.numel(), _ptr(T), _ptr(Y), _ptr(mu), _ptr(lam),
+                                   _stream(stream)))
+
+    def pasr(self, T, p, Y0, Y1, dt, k_sgs, delta, mu, kappa=None, omega=None, Y_out=None,
+             c_eps=1.048, y_min=1e-6, stream=None):
+        _check(lib.chemk_pasr(self.handle, T.numel(), _ptr(T), _ptr(p), _ptr(Y0), _ptr(Y1), float(dt),
+                              _ptr(k_sgs), _ptr(delta), _ptr(mu), float(c_eps), float(y_min), _ptr(kappa),
+                              _ptr(omega), _ptr(Y_out), _stream(stream)))
+
     def tuning(self):
         """(bins, waves per CU, DI factorisation) the context uses when opts leave them 0."""
         out = (C.c_int32 * 3)()
@@ -365,9 +384,9 @@ class Context:
         _check(lib.chemk_ann_forward_packed(self.handle, n, _ptr(X), _ptr(out), _stream(stream)))
 
     def ann_train_step(self, idx, X, Z, lr, update=True, loss=None, grads=None, stream=None,
-                       G=None, w_mass=0.0, w_hrr=0.0):
+                       G=None, w_mass=0.0, w_hrr=0.0, out_w=None):
         _check(lib.chemk_ann_train_step(self.handle, _ptr(idx), idx.numel(), _ptr(X), _ptr(Z), _ptr(G),
-                                        float(w_mass), float(w_hrr), float(lr), int(bool(update)),
+                                        float(w_mass), float(w_hrr), _ptr(out_w), float(lr), int(bool(update)),
                                         _ptr(loss), _ptr(grads), _stream(stream)))
 
     def ann_hrr_weights(self, T, P, Y, Y_next, dt, G, scale=0.0, stream=None):
@@ -378,10 +397,10 @@ class Context:
         return out.value
 
     def ann_train(self, X, Z, epochs, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001, X_hold=None,
-                  Z_hold=None, use_graph=True, stream=None, G=None, w_mass=0.0, w_hrr=0.0):
+                  Z_hold=None, use_graph=True, stream=None, G=None, w_mass=0.0, w_hrr=0.0, out_w=None):
         """Returns (epoch_loss, hold_loss) as host arrays [epochs]."""
         o = TrainOpts(int(batch), int(epochs), float(lr0), float(lr1), int(seed), int(bool(use_graph)),
-                      float(w_mass), float(w_hrr), _ptr(G))
+                      float(w_mass), float(w_hrr), _ptr(G), _ptr(out_w))
         el = np.zeros(epochs, np.float32)
         hl = np.zeros(epochs, np.float32)
         nh = 0 if X_hold is None else X_hold.shape[0]

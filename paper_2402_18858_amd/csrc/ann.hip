@@ -644,27 +644,28 @@ __global__ void mse_kernel(const float *__restrict__ out, const float *__restric
 // release term w_hrr e^2 with e = sum_k G_k d_k; both averaged over rows.
 // dOut = bf16 of the gradient of the total, rounded once.
 __global__ void phys_loss_kernel(const float *__restrict__ out, const float *__restrict__ tgt,
-                                 const float *__restrict__ G, int B, int K, const double *__restrict__ mu,
-                                 const double *__restrict__ sd, float inv_S, float w_mass, float w_hrr,
-                                 uint16_t *dout, LossSink sink) {
+                                 const float *__restrict__ G, const float *__restrict__ ow, float inv_wsum, int B,
+                                 int K, const double *__restrict__ mu, const double *__restrict__ sd, float inv_S,
+                                 float w_mass, float w_hrr, uint16_t *dout, LossSink sink) {
     __shared__ float red[256];
     float s = 0.f;
-    const float sc = 2.0f / (float)(B * K), rb = 1.0f / (float)B;
+    // data term: sum_k w_k d_k^2 / (B sum_k w_k), w_k = 1 without per-output weights
+    const float sc = 2.0f * inv_wsum / (float)B, rb = 1.0f / (float)B;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x) {
         const float *o = out + (size_t)i * K, *t = tgt + (size_t)i * K;
         const float *g = G ? G + (size_t)i * K : nullptr;
         float dd = 0.f, m = 0.f, e = 0.f;
         for (int k = 0; k < K; ++k) {
             const float d = o[k] - t[k];
-            dd += d * d;
+            dd += (ow ? ow[k] : 1.f) * d * d;
             m += (float)mu[k] + (float)sd[k] * o[k];
             if (g) e += g[k] * d;
         }
-        s += dd / (float)(B * K) + w_mass * fabsf(m) * inv_S * rb + (g ? w_hrr * e * e * rb : 0.f);
+        s += dd * inv_wsum * rb + w_mass * fabsf(m) * inv_S * rb + (g ? w_hrr * e * e * rb : 0.f);
         const float cm = w_mass * (m > 0.f ? 1.f : (m < 0.f ? -1.f : 0.f)) * inv_S * rb;
         const float ce = g ? 2.0f * w_hrr * e * rb : 0.f;
         for (int k = 0; k < K; ++k) {
-            const float gr = (o[k] - t[k]) * sc + cm * (float)sd[k] + (g ? ce * g[k] : 0.f);
+            const float gr = (ow ? ow[k] : 1.f) * (o[k] - t[k]) * sc + cm * (float)sd[k] + (g ? ce * g[k] : 0.f);
             dout[(size_t)i * K + k] = f2bf(gr);
         }
     }
@@ -1474,9 +1475,8 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
     if (dims[L] != K) ANN_FAIL(CHEMK_E_ARG, "dims[L]=%d must be K=%d", dims[L], K);
     if (K + 2 > FPAD) ANN_FAIL(CHEMK_E_UNSUPPORTED, "K+2 > %d inputs", FPAD);
     for (int l = 1; l < L; ++l)
-        if (dims[l] < 8 || dims[l] % 64 != 0 || dims[l] > 8192)
-            ANN_FAIL(CHEMK_E_UNSUPPORTED, "hidden width %d must be a multiple of 64 in [64, 8192]",
-                     dims[l]);
+        if (dims[l] < 8 || dims[l] > 8192)
+            ANN_FAIL(CHEMK_E_UNSUPPORTED, "hidden width %d outside [8, 8192]", dims[l]);
     if (hipSetDevice(ctx_device(c)) != hipSuccess) ANN_FAIL(CHEMK_E_HIP, "hipSetDevice");
     ann_destroy(ctx_ann(c));
     ctx_ann(c) = nullptr;
@@ -1485,8 +1485,12 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
     a->F = K + 2;
     a->L = L;
     a->dims.assign(dims, dims + L + 1);
+    // padded widths: the input to the GEMMs' K step, hidden layers to whole
+    // 64-column slabs (the padding units have zero weights and biases, so
+    // their GELU output and every gradient through them stay zero)
     a->pd = a->dims;
     a->pd[0] = FPAD;
+    for (int l = 1; l < L; ++l) a->pd[l] = (dims[l] + 63) / 64 * 64;
     size_t off = 0, pub = 0;
     for (int l = 0; l < L; ++l) {
         a->woff.push_back(off);
@@ -1537,26 +1541,28 @@ extern "C" int chemk_ann_param_count(chemk_ctx *c, int64_t *count) {
 }
 
 // public layout <-> internal (layer 0 rows padded from K+2 to FPAD inputs)
+// Public layout: per layer W [dims[l] x dims[l+1]] row-major, then b; the
+// internal one pads rows to pd[l] and columns to pd[l+1] with zeros.
 static void pub_to_int(const AnnState *a, const float *pub, std::vector<float> &in) {
     in.assign(a->nparam, 0.f);
     size_t p = 0;
     for (int l = 0; l < a->L; ++l) {
-        const size_t w = (size_t)a->dims[l] * a->dims[l + 1];
-        std::memcpy(in.data() + a->woff[l], pub + p, 4 * w);
-        p += w;
-        std::memcpy(in.data() + a->boff[l], pub + p, 4 * a->dims[l + 1]);
-        p += a->dims[l + 1];
+        const int r = a->dims[l], cl = a->dims[l + 1], ld = a->pd[l + 1];
+        for (int i = 0; i < r; ++i) std::memcpy(in.data() + a->woff[l] + (size_t)i * ld, pub + p + (size_t)i * cl, 4 * cl);
+        p += (size_t)r * cl;
+        std::memcpy(in.data() + a->boff[l], pub + p, 4 * cl);
+        p += cl;
     }
 }
 
 static void int_to_pub(const AnnState *a, const float *in, float *pub) {
     size_t p = 0;
     for (int l = 0; l < a->L; ++l) {
-        const size_t w = (size_t)a->dims[l] * a->dims[l + 1];
-        std::memcpy(pub + p, in + a->woff[l], 4 * w);
-        p += w;
-        std::memcpy(pub + p, in + a->boff[l], 4 * a->dims[l + 1]);
-        p += a->dims[l + 1];
+        const int r = a->dims[l], cl = a->dims[l + 1], ld = a->pd[l + 1];
+        for (int i = 0; i < r; ++i) std::memcpy(pub + p + (size_t)i * cl, in + a->woff[l] + (size_t)i * ld, 4 * cl);
+        p += (size_t)r * cl;
+        std::memcpy(pub + p, in + a->boff[l], 4 * cl);
+        p += cl;
     }
 }
 
@@ -1954,15 +1960,33 @@ static hipError_t ensure_train(AnnState *a, int B) {
 
 // One training step's forward (saving Z and A), loss and backward on rows
 // idx[0..B-1] of (X, Z): the gradient lands in a->grad, the batch loss in sink.
+// Sum of the per-output weights of the data term (device [K]): read once,
+// checked finite, >= 0 and not all zero.
+static hipError_t out_weight_sum(const AnnState *a, const float *w, float *sum) {
+    std::vector<float> h(a->K);
+    hipError_t e = hipMemcpy(h.data(), w, 4 * (size_t)a->K, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    double s = 0.0;
+    for (float v : h) {
+        if (!(v >= 0.f) || !std::isfinite(v)) return hipErrorInvalidValue;
+        s += v;
+    }
+    if (!(s > 0.0)) return hipErrorInvalidValue;
+    *sum = (float)s;
+    return hipSuccess;
+}
+
 // Loss weights of the physics terms (Eq. 11's W2, W3) and the heat-release
 // weights G of the training rows (NULL when w_hrr = 0).
 struct PhysLoss {
     const float *G;
     float w_mass, w_hrr;
+    const float *out_w;   // per-output weights of the data term (device [K]), NULL = all 1
+    float out_wsum;       // their sum
 };
 
 static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t *X, const float *Z,
-                          LossSink sink, hipStream_t s, PhysLoss ph = PhysLoss{nullptr, 0.f, 0.f}) {
+                          LossSink sink, hipStream_t s, PhysLoss ph = PhysLoss{nullptr, 0.f, 0.f, nullptr, 0.f}) {
     const int K = a->K, L = a->L;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(B), dim3(64), 0, s, idx, B, X, FPAD, Z, K, a->tX, a->tZt);
     const bool hrr = ph.w_hrr != 0.f && ph.G;
@@ -1971,13 +1995,14 @@ static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t
     hipError_t e;
     if ((e = mlp_forward(a, a->tX, B, a->tOut, nullptr, nullptr, s, a->tZ.data(), a->tA.data())) != hipSuccess)
         return e;
-    if (ph.w_mass != 0.f || hrr) {
+    if (ph.w_mass != 0.f || hrr || ph.out_w) {
         double S = 0.0;
         for (int k = 0; k < K; ++k) S += a->sd_y[k];
         const NormDev nd = norm_dev(a);
+        const float inv_wsum = ph.out_w ? 1.0f / ph.out_wsum : 1.0f / (float)K;
         hipLaunchKernelGGL(phys_loss_kernel, dim3((B + 255) / 256), dim3(256), 0, s, a->tOut, a->tZt,
-                           hrr ? a->tGt : nullptr, B, K, nd.mu_y, nd.sd_y, (float)(1.0 / S), ph.w_mass,
-                           hrr ? ph.w_hrr : 0.f, a->tdZ[0], sink);
+                           hrr ? a->tGt : nullptr, ph.out_w, inv_wsum, B, K, nd.mu_y, nd.sd_y, (float)(1.0 / S),
+                           ph.w_mass, hrr ? ph.w_hrr : 0.f, a->tdZ[0], sink);
     } else {
         hipLaunchKernelGGL(mse_kernel, dim3(std::min(1024, (B * K + 255) / 256)), dim3(256), 0, s, a->tOut,
                            a->tZt, B * K, a->tdZ[0], sink);
@@ -2023,8 +2048,9 @@ static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t
 }
 
 extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B, const uint16_t *X,
-                                    const float *Z, const float *G, float w_mass, float w_hrr, float lr,
-                                    int32_t update, float *loss, float *grads, void *stream) {
+                                    const float *Z, const float *G, float w_mass, float w_hrr,
+                                    const float *out_w, float lr, int32_t update, float *loss, float *grads,
+                                    void *stream) {
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
@@ -2039,13 +2065,18 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
     hipStream_t s = (hipStream_t)stream;
     const int L = a->L;
     hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, s, a->tLoss, 1);
-    ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s, PhysLoss{G, w_mass, w_hrr}));
+    float wsum = 0.f;
+    if (out_w) ANN_TRY(out_weight_sum(a, out_w, &wsum));
+    ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s,
+                    PhysLoss{G, w_mass, w_hrr, out_w, wsum}));
     if (loss) ANN_TRY(hipMemcpyAsync(loss, a->tLoss, 4, hipMemcpyDeviceToDevice, s));
     if (grads) {
         size_t p = 0;
         for (int l = 0; l < L; ++l) {
             const size_t w = (size_t)a->dims[l] * a->dims[l + 1];
-            ANN_TRY(hipMemcpyAsync(grads + p, a->grad + a->woff[l], 4 * w, hipMemcpyDeviceToDevice, s));
+            ANN_TRY(hipMemcpy2DAsync(grads + p, 4 * (size_t)a->dims[l + 1], a->grad + a->woff[l],
+                                     4 * (size_t)a->pd[l + 1], 4 * (size_t)a->dims[l + 1], a->dims[l],
+                                     hipMemcpyDeviceToDevice, s));
             p += w;
             ANN_TRY(hipMemcpyAsync(grads + p, a->grad + a->boff[l], 4 * a->dims[l + 1],
                                    hipMemcpyDeviceToDevice, s));
@@ -2100,6 +2131,8 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
     if (!(o->w_mass >= 0) || !(o->w_hrr >= 0) || !std::isfinite(o->w_mass) || !std::isfinite(o->w_hrr))
         ANN_FAIL(CHEMK_E_ARG, "loss weights must be finite and >= 0");
     if (o->w_hrr > 0 && !o->G) ANN_FAIL(CHEMK_E_ARG, "w_hrr > 0 needs the heat-release weights G");
+    float owsum = 0.f;
+    if (o->out_w) ANN_TRY(out_weight_sum(a, o->out_w, &owsum));
     if (reinterpret_cast<uintptr_t>(X) % 16 || (X_hold && reinterpret_cast<uintptr_t>(X_hold) % 16))
         ANN_FAIL(CHEMK_E_ARG, "X must be 16-byte aligned");
     hipStream_t s0 = (hipStream_t)stream;
@@ -2145,7 +2178,7 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
             hipLaunchKernelGGL(batch_index_kernel, dim3((B + 255) / 256), dim3(256), 0, st, ctl, B, spe,
                                (unsigned int)n, half, (unsigned long long)o->seed, idx);
             hipError_t ee = fwd_bwd(a, idx, B, X, Z, LossSink{eloss, ctl, spe, 1.0f / (float)spe}, st,
-                                    PhysLoss{o->G, o->w_mass, o->w_hrr});
+                                    PhysLoss{o->G, o->w_mass, o->w_hrr, o->out_w, owsum});
             if (ee != hipSuccess) return ee;
             hipLaunchKernelGGL(adam_sched_kernel, dim3(gadam), dim3(256), 0, st, a->master, a->grad, a->m1,
                                a->m2, (int64_t)a->nparam, ctl, (double)o->lr0, (double)o->lr1, total, 0.9,

@@ -185,6 +185,7 @@ struct chemk_ctx {
     std::string arch;                     // gcnArchName of the device
     std::map<GraphKey, hipGraphExec_t> graphs;
     AnnState *ann = nullptr;
+    void *transport = nullptr;            // transport-property tables (closure.hip)
     PhaseTimer timer;
 };
 
@@ -192,6 +193,7 @@ static constexpr int kMaxBins = 256;
 
 // accessors for the learned part (ann.hip)
 AnnState *&ctx_ann(chemk_ctx *c) { return c->ann; }
+void *&ctx_transport(chemk_ctx *c) { return c->transport; }
 int ctx_device(chemk_ctx *c) { return c->device; }
 int ctx_K(chemk_ctx *c) { return c->K; }
 void ctx_set_error(const char *msg) { g_err = msg; }
@@ -365,6 +367,7 @@ extern "C" void chemk_ctx_free(chemk_ctx *c) {
     hipSetDevice(c->device);
     for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second);
     ann_destroy(c->ann);
+    transport_destroy(c->transport);
     hipFree(c->tables);
     hipFree(c->bin);
     hipFree(c->queue);

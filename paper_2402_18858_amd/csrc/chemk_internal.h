@@ -71,6 +71,7 @@ hipError_t launch_di(const DevMech &m, int grid, const int *n_items, const int *
                      int project, int *status, int *nsteps, unsigned long long *stats,
                      int status_or, int variant, hipStream_t s);
 bool di_has_reg_lu(int N);
+void transport_destroy(void *t);
 hipError_t launch_binning(const DevMech &m, int n, const double *T, const double *p,
                           const double *Y, double dt, int bins, int *bin, int *hist, int *offs,
                           int *queue, hipStream_t s);

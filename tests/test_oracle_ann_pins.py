@@ -261,6 +261,49 @@ def test_phys_loss_gradient_matches_finite_differences():
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-9)
 
 
+def test_output_weights_one_hot_uniform_and_by_hand():
+    """Per-output weights of the data term: a one-hot w is the mean squared
+    error of that column alone (the loss of a one-species network), uniform
+    weights of any size give the plain mean, and a hand case."""
+    rng = np.random.default_rng(3)
+    B, K = 9, 6
+    o, t = rng.normal(size=(B, K)), rng.normal(size=(B, K))
+    for k in range(K):
+        w = np.zeros(K)
+        w[k] = 1.0
+        loss, g = ann.phys_loss(o, t, np.zeros(K), np.ones(K), None, 0.0, 0.0, out_w=w)
+        assert loss == pytest.approx(float(np.mean((o[:, k] - t[:, k]) ** 2)), rel=1e-14)
+        assert np.all(g[:, np.arange(K) != k] == 0.0)
+        np.testing.assert_allclose(g[:, k], 2.0 * (o[:, k] - t[:, k]) / B, rtol=1e-14)
+    a, ga = ann.phys_loss(o, t, np.zeros(K), np.ones(K), None, 0.0, 0.0)
+    b, gb = ann.phys_loss(o, t, np.zeros(K), np.ones(K), None, 0.0, 0.0, out_w=np.full(K, 3.5))
+    assert b == pytest.approx(a, rel=1e-14)
+    np.testing.assert_allclose(gb, ga, rtol=1e-14)
+    # two rows, two outputs, w = (1, 3): d = ((1, 2), (0, -1)) ->
+    # (1*1 + 3*4 + 0 + 3*1) / (2 * 4) = 16 / 8 = 2
+    o2, t2 = np.array([[1.0, 2.0], [0.0, -1.0]]), np.zeros((2, 2))
+    loss, g = ann.phys_loss(o2, t2, np.zeros(2), np.ones(2), None, 0.0, 0.0, out_w=[1.0, 3.0])
+    assert loss == 2.0
+    np.testing.assert_array_equal(g, [[2 * 1 * 1 / 8, 2 * 3 * 2 / 8], [0.0, 2 * 3 * -1 / 8]])
+
+
+def test_weighted_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(4)
+    B, K = 5, 4
+    o, t = rng.normal(size=(B, K)), rng.normal(size=(B, K))
+    w = rng.uniform(0.0, 2.0, K)
+    f = lambda x: ann.phys_loss(x, t, np.zeros(K), np.ones(K), None, 0.0, 0.0, out_w=w)[0]
+    _, g = ann.phys_loss(o, t, np.zeros(K), np.ones(K), None, 0.0, 0.0, out_w=w)
+    h = 1e-6
+    fd = np.zeros_like(o)
+    for i in range(B):
+        for k in range(K):
+            e = np.zeros_like(o)
+            e[i, k] = h
+            fd[i, k] = (f(o + e) - f(o - e)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-10)
+
+
 def test_mass_loss_by_hand_and_zero_when_mass_is_conserved():
     # two species, mu = (1e-3, -1e-3), sd = (1e-3, 2e-3): out = (1, 1) predicts
     # dY = (2e-3, 1e-3), sum 3e-3; |m| / sum(sd) = 3e-3 / 3e-3 = 1
