@@ -122,6 +122,44 @@ def closure_timing(ctx, mech, Tin, P, Yin, T_a, Y_a, dt, log, reps=10):
             "inputs": "transport fits of synth/transport.py; k_sgs ~ 10^U[-1,2] m^2/s^2, delta = 1 mm"}
 
 
+def species_timing(ctx, mech, Tin, P, Yin, log, reps=5, hidden=(1600, 800, 400)):
+    """Forward of the per-species networks at the paper's size (one network
+    per species, hidden 1600-800-400, GELU; random He-uniform weights, seeded)
+    on the block's cells, HIP-event timed over `reps` passes on the stream the
+    kernels run on; algorithmic FLOPs 2 x (multiply-adds of the unpadded
+    layers) per cell and network.  Inference only: the weights play no part in
+    the time."""
+    import torch
+    from paper_2402_18858_amd import chemk, train
+
+    n, K = Yin.shape
+    dims1 = [K + 2, *hidden, 1]
+    ens = chemk.Context(mech)
+    ens.ann_create_species(dims1)
+    ens.ann_set_weights(np.concatenate([train.init_params(dims1, 500 + k) for k in range(K)]))
+    ens.ann_set_norm(*ctx.ann_get_norm())
+    X = torch.empty((n, 64), dtype=torch.int16, device="cuda:0")
+    ens.ann_pack(Tin, P, Yin, None, X, None)
+    out = torch.empty((n, K), dtype=torch.float32, device="cuda:0")
+    ens.ann_forward_packed(X, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ens.ann_forward_packed(X, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    fl = K * train.mlp_flops_per_cell(dims1)
+    tf = fl * n / (ms * 1e-3) / 1e12
+    log(f"per-species networks {K} x {dims1}: {ms:.3f} ms per forward of {n} cells, {tf:.1f} TFLOP/s")
+    del ens
+    return {"networks": K, "dims": dims1, "cells": n, "ms_per_forward": ms, "cells_per_s": n / (ms * 1e-3),
+            "flops_per_cell": fl, "tflops": tf, "peak_tflops": PEAK_BF16_TFLOPS,
+            "frac": tf / PEAK_BF16_TFLOPS,
+            "weights": "random He-uniform, seeded (the forward's time does not depend on them)"}
+
+
 def element_mass(mech, Y):
     comp = mech.composition.astype(np.float64)
     Em = comp * mech.element_mass[None, :] / (comp @ mech.element_mass)[:, None]
@@ -242,6 +280,11 @@ def main():
                     help="network weights to load (train.py --out); default: the workload's stock file")
     ap.add_argument("--di-kernel", type=int, default=0, choices=[0, 1, 2],
                     help="DI factorisation: 0 automatic, 1 LDS LU, 2 register LU")
+    ap.add_argument("--no-species", action="store_true",
+                    help="skip the timing of the per-species networks' forward")
+    ap.add_argument("--species-only", action="store_true",
+                    help="time only the per-species networks' forward on the block and print that "
+                         "(not the headline metric)")
     ap.add_argument("--bins", type=int, default=0, help="fixed stiffness bins (skips the autotuner)")
     ap.add_argument("--wpc", type=int, default=0, help="fixed DI waves per CU (with --bins)")
     args = ap.parse_args()
@@ -297,6 +340,19 @@ def main():
             if mode == "ann":
                 raise
         mode = "ann" if have_ann else "di"
+
+    if args.species_only:
+        if not have_ann or getattr(ctx, "species_nets", False):
+            raise SystemExit("bench.py: --species-only takes its normalisation from a one-network weight file")
+        sp = species_timing(ctx, mech, Tin, P, Yin, log)
+        print(json.dumps({"metric": "per-species network forward", "value": sp["cells_per_s"],
+                          "unit": "cell-forwards/s", "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "bf16", "data": "synthetic",
+                          "config": {"workload": f"{n} cells ({wl['nx']}^3 flame block) x {K} species"},
+                          "roofline": {"bound": "mfma", "achieved": sp["tflops"], "peak": PEAK_BF16_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": sp["frac"], "traffic": None},
+                          "species_networks": sp}))
+        return
 
     # DI tuning on the workload (untimed): bins x waves-per-CU grid on copies
     if args.bins > 0:
@@ -405,7 +461,9 @@ def main():
         cnt = ctx.last_counters()
         ann_cups = n * args.steps / wall_a
         dims = ctx.dims
-        layer_fl = [2 * dims[i] * dims[i + 1] for i in range(len(dims) - 1)]
+        # per-species networks: K networks of these dims run together
+        nets = K if getattr(ctx, "species_nets", False) else 1
+        layer_fl = [2 * nets * dims[i] * dims[i + 1] for i in range(len(dims) - 1)]
         launches = {f"layer{i + 1}": ph_a[f"layer{i + 1}"] for i in range(min(4, len(dims) - 1))}
         per_layer = {}
         for i, (k_, (ms, nl)) in enumerate(launches.items()):
@@ -415,7 +473,7 @@ def main():
             per_layer[k_] = {"launches": nl, "avg_launch_us": 1e3 * avg, "rows_per_launch": rows,
                              "tflops": tf, "frac": tf / PEAK_BF16_TFLOPS}
         mlp_ms = ph_a["mlp"][0] / nsp
-        mlp_tf = train.mlp_flops_per_cell(dims) * n / (mlp_ms * 1e-3) / 1e12
+        mlp_tf = nets * train.mlp_flops_per_cell(dims) * n / (mlp_ms * 1e-3) / 1e12
         phases = {k_: {"ms_per_step": v[0] / nsp, "launches_per_step": v[1] / nsp}
                   for k_, v in ph_a.items() if v[1] > 0}
         # HBM streams of the ingest and post kernels, algorithmic bytes per cell
@@ -436,12 +494,15 @@ def main():
                     "unit": "TFLOP/s", "frac": per_layer[dom]["frac"],
                     "traffic": (measured_traffic("gemm_layer2") if (stock_counters and dom == "layer2")
                                 else None),
-                    "kernel": f"gemm_dma_kernel, MLP {dom} ({dims[int(dom[-1]) - 1]} -> {dims[int(dom[-1])]}, "
-                              f"{per_layer[dom]['rows_per_launch']:.0f} rows per launch)",
+                    "kernel": (f"gemm_dma_kernel, MLP {dom} ({dims[int(dom[-1]) - 1]} -> {dims[int(dom[-1])]}, "
+                               f"{per_layer[dom]['rows_per_launch']:.0f} rows per launch)" if nets == 1 else
+                               f"gemm_bf16_kernel grouped over {nets} per-species networks, {dom} "
+                               f"({dims[int(dom[-1]) - 1]} -> {dims[int(dom[-1])]}, "
+                               f"{per_layer[dom]['rows_per_launch']:.0f} rows per launch)"),
                     "flops_per_launch": layer_fl[int(dom[-1]) - 1] * per_layer[dom]["rows_per_launch"],
                     "mlp_phase": {"ms_per_step": mlp_ms, "tflops": mlp_tf,
                                   "frac": mlp_tf / PEAK_BF16_TFLOPS,
-                                  "flops_per_cell": train.mlp_flops_per_cell(dims)},
+                                  "flops_per_cell": nets * train.mlp_flops_per_cell(dims)},
                     "per_layer": per_layer}
         routed_ns = ns_a[routed_all]
         fb_steps = float(routed_ns.sum()) * nsp
@@ -472,6 +533,8 @@ def main():
         log(f"ANN: {1e3 * wall_a / args.steps:.3f} ms per step, {ann_cups:.4g} cell-updates/s, "
             f"routed {int(routed_all.sum())}")
         result["closure"] = closure_timing(ctx, mech, Tin, P, Yin, T_a, Y_a, dt, log)
+        if not args.no_species and nets == 1:
+            result["species_networks"] = species_timing(ctx, mech, Tin, P, Yin, log)
         if args.envelope_sweep:
             result["ann"]["envelope_sweep"] = envelope_sweep(ctx, mech, dt, Tin, P, Yin, o_ann, region,
                                                              T_di, Y_di, sd_y, di_idx, log)

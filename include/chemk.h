@@ -286,6 +286,20 @@ int chemk_last_counters(chemk_ctx *ctx, int64_t out[3], void *stream);
  * (host, FP32): for each layer l: W_l [dims[l] x dims[l+1]] row-major, then
  * b_l [dims[l+1]].                                                           */
 int chemk_ann_create(chemk_ctx *ctx, const int32_t *dims, int32_t n_layers);
+
+/* One network per species (Sec. II.B: training and prediction are done for
+ * each species' mass fraction separately): K MLPs of the same shape, dims[0] =
+ * K + 2, hidden dims[1..L-1] (n_layers >= 2), dims[L] = 1, network k
+ * predicting the z-scored change of Y_k.  Replaces the context's network like
+ * chemk_ann_create and serves chemk_advance and chemk_ann_forward_packed as a
+ * K-output network would.  Parameter vector: the K networks' vectors (each in
+ * the layout above with dims[L] = 1) one after the other, species order.  The
+ * K networks run as one product for the first layer, one grouped product per
+ * hidden layer and one block-diagonal product for the outputs.  Not
+ * trainable in place (chemk_ann_train*, chemk_ann_reset_optimizer return
+ * CHEMK_E_UNSUPPORTED): train network k as a K-output network with a one-hot
+ * out_w (chemk_ann_train_step) and keep its output row k.                   */
+int chemk_ann_create_species(chemk_ctx *ctx, const int32_t *dims, int32_t n_layers);
 int chemk_ann_param_count(chemk_ctx *ctx, int64_t *count);
 int chemk_ann_set_weights(chemk_ctx *ctx, const float *params, int64_t count);
 int chemk_ann_get_weights(chemk_ctx *ctx, float *params, int64_t count);
@@ -400,7 +414,7 @@ int chemk_ann_hrr_weights(chemk_ctx *ctx, int64_t n, const double *T, const doub
  * plain mean (all w_k = 1 when NULL); a one-hot out_w trains a network on one
  * species alone (the per-species ensemble the paper names as an alternative
  * in Sec. II.B).  Weights must be finite, >= 0 and not all zero, else
- * CHEMK_E_HIP with the message naming them.  loss (device FP32 scalar, may
+ * CHEMK_E_ARG.  loss (device FP32 scalar, may
  * be NULL) receives the batch loss before the update.  grads (device FP32
  * [param_count], may be NULL) receives the gradient in the layout of
  * chemk_ann_get_weights; with update = 0 the weights are left unchanged.      */

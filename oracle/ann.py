@@ -17,6 +17,9 @@ layers use GELU and the parameters are fitted with Adam on the data loss
   the backward pass rounds the output gradient and every pre-activation
   gradient.  Sums are accumulated in float64 here.
 * Adam follows Kingma & Ba (2015), Algorithm 1.
+* The per-species networks (one network per mass fraction) each take the full
+  input and give one output; a one-output network is trained as a K-output
+  network whose data loss weights only its species' column.
 * The physics losses (Eqs. 9-11) act on the z-scored outputs: Eq. 9 as the
   mean absolute deviation of the predicted mass fractions' sum from one,
   divided by the summed spread of dY; Eq. 10 on the heat release over the
@@ -115,6 +118,21 @@ def forward(Ws, bs, X, quantize=True):
         else:
             a = z
     return a, cache
+
+
+def species_forward(nets, X, quantize=True):
+    """Forward of the per-species networks (Sec. II.B: one network per
+    species' mass fraction): nets[k] = (Ws, bs) of a network with one output;
+    column k of the result [n, K] is network k's output."""
+    return np.stack([forward(Ws, bs, X, quantize)[0][:, 0] for Ws, bs in nets], axis=1)
+
+
+def species_split(Ws, bs):
+    """The K one-output networks whose outputs are the columns of the K-output
+    network (Ws, bs): network k keeps every hidden layer and column k of the
+    output layer."""
+    K = Ws[-1].shape[1]
+    return [(list(Ws[:-1]) + [Ws[-1][:, k:k + 1]], list(bs[:-1]) + [bs[-1][k:k + 1]]) for k in range(K)]
 
 
 def mse_loss(out, target):

@@ -91,6 +91,7 @@ _SIGS = {
     "chemk_timing": (C.c_int, [_vp, C.c_int32]),
     "chemk_timing_read": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), _vp]),
     "chemk_ann_create": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_int32]),
+    "chemk_ann_create_species": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_int32]),
     "chemk_ann_param_count": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
     "chemk_ann_set_weights": (C.c_int, [_vp, _vp, _i64]),
     "chemk_ann_get_weights": (C.c_int, [_vp, _vp, _i64]),
@@ -301,6 +302,14 @@ class Context:
         d = (C.c_int32 * len(dims))(*dims)
         _check(lib.chemk_ann_create(self.handle, d, len(dims) - 1))
         self.dims = list(dims)
+        self.species_nets = False
+
+    def ann_create_species(self, dims):
+        """K networks of shape dims (dims[-1] = 1), one per species."""
+        d = (C.c_int32 * len(dims))(*dims)
+        _check(lib.chemk_ann_create_species(self.handle, d, len(dims) - 1))
+        self.dims = list(dims)
+        self.species_nets = True
 
     def ann_param_count(self):
         c = C.c_int64()

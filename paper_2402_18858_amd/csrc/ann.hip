@@ -879,7 +879,7 @@ __global__ void cast_layer_kernel(const float *__restrict__ Wm, int in, int out,
     if (i >= in * out) return;
     const int r = i / out, c = i - r * out;
     const uint16_t v = f2bf(Wm[i]);
-    Wb[i] = v;
+    if (Wb) Wb[i] = v;
     Wt[(size_t)c * in + r] = v;
 }
 
@@ -1126,6 +1126,12 @@ __global__ void reset_step_kernel(int *n_routed, int *counter, unsigned long lon
 // ---------------------------------------------------------------------------
 struct AnnState {
     int K = 0, F = 0, L = 0;
+    // G = 1: one network with K outputs.  G = K: one network per species
+    // (dims[L] = 1), run together for inference only; master then holds G
+    // copies of the one-network layout, gstride floats apart.
+    int G = 1;
+    size_t gstride = 0;
+    std::vector<float *> eB;          // ensemble biases per layer [G pd[l+1]]
     std::vector<int> dims;       // logical, dims[0] = K + 2
     std::vector<int> pd;         // internal: pd[0] = FPAD
     std::vector<size_t> woff, boff;   // offsets (floats) of W_l, b_l in the master vector
@@ -1183,6 +1189,7 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->m2);
     for (auto p : a->Wt) (void)hipFree(p);
     for (auto p : a->Wb) (void)hipFree(p);
+    for (auto p : a->eB) (void)hipFree(p);
     (void)hipFree(a->normdev);
     (void)hipFree(a->rowtab);
     (void)hipFree(a->X);
@@ -1207,7 +1214,26 @@ void ann_destroy(AnnState *a) {
 bool ann_ready(const AnnState *a) { return a && a->have_w && a->have_norm; }
 double ann_dt(const AnnState *a) { return a ? a->dt : 0.0; }
 
+// BF16 product operands and gathered biases of the G networks of an ensemble
+static hipError_t refresh_ensemble(AnnState *a, hipStream_t s) {
+    const int G = a->G, L = a->L;
+    for (int l = 0; l < L; ++l) {
+        const int in = a->pd[l], out = a->pd[l + 1];
+        for (int g = 0; g < G; ++g) {
+            uint16_t *dst = l < L - 1 ? a->Wt[l] + (size_t)g * out * in
+                                      : a->Wt[l] + (size_t)g * G * in + (size_t)g * in;
+            hipLaunchKernelGGL(cast_layer_kernel, dim3((in * out + 255) / 256), dim3(256), 0, s,
+                               a->master + g * a->gstride + a->woff[l], in, out, dst, (uint16_t *)nullptr);
+        }
+        hipError_t e = hipMemcpy2DAsync(a->eB[l], 4 * (size_t)out, a->master + a->boff[l], 4 * a->gstride,
+                                        4 * (size_t)out, G, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
 static hipError_t refresh_bf16(AnnState *a, hipStream_t s) {
+    if (a->G > 1) return refresh_ensemble(a, s);
     for (int l = 0; l < a->L; ++l) {
         const int in = a->pd[l], out = a->pd[l + 1];
         hipLaunchKernelGGL(cast_layer_kernel, dim3((in * out + 255) / 256), dim3(256), 0, s,
@@ -1275,10 +1301,95 @@ static hipError_t row_tables(AnnState *a, const DevMech &m, hipStream_t s, const
     return hipSuccess;
 }
 
+// Forward of the G = K per-species networks on `rows` packed inputs: the
+// first layers of all networks read the same input, so they are one product
+// [rows x FPAD] x [FPAD x G pd1]; hidden layer l is a grouped product, network
+// g multiplying its column slab g of the previous activations [rows x G pd[l]]
+// by its own weights; the output layer is one product with a block-diagonal
+// [G pd[L-1] x G] matrix (network g's output weights in block g), so that out
+// [rows x K] holds network k's prediction in column k.  (The zeros of the
+// block-diagonal matrix are exact in the FP32 sums; that layer is about 1 % of
+// the work.)  Activations of network g sit in columns [g pd[l], (g+1) pd[l]).
+static hipError_t ens_forward(AnnState *a, const uint16_t *X, int rows, float *out, uint16_t *buf0,
+                              uint16_t *buf1, hipStream_t s, PhaseTimer *tm) {
+    const int G = a->G, L = a->L;
+    const uint16_t *in = X;
+    uint16_t *bufs[2] = {buf0, buf1};
+    for (int l = 0; l < L; ++l) {
+        GemmArgs g{};
+        g.M = rows;
+        g.B = a->Wt[l];
+        g.bias = a->eB[l];
+        const bool last = l == L - 1;
+        const int ph = CHEMK_PHASE_LAYER1 + (l < 3 ? l : 3);
+        int groups = 1, epi = EPI_BIAS_GELU;
+        uint16_t *dst = bufs[l & 1];
+        if (l == 0) {
+            g.N = G * a->pd[1];
+            g.K = FPAD;
+            g.A = in;
+            g.lda = FPAD;
+            g.ldb = FPAD;
+        } else if (!last) {
+            g.N = a->pd[l + 1];
+            g.K = a->pd[l];
+            g.A = in;
+            g.lda = G * a->pd[l];
+            g.ldb = a->pd[l];
+            g.gsA = a->pd[l];
+            g.gsB = (long long)a->pd[l] * a->pd[l + 1];
+            g.gsC = a->pd[l + 1];
+            groups = G;
+        } else {
+            g.N = G;
+            g.K = G * a->pd[l];
+            g.A = in;
+            g.lda = G * a->pd[l];
+            g.ldb = G * a->pd[l];
+            epi = EPI_BIAS;
+        }
+        if (last) {
+            g.Cf = out;
+            g.ldc = G;
+        } else {
+            g.Cb = dst;
+            g.ldcb = G * a->pd[l + 1];
+        }
+        if (tm) tm->begin(ph, s);
+        const hipError_t e = launch_gemm(g, true, true, epi, s, groups);
+        if (tm) tm->end(ph, s);
+        if (e != hipSuccess) return e;
+        in = dst;
+    }
+    return hipSuccess;
+}
+
+#ifndef ENS_CHUNK_MB
+#define ENS_CHUNK_MB 3072
+#endif
+// rows per forward chunk: CHUNK for one network; for an ensemble as many as
+// keep the activations of a chunk near ENS_CHUNK_MB MB and the operands' byte
+// offsets 31-bit (17,408 rows for the paper's 32 networks of 1600-800-400:
+// measured, 192 MB chunks that stay in the memory-side cache ran the forward
+// 1.8 times slower, and 48 MB chunks 4.4 times)
+static int chunk_rows(const AnnState *a) {
+    if (a->G == 1) return CHUNK;
+    size_t per = 0, wmax = 0;
+    for (int l = 1; l < a->L; ++l) {
+        per += 2 * (size_t)a->G * a->pd[l];
+        wmax = std::max(wmax, (size_t)a->G * a->pd[l]);
+    }
+    size_t r = ((size_t)ENS_CHUNK_MB << 20) / per;
+    r = std::min(r, (size_t)0x7fffffff / (2 * wmax));
+    r = std::max<size_t>(256, r / 256 * 256);
+    return (int)std::min<size_t>(r, CHUNK);
+}
+
 // forward of `rows` packed inputs X [rows x FPAD] into out [rows x K] (FP32)
 static hipError_t mlp_forward(AnnState *a, const uint16_t *X, int rows, float *out, uint16_t *buf0,
                               uint16_t *buf1, hipStream_t s, float **Zsave = nullptr,
                               uint16_t **Asave = nullptr, PhaseTimer *tm = nullptr) {
+    if (a->G > 1) return ens_forward(a, X, rows, out, buf0, buf1, s, tm);
     const uint16_t *in = X;
     uint16_t *bufs[2] = {buf0, buf1};
     for (int l = 0; l < a->L; ++l) {
@@ -1323,9 +1434,9 @@ static hipError_t ensure_infer(AnnState *a, int64_t n) {
     (void)hipFree(a->act[0]);
     (void)hipFree(a->act[1]);
     a->cap = 0;
-    int wmax = 0;
-    for (int l = 1; l < a->L; ++l) wmax = std::max(wmax, a->pd[l]);
-    const int64_t ch = std::min<int64_t>(n, CHUNK);
+    int64_t wmax = 0;
+    for (int l = 1; l < a->L; ++l) wmax = std::max<int64_t>(wmax, (int64_t)a->G * a->pd[l]);
+    const int64_t ch = std::min<int64_t>(n, chunk_rows(a));
     hipError_t e;
     if ((e = hipMalloc(&a->X, sizeof(uint16_t) * n * FPAD)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->route, sizeof(int) * n)) != hipSuccess) return e;
@@ -1403,8 +1514,9 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
     if (tm) tm->end(CHEMK_PHASE_INGEST, s);
     // MLP in chunks
     if (tm) tm->begin(CHEMK_PHASE_MLP, s);
-    for (int64_t c0 = 0; c0 < n; c0 += CHUNK) {
-        const int rows = (int)std::min<int64_t>(CHUNK, n - c0);
+    const int chunk = chunk_rows(a);
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int rows = (int)std::min<int64_t>(chunk, n - c0);
         if ((e = mlp_forward(a, a->X + c0 * FPAD, rows, a->out + c0 * a->K, a->act[0], a->act[1], s,
                              nullptr, nullptr, tm)) != hipSuccess)
             return e;
@@ -1466,13 +1578,53 @@ static int need_ann(chemk_ctx *c, AnnState **out) {
     return CHEMK_OK;
 }
 
+// Sum of the per-output weights of the data term (device [K]): read once,
+// checked finite, >= 0 and not all zero.
+static int out_weight_sum(chemk_ctx *c, const AnnState *a, const float *w, float *sum) {
+    (void)c;
+    std::vector<float> h(a->K);
+    ANN_TRY(hipMemcpy(h.data(), w, 4 * (size_t)a->K, hipMemcpyDeviceToHost));
+    double s = 0.0;
+    for (int k = 0; k < a->K; ++k) {
+        if (!(h[k] >= 0.f) || !std::isfinite(h[k])) ANN_FAIL(CHEMK_E_ARG, "out_w[%d] = %g is not finite and >= 0", k, h[k]);
+        s += h[k];
+    }
+    if (!(s > 0.0)) ANN_FAIL(CHEMK_E_ARG, "out_w is all zero");
+    *sum = (float)s;
+    return CHEMK_OK;
+}
+
+// Training runs on single networks only.
+static int need_single(AnnState *a) {
+    if (a->G > 1)
+        ANN_FAIL(CHEMK_E_UNSUPPORTED, "per-species networks are not trained in place: train each as a "
+                                      "K-output network with a one-hot out_w and install them together");
+    return CHEMK_OK;
+}
+
+static int create_net(chemk_ctx *c, const int32_t *dims, int32_t L, int G);
+
 extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
     ctx_set_error("");
     if (!c || !dims) ANN_FAIL(CHEMK_E_ARG, "null argument");
-    const int K = ctx_K(c);
     if (L < 1 || L > 16) ANN_FAIL(CHEMK_E_ARG, "n_layers=%d outside [1, 16]", L);
-    if (dims[0] != K + 2) ANN_FAIL(CHEMK_E_ARG, "dims[0]=%d must be K+2=%d", dims[0], K + 2);
+    const int K = ctx_K(c);
     if (dims[L] != K) ANN_FAIL(CHEMK_E_ARG, "dims[L]=%d must be K=%d", dims[L], K);
+    return create_net(c, dims, L, 1);
+}
+
+extern "C" int chemk_ann_create_species(chemk_ctx *c, const int32_t *dims, int32_t L) {
+    ctx_set_error("");
+    if (!c || !dims) ANN_FAIL(CHEMK_E_ARG, "null argument");
+    if (L < 2 || L > 16) ANN_FAIL(CHEMK_E_ARG, "n_layers=%d outside [2, 16] (one hidden layer at least)", L);
+    if (dims[L] != 1) ANN_FAIL(CHEMK_E_ARG, "dims[L]=%d must be 1 (one output per species network)", dims[L]);
+    return create_net(c, dims, L, ctx_K(c));
+}
+
+static int create_net(chemk_ctx *c, const int32_t *dims, int32_t L, int G) {
+    ctx_set_error("");
+    const int K = ctx_K(c);
+    if (dims[0] != K + 2) ANN_FAIL(CHEMK_E_ARG, "dims[0]=%d must be K+2=%d", dims[0], K + 2);
     if (K + 2 > FPAD) ANN_FAIL(CHEMK_E_UNSUPPORTED, "K+2 > %d inputs", FPAD);
     for (int l = 1; l < L; ++l)
         if (dims[l] < 8 || dims[l] > 8192)
@@ -1484,6 +1636,7 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
     a->K = K;
     a->F = K + 2;
     a->L = L;
+    a->G = G;
     a->dims.assign(dims, dims + L + 1);
     // padded widths: the input to the GEMMs' K step, hidden layers to whole
     // 64-column slabs (the padding units have zero weights and biases, so
@@ -1499,23 +1652,41 @@ extern "C" int chemk_ann_create(chemk_ctx *c, const int32_t *dims, int32_t L) {
         off += a->pd[l + 1];
         pub += (size_t)a->dims[l] * a->dims[l + 1] + a->dims[l + 1];
     }
-    a->nparam = off;
-    a->npublic = pub;
+    // G networks: master holds G copies of the one-network layout
+    a->gstride = off;
+    a->nparam = off * G;
+    a->npublic = pub * G;
     ctx_ann(c) = a;
-    ANN_TRY(hipMalloc(&a->master, 4 * off));
-    ANN_TRY(hipMalloc(&a->grad, 4 * off));
-    ANN_TRY(hipMalloc(&a->m1, 4 * off));
-    ANN_TRY(hipMalloc(&a->m2, 4 * off));
-    ANN_TRY(hipMemset(a->master, 0, 4 * off));
-    ANN_TRY(hipMemset(a->grad, 0, 4 * off));
-    ANN_TRY(hipMemset(a->m1, 0, 4 * off));
-    ANN_TRY(hipMemset(a->m2, 0, 4 * off));
-    for (int l = 0; l < L; ++l) {
-        uint16_t *wt = nullptr, *wb = nullptr;
-        ANN_TRY(hipMalloc(&wt, 2 * (size_t)a->pd[l] * a->pd[l + 1]));
-        ANN_TRY(hipMalloc(&wb, 2 * (size_t)a->pd[l] * a->pd[l + 1]));
-        a->Wt.push_back(wt);
-        a->Wb.push_back(wb);
+    ANN_TRY(hipMalloc(&a->master, 4 * a->nparam));
+    ANN_TRY(hipMemset(a->master, 0, 4 * a->nparam));
+    if (G == 1) {
+        ANN_TRY(hipMalloc(&a->grad, 4 * off));
+        ANN_TRY(hipMalloc(&a->m1, 4 * off));
+        ANN_TRY(hipMalloc(&a->m2, 4 * off));
+        ANN_TRY(hipMemset(a->grad, 0, 4 * off));
+        ANN_TRY(hipMemset(a->m1, 0, 4 * off));
+        ANN_TRY(hipMemset(a->m2, 0, 4 * off));
+        for (int l = 0; l < L; ++l) {
+            uint16_t *wt = nullptr, *wb = nullptr;
+            ANN_TRY(hipMalloc(&wt, 2 * (size_t)a->pd[l] * a->pd[l + 1]));
+            ANN_TRY(hipMalloc(&wb, 2 * (size_t)a->pd[l] * a->pd[l + 1]));
+            a->Wt.push_back(wt);
+            a->Wb.push_back(wb);
+        }
+    } else {
+        // product operands of the ensemble (see ens_forward): layer 0 one
+        // [G pd1 x FPAD] matrix, hidden layers G blocks [pd[l+1] x pd[l]],
+        // the output layer block diagonal [G x G pd[L-1]]; biases [G pd[l+1]]
+        for (int l = 0; l < L; ++l) {
+            const size_t n = l < L - 1 ? (size_t)G * a->pd[l + 1] * a->pd[l] : (size_t)G * G * a->pd[l];
+            uint16_t *wt = nullptr;
+            float *b = nullptr;
+            ANN_TRY(hipMalloc(&wt, 2 * n));
+            ANN_TRY(hipMemset(wt, 0, 2 * n));
+            ANN_TRY(hipMalloc(&b, 4 * (size_t)G * a->pd[l + 1]));
+            a->Wt.push_back(wt);
+            a->eB.push_back(b);
+        }
     }
     ANN_TRY(hipMalloc(&a->normdev, 8 * normdev_doubles(a)));
     ANN_TRY(hipMalloc(&a->rowtab, 8 * ROW_TAB_DOUBLES));
@@ -1543,26 +1714,35 @@ extern "C" int chemk_ann_param_count(chemk_ctx *c, int64_t *count) {
 // public layout <-> internal (layer 0 rows padded from K+2 to FPAD inputs)
 // Public layout: per layer W [dims[l] x dims[l+1]] row-major, then b; the
 // internal one pads rows to pd[l] and columns to pd[l+1] with zeros.
+// With G networks both layouts hold G such vectors one after the other.
 static void pub_to_int(const AnnState *a, const float *pub, std::vector<float> &in) {
     in.assign(a->nparam, 0.f);
     size_t p = 0;
-    for (int l = 0; l < a->L; ++l) {
-        const int r = a->dims[l], cl = a->dims[l + 1], ld = a->pd[l + 1];
-        for (int i = 0; i < r; ++i) std::memcpy(in.data() + a->woff[l] + (size_t)i * ld, pub + p + (size_t)i * cl, 4 * cl);
-        p += (size_t)r * cl;
-        std::memcpy(in.data() + a->boff[l], pub + p, 4 * cl);
-        p += cl;
+    for (int g = 0; g < a->G; ++g) {
+        float *base = in.data() + g * a->gstride;
+        for (int l = 0; l < a->L; ++l) {
+            const int r = a->dims[l], cl = a->dims[l + 1], ld = a->pd[l + 1];
+            for (int i = 0; i < r; ++i)
+                std::memcpy(base + a->woff[l] + (size_t)i * ld, pub + p + (size_t)i * cl, 4 * cl);
+            p += (size_t)r * cl;
+            std::memcpy(base + a->boff[l], pub + p, 4 * cl);
+            p += cl;
+        }
     }
 }
 
 static void int_to_pub(const AnnState *a, const float *in, float *pub) {
     size_t p = 0;
-    for (int l = 0; l < a->L; ++l) {
-        const int r = a->dims[l], cl = a->dims[l + 1], ld = a->pd[l + 1];
-        for (int i = 0; i < r; ++i) std::memcpy(pub + p + (size_t)i * cl, in + a->woff[l] + (size_t)i * ld, 4 * cl);
-        p += (size_t)r * cl;
-        std::memcpy(pub + p, in + a->boff[l], 4 * cl);
-        p += cl;
+    for (int g = 0; g < a->G; ++g) {
+        const float *base = in + g * a->gstride;
+        for (int l = 0; l < a->L; ++l) {
+            const int r = a->dims[l], cl = a->dims[l + 1], ld = a->pd[l + 1];
+            for (int i = 0; i < r; ++i)
+                std::memcpy(pub + p + (size_t)i * cl, base + a->woff[l] + (size_t)i * ld, 4 * cl);
+            p += (size_t)r * cl;
+            std::memcpy(pub + p, base + a->boff[l], 4 * cl);
+            p += cl;
+        }
     }
 }
 
@@ -1892,10 +2072,11 @@ extern "C" int chemk_ann_forward_packed(chemk_ctx *c, int64_t n, const uint16_t 
     if (n < 0 || n > (1ll << 31) - 1) ANN_FAIL(CHEMK_E_ARG, "bad n");
     if (n == 0) return CHEMK_OK;
     if (!X || !out) ANN_FAIL(CHEMK_E_ARG, "null array");
-    ANN_TRY(ensure_infer(a, std::min<int64_t>(n, CHUNK)));
+    const int chunk = chunk_rows(a);
+    ANN_TRY(ensure_infer(a, std::min<int64_t>(n, chunk)));
     hipStream_t s = (hipStream_t)stream;
-    for (int64_t c0 = 0; c0 < n; c0 += CHUNK) {
-        const int rows = (int)std::min<int64_t>(CHUNK, n - c0);
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int rows = (int)std::min<int64_t>(chunk, n - c0);
         ANN_TRY(mlp_forward(a, X + c0 * FPAD, rows, out + c0 * a->K, a->act[0], a->act[1], s));
     }
     return CHEMK_OK;
@@ -1960,21 +2141,6 @@ static hipError_t ensure_train(AnnState *a, int B) {
 
 // One training step's forward (saving Z and A), loss and backward on rows
 // idx[0..B-1] of (X, Z): the gradient lands in a->grad, the batch loss in sink.
-// Sum of the per-output weights of the data term (device [K]): read once,
-// checked finite, >= 0 and not all zero.
-static hipError_t out_weight_sum(const AnnState *a, const float *w, float *sum) {
-    std::vector<float> h(a->K);
-    hipError_t e = hipMemcpy(h.data(), w, 4 * (size_t)a->K, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return e;
-    double s = 0.0;
-    for (float v : h) {
-        if (!(v >= 0.f) || !std::isfinite(v)) return hipErrorInvalidValue;
-        s += v;
-    }
-    if (!(s > 0.0)) return hipErrorInvalidValue;
-    *sum = (float)s;
-    return hipSuccess;
-}
 
 // Loss weights of the physics terms (Eq. 11's W2, W3) and the heat-release
 // weights G of the training rows (NULL when w_hrr = 0).
@@ -2054,6 +2220,7 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
+    if (int r = need_single(a)) return r;
     if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
     if (!idx || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null array");
     if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
@@ -2066,7 +2233,8 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
     const int L = a->L;
     hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, s, a->tLoss, 1);
     float wsum = 0.f;
-    if (out_w) ANN_TRY(out_weight_sum(a, out_w, &wsum));
+    if (out_w)
+        if (int r = out_weight_sum(c, a, out_w, &wsum)) return r;
     ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s,
                     PhysLoss{G, w_mass, w_hrr, out_w, wsum}));
     if (loss) ANN_TRY(hipMemcpyAsync(loss, a->tLoss, 4, hipMemcpyDeviceToDevice, s));
@@ -2118,6 +2286,7 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
+    if (int r = need_single(a)) return r;
     if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
     if (!o || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null argument");
     const int B = o->batch;
@@ -2132,7 +2301,8 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
         ANN_FAIL(CHEMK_E_ARG, "loss weights must be finite and >= 0");
     if (o->w_hrr > 0 && !o->G) ANN_FAIL(CHEMK_E_ARG, "w_hrr > 0 needs the heat-release weights G");
     float owsum = 0.f;
-    if (o->out_w) ANN_TRY(out_weight_sum(a, o->out_w, &owsum));
+    if (o->out_w)
+        if (int r = out_weight_sum(c, a, o->out_w, &owsum)) return r;
     if (reinterpret_cast<uintptr_t>(X) % 16 || (X_hold && reinterpret_cast<uintptr_t>(X_hold) % 16))
         ANN_FAIL(CHEMK_E_ARG, "X must be 16-byte aligned");
     hipStream_t s0 = (hipStream_t)stream;
@@ -2259,6 +2429,7 @@ extern "C" int chemk_ann_reset_optimizer(chemk_ctx *c) {
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
+    if (int r = need_single(a)) return r;
     ANN_TRY(hipMemset(a->m1, 0, 4 * a->nparam));
     ANN_TRY(hipMemset(a->m2, 0, 4 * a->nparam));
     a->step = 0;

@@ -29,12 +29,19 @@ struct GemmArgs {
     // K rows [z K, (z + 1) K) of both operands and writes its partial product
     // to Cf + z * split_stride
     long long split_stride;
+    // groups over gridDim.z > 1 (launch_gemm with groups > 1): group z offsets
+    // A by z gsA, B by z gsB, and bias, Cf, Cb and Zin by z gsC elements
+    long long gsA, gsB, gsC;
 };
 
 // Any K >= 1 and leading dimensions; operands in whole, 16-byte aligned
 // chunks of 8 (K, lda, ldb and the chunked extents multiples of 8) take the
 // buffer-load path, others an element-by-element one.  Operands below 2 GiB.
-hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s);
+// groups > 1 runs that many independent products of the same shape in one
+// launch (the per-species layers of an ensemble), group z at the offsets
+// gsA, gsB, gsC of GemmArgs; every group's operands must lie within its own
+// buffer extents as for a single product.
+hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s, int groups = 1);
 
 // C = A^T B with both operands K-major rows (A [K x M], B [K x N], the
 // weight-gradient product of training), FP32 result, K split into `split`

@@ -11,10 +11,11 @@
 // Tiling: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves, each
 // 64 x 64 in MFMA tiles of 32 x 32), K step 64 (four MFMA k-steps).  Two
 // kernels:
-//  * forward layers whose slab count is one the MLP has (1, 4, 8, 16): the
-//    slabs go from global memory straight into LDS (buffer loads with an LDS
-//    destination), into unpadded rows with a swizzled chunk order.  1, 8 and
-//    16 slabs use a single LDS stage shared with the output staging (37 KB,
+//  * forward layers whose slab count is one the networks have (1, 4, 8, 16;
+//    13 and 25 for the per-species networks): the slabs go from global
+//    memory straight into LDS (buffer loads with an LDS destination), into
+//    unpadded rows with a swizzled chunk order.  1, 8, 13, 16 and 25 slabs
+//    use a single LDS stage shared with the output staging (37 KB,
 //    four workgroups per CU, which hide each other's slab loads); 4 slabs
 //    (the last layer) use two stages and prefetch;
 //  * everything else (training products, transposing loads, other K): two
@@ -56,6 +57,22 @@ constexpr int NTHREADS = 256;
 
 // bf16 elements per LDS row for a K step of BK (16-byte pad)
 template <int BK> constexpr int lds_ld() { return BK + 8; }
+
+// the group's operands of a grouped launch (gridDim.z > 1): the per-species
+// networks' hidden layers, network z multiplying its own column slab of the
+// activations by its own weights
+__device__ __forceinline__ void group_offsets(GemmArgs &g) {
+    if (gridDim.z > 1) {
+        const long long z = blockIdx.z;
+        g.A += z * g.gsA;
+        g.B += z * g.gsB;
+        const long long c = z * g.gsC;
+        if (g.bias) g.bias += c;
+        if (g.Cf) g.Cf += c;
+        if (g.Cb) g.Cb += c;
+        if (g.Zin) g.Zin += c;
+    }
+}
 
 typedef __attribute__((ext_vector_type(2))) float floatx2_t;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
@@ -356,6 +373,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16_t (&a
 template <int BM, int BN, int BK, bool AK, bool BKc, int EPI, bool VEC>
 __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_kernel(GemmArgs g) {
     constexpr int PD = 2;   // K slabs in flight in registers ahead of the one multiplied
+    group_offsets(g);
     if (gridDim.y > 1) {   // split K: this slice's rows of both operands, its own partial C
         const long long z = blockIdx.y;
         g.A += z * g.K * (AK ? 1 : g.lda);
@@ -506,6 +524,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
     constexpr int S1 = SA + SB > 4 * STG ? SA + SB : 4 * STG;
     __shared__ __attribute__((aligned(16))) uint16_t sA0[ONE ? S1 : SA], sB0[ONE ? 8 : SB],
         sA1[ONE ? 8 : SA], sB1[ONE ? 8 : SB];
+    group_offsets(g);
 
     const int mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
     const int tiles = mt * nt;
@@ -608,10 +627,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
 }
 
 template <bool AKV, bool BKV, int EP>
-static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
+static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s, int groups) {
     constexpr int TB = 128, TK = 64;
     const int tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);
-    const int grid = ((tiles + 7) / 8) * 8;
+    const dim3 grid(((tiles + 7) / 8) * 8, 1, groups);
     const int kt = (g.K + TK - 1) / TK;
     // forward layers of the MLP get a K loop unrolled for their slab count
     constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS);
@@ -622,12 +641,16 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s) {
         GEMM_LAUNCH(false);
     } else if constexpr (fwd) {
         // forward layers with a slab count the MLP has: slabs loaded straight into LDS
-        // stages as measured fastest: one (four workgroups per CU) for 1, 8
-        // and 16 slabs; two for 4 slabs (the last layer, N = 32)
+        // stages as measured fastest: one (four workgroups per CU) for 1, 8,
+        // 13, 16 and 25 slabs; two for 4 slabs (the last layer, N = 32)
         if (kt == 1) hipLaunchKernelGGL((gemm_dma_kernel<EP, 1, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
         else if (kt == 16) hipLaunchKernelGGL((gemm_dma_kernel<EP, 16, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
         else if (kt == 8) hipLaunchKernelGGL((gemm_dma_kernel<EP, 8, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
         else if (kt == 4) hipLaunchKernelGGL((gemm_dma_kernel<EP, 4, 2>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        // the hidden layers of the per-species networks (1600 -> 800 -> 400,
+        // K = 1600 and 832): 1.24 and 1.34 times faster than the register ring
+        else if (kt == 25) hipLaunchKernelGGL((gemm_dma_kernel<EP, 25, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 13) hipLaunchKernelGGL((gemm_dma_kernel<EP, 13, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
         else GEMM_LAUNCH(true);
     } else {
         GEMM_LAUNCH(true);
@@ -671,9 +694,11 @@ hipError_t launch_gemm_splitk(const GemmArgs &g0, int split, float *work, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s) {
-    if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    if (g.K <= 0) return hipErrorInvalidValue;
+hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, hipStream_t s, int groups) {
+    if (g.M <= 0 || g.N <= 0 || groups == 0) return hipSuccess;
+    if (g.K <= 0 || groups < 0 || groups > 65535) return hipErrorInvalidValue;
+    // grouped operands must keep the alignment of the first group
+    if (groups > 1 && (g.gsA % 8 != 0 || g.gsB % 8 != 0 || g.gsC % 8 != 0)) return hipErrorInvalidValue;
     // byte offsets of the buffer loads are 31-bit
     const int64_t bytesA = 2ll * g.lda * (a_kcont ? g.M : g.K);
     const int64_t bytesB = 2ll * g.ldb * (b_kcont ? g.N : g.K);
@@ -684,15 +709,15 @@ hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, h
                      (b_kcont ? g.K : g.N) % 8 == 0;
     if (a_kcont && b_kcont) {
         switch (epi) {
-            case EPI_BIAS_GELU: return launch_case<true, true, EPI_BIAS_GELU>(g, vec, s);
-            case EPI_BIAS: return launch_case<true, true, EPI_BIAS>(g, vec, s);
-            case EPI_GELU_GRAD: return launch_case<true, true, EPI_GELU_GRAD>(g, vec, s);
-            case EPI_STORE_F32: return launch_case<true, true, EPI_STORE_F32>(g, vec, s);
+            case EPI_BIAS_GELU: return launch_case<true, true, EPI_BIAS_GELU>(g, vec, s, groups);
+            case EPI_BIAS: return launch_case<true, true, EPI_BIAS>(g, vec, s, groups);
+            case EPI_GELU_GRAD: return launch_case<true, true, EPI_GELU_GRAD>(g, vec, s, groups);
+            case EPI_STORE_F32: return launch_case<true, true, EPI_STORE_F32>(g, vec, s, groups);
             default: return hipErrorInvalidValue;
         }
     }
     if (!a_kcont && !b_kcont && epi == EPI_STORE_F32)
-        return launch_case<false, false, EPI_STORE_F32>(g, vec, s);
+        return launch_case<false, false, EPI_STORE_F32>(g, vec, s, groups);
     return hipErrorInvalidValue;
 }
 

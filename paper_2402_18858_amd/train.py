@@ -47,6 +47,26 @@ def init_params(dims, seed):
     return np.concatenate(parts)
 
 
+def species_slice(params, dims, k):
+    """Public parameter vector of the one-output network of species k cut
+    from a K-output network's (dims[-1] = K): every hidden layer unchanged,
+    column k of the output layer's weights and its bias k."""
+    off = 0
+    parts = []
+    L = len(dims) - 1
+    for i in range(L):
+        nw = dims[i] * dims[i + 1]
+        W = params[off:off + nw]
+        b = params[off + nw:off + nw + dims[i + 1]]
+        off += nw + dims[i + 1]
+        if i < L - 1:
+            parts += [W, b]
+        else:
+            parts += [W.reshape(dims[i], dims[i + 1])[:, k].copy(), b[k:k + 1].copy()]
+    assert off == params.size
+    return np.concatenate(parts).astype(np.float32)
+
+
 def _advance(ctx, T, P, Y, dt, st, max_steps=100000):
     from . import chemk
     ctx.advance(T, P, Y, dt, st, None, opts=chemk.default_opts(max_steps=max_steps))
@@ -326,6 +346,60 @@ def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed
     return hist
 
 
+def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, batch=4096, lr0=1e-3,
+                           lr1=1e-5, seed=3001, log=print):
+    """The per-species networks of Sec. II.B: one network per mass fraction,
+    hidden widths `hidden` with GELU.  Takes the normalisation, envelope and
+    checks already fitted on ctx (train_network) and the same training split
+    (data[-1] = the held-out indices); network k is trained as a K-output
+    network whose data loss weights column k alone (a one-hot out_w), so its
+    gradient flows from output k only, and keeps its hidden layers and output
+    row k.  Every network starts from its own He-uniform draw and sees the
+    same per-epoch row orders.  Installs the K networks in ctx
+    (chemk_ann_create_species) and returns a history dict."""
+    import torch
+
+    dev = "cuda:0"
+    T, p, Y, Yn, hold = data
+    K = Y.shape[1]
+    tr = np.setdiff1d(np.arange(T.size), hold)
+    norm = ctx.ann_get_norm()
+    env = ctx.ann_get_envelope()
+    ck = ctx.ann_get_checks()
+    dims = [K + 2, *hidden, K]
+    ctx.ann_create(dims)
+    ctx.ann_set_norm(*norm)
+    Td = [torch.from_numpy(np.ascontiguousarray(v[tr])).to(dev) for v in (T, p, Y, Yn)]
+    ntr = tr.size
+    X = torch.empty((ntr, 64), dtype=torch.int16, device=dev)
+    Z = torch.empty((ntr, K), dtype=torch.float32, device=dev)
+    ctx.ann_pack(*Td, X, Z)
+    del Td
+    hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "hidden": list(hidden), "loss_last": []}
+    nets = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(K):
+        ctx.ann_create(dims)
+        ctx.ann_set_norm(*norm)
+        ctx.ann_set_weights(init_params(dims, seed + 7919 * (k + 1)))
+        ctx.ann_reset_optimizer()
+        w = torch.zeros(K, dtype=torch.float32, device=dev)
+        w[k] = 1.0
+        el, _ = ctx.ann_train(X, Z, epochs, batch=batch, lr0=lr0, lr1=lr1, seed=seed, out_w=w)
+        nets.append(species_slice(ctx.ann_get_weights(), dims, k))
+        hist["loss_last"].append(float(el[-1]))
+        log(f"species {k + 1}/{K}: loss {el[0]:.3e} -> {el[-1]:.3e} ({time.time() - t0:.0f} s)")
+    hist["train_s"] = time.time() - t0
+    hist["steps"] = (ntr // batch) * epochs * K
+    ctx.ann_create_species([K + 2, *hidden, 1])
+    ctx.ann_set_weights(np.concatenate(nets))
+    ctx.ann_set_norm(*norm)
+    ctx.ann_set_envelope(*env)
+    ctx.ann_set_checks(adj_max=ck["adj_max"], dT=ck["dT"], ratios=ck["ratios"])
+    return hist
+
+
 def evaluate(ctx, T, p, Y, Yn_ref, hrr_scale=None):
     """Per-species RMS and max of the normalised dY error of the network
     (no projection, no fallback) against reference dY, plus the frozen-
@@ -384,7 +458,8 @@ def save(ctx, path=WEIGHTS, extra=None):
     ck = ctx.ann_get_checks()
     E = ctx.mech.E
     rat = ck["ratios"]
-    np.savez(path, params=ctx.ann_get_weights(), dims=np.array(ctx.dims), mu_x=mx, sd_x=sx,
+    np.savez(path, params=ctx.ann_get_weights(), dims=np.array(ctx.dims),
+             species=np.array(int(getattr(ctx, "species_nets", False))), mu_x=mx, sd_x=sx,
              mu_y=my, sd_y=sy, dt=dt, env_lo=lo, env_hi=hi, neg_tol=neg_tol,
              ck_adj_max=ck["adj_max"], ck_dT=np.array(ck["dT"]),
              ck_num=np.array([r[0] for r in rat]).reshape(len(rat), E),
@@ -395,7 +470,11 @@ def save(ctx, path=WEIGHTS, extra=None):
 
 def load(ctx, path=WEIGHTS, neg_tol=None):
     d = np.load(path, allow_pickle=False)
-    ctx.ann_create([int(v) for v in d["dims"]])
+    dims = [int(v) for v in d["dims"]]
+    if "species" in d.files and int(d["species"]):
+        ctx.ann_create_species(dims)
+    else:
+        ctx.ann_create(dims)
     ctx.ann_set_weights(d["params"])
     ctx.ann_set_norm(d["mu_x"], d["sd_x"], d["mu_y"], d["sd_y"], float(d["dt"]))
     if "env_lo" in d.files:
@@ -448,6 +527,12 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--w-mass", type=float, default=0.0, help="weight of the mass loss (Eq. 9)")
     ap.add_argument("--w-hrr", type=float, default=0.0, help="weight of the heat-release loss (Eq. 10)")
+    ap.add_argument("--species-nets", action="store_true",
+                    help="also train the per-species networks (one per mass fraction) on the same split "
+                         "and report both")
+    ap.add_argument("--species-hidden", default="1600,800,400")
+    ap.add_argument("--species-epochs", type=int, default=20)
+    ap.add_argument("--species-out", default=None, help="where to save the per-species networks")
     ap.add_argument("--recipe", default="cfg4", choices=["cfg4", "hfrd"],
                     help="cfg4: noisy trajectories + mixing lines + flame-block states; "
                          "hfrd: the paper's perturbation recipe (generate_pairs_hfrd)")
@@ -489,6 +574,24 @@ def main(argv=None):
            "holdout_frozen_rms_norm_all": ev["frozen_rms_norm_all"],
            "holdout_rms_norm": [float(v) for v in ev["rms_norm"]],
            "holdout_max_norm": [float(v) for v in ev["max_norm"]], "weights": a.out}
+    if a.species_nets:
+        hidden = tuple(int(v) for v in a.species_hidden.split(","))
+        hs = train_species_networks(ctx, (T, p, Y, Yn, hold), a.dt, hidden=hidden, epochs=a.species_epochs,
+                                    batch=a.batch, log=log)
+        es = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold], hrr_scale=hrr_unit)
+        torch.cuda.synchronize()
+        dims1 = [mech.K + 2, *hidden, 1]
+        fls = 3 * mlp_flops_per_cell(dims1[:-1] + [mech.K]) * a.batch * hs["steps"]
+        out_s = a.species_out or a.out.replace(".npz", "_species.npz")
+        save(ctx, out_s)
+        rep["species"] = {"dims": dims1, "networks": mech.K, "epochs": a.species_epochs,
+                          "train_s": hs["train_s"], "train_tflops_wall": fls / hs["train_s"] / 1e12,
+                          "loss_last": hs["loss_last"],
+                          "holdout_rms_norm_all": es["rms_norm_all"],
+                          "holdout_rms_norm": [float(v) for v in es["rms_norm"]],
+                          "holdout_max_norm": [float(v) for v in es["max_norm"]],
+                          "holdout_mass_defect": es["mass_defect_mean_abs"],
+                          "holdout_hrr_rms_err": es["hrr_rms_err"], "weights": out_s}
     print(json.dumps(rep))
 
 

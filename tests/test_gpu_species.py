@@ -1,0 +1,284 @@
+"""Per-species networks (Sec. II.B: one network per mass fraction) on the GPU,
+and the training features they rest on: hidden widths that are not multiples
+of the 64-column slab (padded internally), per-output weights of the data
+loss.  Everything against the FP64 oracle network (same BF16 rounding
+points)."""
+import numpy as np
+import pytest
+
+from oracle import ann as oann
+from synth import mechanism as sm, workload as sw
+from tests.gpu_util import announce, dev, host
+from tests.test_gpu_ann import (_check_ann_step, _gpu_out, _oracle_inputs, _run_ann, _set_norm, _states,
+                                _unpack)
+
+pytestmark = pytest.mark.gpu
+
+
+def _with_biases(params, dims, seed):
+    rng = np.random.default_rng(seed)
+    off = 0
+    for i in range(len(dims) - 1):
+        off += dims[i] * dims[i + 1]
+        params[off:off + dims[i + 1]] = rng.normal(0, 0.1, dims[i + 1]).astype(np.float32)
+        off += dims[i + 1]
+    return params
+
+
+def _net(mech, dims, seed):
+    from paper_2402_18858_amd import chemk, train
+    ctx = chemk.Context(mech)
+    ctx.ann_create(dims)
+    params = _with_biases(train.init_params(dims, seed), dims, seed + 1)
+    ctx.ann_set_weights(params)
+    return ctx, params
+
+
+def _packed(ctx, T, p, Y):
+    import torch
+    X = torch.empty((T.size, 64), dtype=torch.int16, device="cuda:0")
+    ctx.ann_pack(dev(T), dev(p), dev(Y), None, X, None)
+    return X
+
+
+def _grads_vs_oracle(ctx, dims, params, T, p, Y, mu_x, sd_x, Zt, out_w=None, w_mass=0.0):
+    import torch
+    B = T.size
+    X = _packed(ctx, T, p, Y)
+    idx = dev(np.arange(B, dtype=np.int32))
+    grads = torch.zeros(ctx.ann_param_count(), dtype=torch.float32, device="cuda:0")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    ctx.ann_train_step(idx, X, dev(Zt), 0.0, update=False, loss=loss, grads=grads, w_mass=w_mass,
+                       out_w=None if out_w is None else dev(out_w.astype(np.float32)))
+    Ws, bs = _unpack(params, dims)
+    o, cache = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
+    K = dims[-1]
+    lo, dout = oann.phys_loss(o, Zt.astype(np.float64), np.zeros(K), np.full(K, 1e-3), None, w_mass, 0.0,
+                              out_w=out_w)
+    gW, gb = oann.backward(Ws, bs, cache, dout, quantize=True)
+    ref = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(gW, gb)])
+    gg = host(grads).astype(np.float64)
+    rel = np.sqrt(np.mean((gg - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+    return host(loss)[0], lo, rel, gg, ref
+
+
+def test_hidden_widths_off_the_slab_train_like_the_oracle():
+    """Hidden widths 100 and 40 (padded to 128 and 64 inside): forward and
+    gradients against the oracle, then three Adam steps; the network the
+    library returns then still computes what the oracle computes with the
+    returned weights, so the padding units stayed at zero."""
+    mech = sm.mech_medium()
+    K = mech.K
+    dims = [K + 2, 100, 40, K]
+    ctx, params = _net(mech, dims, 31)
+    T, p, Y = _states(mech, 320, 51)
+    mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
+    Zt = np.random.default_rng(52).normal(0, 1, (T.size, K)).astype(np.float32)
+    lg, lo, rel, _, _ = _grads_vs_oracle(ctx, dims, params, T, p, Y, mu_x, sd_x, Zt)
+    out = _gpu_out(ctx, T, p, Y)
+    Ws, bs = _unpack(params, dims)
+    o, _ = oann.forward(Ws, bs, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
+    f_rel = np.sqrt(np.mean((out - o) ** 2)) / np.sqrt(np.mean(o ** 2))
+    announce(f"widths {dims}: forward rel rms {f_rel:.2e}; gradients rel rms {rel:.2e}; loss {lg:.6f} "
+             f"(oracle {lo:.6f})")
+    assert f_rel < 2e-3 and np.abs(out - o).max() < 1e-2 * o.std()
+    assert rel < 1e-2 and lg == pytest.approx(lo, rel=1e-3)
+    X = _packed(ctx, T, p, Y)
+    idx = dev(np.arange(T.size, dtype=np.int32))
+    for _ in range(3):
+        ctx.ann_train_step(idx, X, dev(Zt), 1e-3, update=True)
+    p3 = ctx.ann_get_weights()
+    assert np.abs(p3 - params).max() > 1e-4          # the weights moved
+    out3 = _gpu_out(ctx, T, p, Y)
+    W3, b3 = _unpack(p3, dims)
+    o3, _ = oann.forward(W3, b3, _oracle_inputs(T, p, Y, mu_x, sd_x), quantize=True)
+    r3 = np.sqrt(np.mean((out3 - o3) ** 2)) / np.sqrt(np.mean(o3 ** 2))
+    announce(f"after 3 Adam steps: forward rel rms {r3:.2e} against the oracle on the returned weights")
+    assert r3 < 2e-3 and np.abs(out3 - o3).max() < 1e-2 * o3.std()
+
+
+@pytest.mark.parametrize("kind", ["one_hot", "random"])
+def test_output_weights_match_oracle(kind):
+    """Per-output weights of the data loss: one-hot (the loss of one species'
+    network) and random weights, with the mass term on top; loss and
+    gradients against the oracle."""
+    mech = sm.mech_medium()
+    K = mech.K
+    dims = [K + 2, 128, 64, K]
+    ctx, params = _net(mech, dims, 33)
+    T, p, Y = _states(mech, 256, 53)
+    mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
+    rng = np.random.default_rng(54)
+    Zt = rng.normal(0, 1, (T.size, K)).astype(np.float32)
+    if kind == "one_hot":
+        w = np.zeros(K)
+        w[7] = 1.0
+    else:
+        w = rng.uniform(0.0, 3.0, K).astype(np.float32).astype(np.float64)
+    lg, lo, rel, gg, ref = _grads_vs_oracle(ctx, dims, params, T, p, Y, mu_x, sd_x, Zt, out_w=w, w_mass=0.3)
+    announce(f"out_w {kind}: gradients rel rms {rel:.2e}; loss {lg:.6f} (oracle {lo:.6f})")
+    assert lg == pytest.approx(lo, rel=1e-3)
+    assert rel < 1e-2
+    if kind == "one_hot":
+        # without the mass term only column 7 of the output layer moves
+        import torch
+        X = _packed(ctx, T, p, Y)
+        grads = torch.zeros(ctx.ann_param_count(), dtype=torch.float32, device="cuda:0")
+        ctx.ann_train_step(dev(np.arange(T.size, dtype=np.int32)), X, dev(Zt), 0.0, update=False, grads=grads,
+                           out_w=dev(w.astype(np.float32)))
+        g = host(grads)
+        nl = sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 2))
+        Wg = g[nl:nl + dims[-2] * K].reshape(dims[-2], K)
+        bg = g[nl + dims[-2] * K:]
+        others = np.arange(K) != 7
+        assert np.all(Wg[:, others] == 0.0) and np.all(bg[others] == 0.0)
+        assert np.abs(Wg[:, 7]).max() > 0.0
+    X = _packed(ctx, T, p, Y)
+    idx = dev(np.arange(T.size, dtype=np.int32))
+    for bad in (np.zeros(K), np.r_[-1.0, np.ones(K - 1)], np.r_[np.nan, np.ones(K - 1)]):
+        with pytest.raises(Exception):
+            ctx.ann_train_step(idx, X, dev(Zt), 0.0, update=False, out_w=dev(bad.astype(np.float32)))
+
+
+def _species_ctx(mech, dims1, nets_params):
+    """A context holding the K one-output networks dims1 = [K+2, ..., 1]."""
+    from paper_2402_18858_amd import chemk
+    ctx = chemk.Context(mech)
+    ctx.ann_create_species(dims1)
+    ctx.ann_set_weights(np.concatenate(nets_params))
+    return ctx
+
+
+def test_species_networks_equal_the_k_output_network_they_are_cut_from():
+    """K one-output networks cut from a K-output network (hidden layers
+    shared, output column k) run as the ensemble (one first-layer product,
+    grouped hidden products, a block-diagonal output product) must give the
+    K-output network's outputs: the same BF16 operands and FP32 sums, only
+    exact zeros added in the block-diagonal layer.  Rows: several 128-row
+    tiles and a ragged tail."""
+    from paper_2402_18858_amd import train
+    mech = sm.mech_medium()
+    K = mech.K
+    dims = [K + 2, 128, 64, K]
+    ctx, params = _net(mech, dims, 35)
+    T, p, Y = _states(mech, 700, 55)
+    mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
+    out1 = _gpu_out(ctx, T, p, Y)
+    ens = _species_ctx(mech, dims[:-1] + [1], [train.species_slice(params, dims, k) for k in range(K)])
+    _set_norm(ens, mech, T, p, Y)
+    assert ens.ann_param_count() == K * sum(d * e + e for d, e in zip(dims[:-1], dims[1:-1] + [1]))
+    np.testing.assert_array_equal(ens.ann_get_weights()[:params.size // K],
+                                  train.species_slice(params, dims, 0)[:params.size // K])
+    out2 = _gpu_out(ens, T, p, Y)
+    d = np.abs(out2 - out1)
+    announce(f"ensemble vs the K-output network: max |diff| {d.max():.3e} ({(d == 0).mean() * 100:.2f} % "
+             f"of outputs bitwise equal), outputs' spread {out1.std():.3e}")
+    assert d.max() <= 1e-5 * out1.std()
+
+
+def test_species_networks_match_oracle_and_drive_the_advance():
+    """K distinct random networks 34-96-72-1 (padded to 128 and 128 inside)
+    against the oracle's per-species forward on 700 rows; the ANN step of
+    chemk_advance on them against the oracle post step; the forward over more
+    rows than one chunk holds (two chunks of 65,536 rows and a ragged tail),
+    sampled at the chunk edges."""
+    import torch
+    from paper_2402_18858_amd import train
+    mech = sm.mech_medium()
+    K = mech.K
+    dims1 = [K + 2, 96, 72, 1]
+    nets = [_with_biases(train.init_params(dims1, 100 + k), dims1, 200 + k) for k in range(K)]
+    ens = _species_ctx(mech, dims1, nets)
+    T, p, Y = _states(mech, 700, 56)
+    mu_x, sd_x = _set_norm(ens, mech, T, p, Y)
+    out = _gpu_out(ens, T, p, Y)
+    o = oann.species_forward([_unpack(v, dims1) for v in nets], _oracle_inputs(T, p, Y, mu_x, sd_x))
+    rel = np.sqrt(np.mean((out - o) ** 2)) / np.sqrt(np.mean(o ** 2))
+    announce(f"ensemble {K} x {dims1}: rel rms {rel:.2e}, max {np.abs(out - o).max():.2e} "
+             f"(spread {o.std():.2e})")
+    assert rel < 2e-3 and np.abs(out - o).max() < 1e-2 * o.std()
+    # the ANN step on the ensemble's output
+    n = 3000
+    T, p, Y = _states(mech, n, 57)
+    rng = np.random.default_rng(58)
+    raw = oann.raw_features(T, p, Y)
+    mu_x, sd_x = oann.norm_stats(raw)
+    sd_y = 10.0 ** rng.uniform(-5.5, -2.5, K)
+    ens.ann_set_norm(mu_x, sd_x, np.zeros(K), sd_y, 5e-7)
+    ens.ann_set_checks(adj_max=2.5, dT=(-40.0, 60.0))
+    Tg, Yg, sg = _run_ann(ens, T, p, Y, 5e-7)
+    routed, net = _check_ann_step(mech, ens, T, p, Y, Tg, Yg, sg, ens.ann_get_checks(),
+                                  f"ensemble ANN step ({n} cells)")
+    assert net.sum() > 0 and routed.sum() > 0
+    # 2 x 32 x (128 + 128) B of activations per row: a chunk is the 65,536-row cap
+    chunk = 65536
+    n = 2 * chunk + 333
+    T, p, Y = _states(mech, n, 61)
+    X = _packed(ens, T, p, Y)
+    outd = torch.empty((n, K), dtype=torch.float32, device="cuda:0")
+    ens.ann_forward_packed(X, outd)
+    rows = np.unique(np.r_[np.arange(0, 32), np.arange(chunk - 32, chunk + 32),
+                           np.arange(2 * chunk - 32, 2 * chunk + 32), np.arange(n - 32, n)])
+    o = oann.species_forward([_unpack(v, dims1) for v in nets],
+                             _oracle_inputs(T[rows], p[rows], Y[rows], mu_x, sd_x))
+    g = host(outd)[rows].astype(np.float64)
+    rel = np.sqrt(np.mean((g - o) ** 2)) / np.sqrt(np.mean(o ** 2))
+    announce(f"ensemble forward over chunk edges ({n} rows), {rows.size} rows: rel rms {rel:.2e}")
+    assert rel < 2e-3 and np.abs(g - o).max() < 1e-2 * o.std()
+
+
+def test_species_networks_at_paper_size_on_the_flame_block():
+    """The paper's per-species networks (hidden 1600-800-400, GELU) for all
+    K = 32 species, random weights, on the 262,144-cell flame block in the
+    launch configuration of the timed ensemble forward (chunks of 17,408
+    rows): sampled rows (chunk edges and random ones) against the oracle."""
+    import torch
+    from paper_2402_18858_amd import train
+    mech = sm.mech_medium()
+    K = mech.K
+    dims1 = [K + 2, 1600, 800, 400, 1]
+    nets = [_with_biases(train.init_params(dims1, 300 + k), dims1, 400 + k) for k in range(K)]
+    ens = _species_ctx(mech, dims1, nets)
+    T, p, Y, _ = sw.flame_block(mech, 64, 2002)
+    mu_x, sd_x = oann.norm_stats(oann.raw_features(T[::64], p[::64], Y[::64]))
+    ens.ann_set_norm(mu_x, sd_x, np.zeros(K), np.full(K, 1e-3), 5e-7)
+    n = T.size
+    X = _packed(ens, T, p, Y)
+    out = torch.empty((n, K), dtype=torch.float32, device="cuda:0")
+    ens.ann_forward_packed(X, out)
+    g_all = host(out)
+    rng = np.random.default_rng(59)
+    ch = 17408
+    rows = np.unique(np.r_[np.arange(0, 16), np.arange(ch - 16, ch + 16), np.arange(15 * ch - 16, 15 * ch + 16),
+                           np.arange(n - 16, n), rng.choice(n, 64, replace=False)])
+    o = oann.species_forward([_unpack(v, dims1) for v in nets],
+                             _oracle_inputs(T[rows], p[rows], Y[rows], mu_x, sd_x))
+    g = g_all[rows].astype(np.float64)
+    rel = np.sqrt(np.mean((g - o) ** 2)) / np.sqrt(np.mean(o ** 2))
+    announce(f"paper-size ensemble on {n} cells, {rows.size} sampled rows: rel rms {rel:.2e}, max "
+             f"{np.abs(g - o).max():.2e} (spread {o.std():.2e})")
+    assert np.isfinite(g_all).all()
+    assert rel < 2e-3 and np.abs(g - o).max() < 2e-2 * o.std()
+
+
+def test_species_networks_refuse_training_and_bad_shapes():
+    import torch
+    from paper_2402_18858_amd import chemk, train
+    mech = sm.mech_medium()
+    K = mech.K
+    dims1 = [K + 2, 64, 1]
+    ens = _species_ctx(mech, dims1, [train.init_params(dims1, k) for k in range(K)])
+    T, p, Y = _states(mech, 128, 60)
+    _set_norm(ens, mech, T, p, Y)
+    X = _packed(ens, T, p, Y)
+    Zt = torch.zeros((128, K), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(chemk.ChemkError):
+        ens.ann_train_step(dev(np.arange(128, dtype=np.int32)), X, Zt, 1e-3)
+    with pytest.raises(chemk.ChemkError):
+        ens.ann_train(X, Zt, 1, batch=128)
+    with pytest.raises(chemk.ChemkError):
+        ens.ann_reset_optimizer()
+    ctx = chemk.Context(mech)
+    for bad in ([K + 2, 1], [K + 2, 64, 2], [K + 1, 64, 1]):
+        with pytest.raises(chemk.ChemkError):
+            ctx.ann_create_species(bad)

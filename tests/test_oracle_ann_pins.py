@@ -287,6 +287,35 @@ def test_output_weights_one_hot_uniform_and_by_hand():
     np.testing.assert_array_equal(g, [[2 * 1 * 1 / 8, 2 * 3 * 2 / 8], [0.0, 2 * 3 * -1 / 8]])
 
 
+def test_species_networks_reproduce_the_k_output_network():
+    """Splitting a K-output network into K one-output networks (hidden
+    layers shared, output column k) must give the same outputs column by
+    column: pins the column order of species_forward (a transposed stack, a
+    shifted column or the wrong output slice fails)."""
+    rng = np.random.default_rng(5)
+    dims = [7, 12, 9, 5]
+    Ws, bs = ann.init_params(dims, 3)
+    bs = [rng.normal(0, 0.1, b.shape) for b in bs]
+    X = rng.normal(size=(11, 7))
+    for q in (False, True):
+        full, _ = ann.forward(Ws, bs, X, quantize=q)
+        sp = ann.species_forward(ann.species_split(Ws, bs), X, quantize=q)
+        assert sp.shape == full.shape
+        # equal up to the summation order of the library product
+        np.testing.assert_allclose(sp, full, rtol=1e-13, atol=1e-15)
+    # distinct networks: column k is network k's own forward, by hand for a
+    # one-hidden-unit network with identity-like weights
+    nets = []
+    for k in range(3):
+        W = [np.full((2, 1), float(k + 1)), np.array([[2.0]])]
+        b = [np.zeros(1), np.array([float(k)])]
+        nets.append((W, b))
+    x = np.array([[1.0, 0.5]])
+    out = ann.species_forward(nets, x, quantize=False)
+    expect = [2.0 * ann.gelu(np.array(1.5 * (k + 1)))[()] + k for k in range(3)]
+    np.testing.assert_allclose(out[0], expect, rtol=1e-15)
+
+
 def test_weighted_loss_gradient_matches_finite_differences():
     rng = np.random.default_rng(4)
     B, K = 5, 4
