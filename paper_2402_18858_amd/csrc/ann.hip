@@ -873,6 +873,27 @@ __global__ void adam_kernel(float *p, const float *__restrict__ g, float *mo, fl
 }
 
 // BF16 copies of one layer: Wt [out x in] (forward, K-contiguous) and W [in x out]
+// dst[g n + j] = src[g stride + j] rounded to BF16 (kept as FP32), j < n, g < G
+__global__ void bf16_rows_kernel(const float *__restrict__ src, size_t stride, int n, int G, float *dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * G) return;
+    const int g = i / n, j = i - g * n;
+    dst[i] = __uint_as_float((uint32_t)f2bf(src[g * stride + j]) << 16);
+}
+
+// out[r, g] = sum_p P[r, g S + p] (p ascending) + b[g]: the per-species
+// networks' outputs from the fused last hidden layer's partial sums
+__global__ void species_out_kernel(const float *__restrict__ P, int S, int G, int rows,
+                                   const float *__restrict__ b, float *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * G) return;
+    const int g = i % G;
+    const float *p = P + (size_t)i * S;
+    float s = 0.f;
+    for (int k = 0; k < S; ++k) s += p[k];
+    out[i] = s + b[g];
+}
+
 __global__ void cast_layer_kernel(const float *__restrict__ Wm, int in, int out, uint16_t *Wt,
                                   uint16_t *Wb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1132,6 +1153,8 @@ struct AnnState {
     int G = 1;
     size_t gstride = 0;
     std::vector<float *> eB;          // ensemble biases per layer [G pd[l+1]]
+    float *eW = nullptr;              // output weights, BF16-rounded, [G pd[L-1]] (L >= 3)
+    float *eP = nullptr;              // partial output sums of the fused last hidden layer
     std::vector<int> dims;       // logical, dims[0] = K + 2
     std::vector<int> pd;         // internal: pd[0] = FPAD
     std::vector<size_t> woff, boff;   // offsets (floats) of W_l, b_l in the master vector
@@ -1190,6 +1213,8 @@ void ann_destroy(AnnState *a) {
     for (auto p : a->Wt) (void)hipFree(p);
     for (auto p : a->Wb) (void)hipFree(p);
     for (auto p : a->eB) (void)hipFree(p);
+    (void)hipFree(a->eW);
+    (void)hipFree(a->eP);
     (void)hipFree(a->normdev);
     (void)hipFree(a->rowtab);
     (void)hipFree(a->X);
@@ -1229,8 +1254,17 @@ static hipError_t refresh_ensemble(AnnState *a, hipStream_t s) {
                                         4 * (size_t)out, G, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
+    if (a->eW) {
+        const int n = a->pd[L - 1];
+        hipLaunchKernelGGL(bf16_rows_kernel, dim3((n * G + 255) / 256), dim3(256), 0, s,
+                           a->master + a->woff[L - 1], a->gstride, n, G, a->eW);
+    }
     return hipGetLastError();
 }
+
+// partial sums per row and network of the fused last hidden layer: two per
+// 128-column tile of its padded width
+static int species_slots(const AnnState *a) { return 2 * ((a->pd[a->L - 1] + 127) / 128); }
 
 static hipError_t refresh_bf16(AnnState *a, hipStream_t s) {
     if (a->G > 1) return refresh_ensemble(a, s);
@@ -1305,23 +1339,36 @@ static hipError_t row_tables(AnnState *a, const DevMech &m, hipStream_t s, const
 // first layers of all networks read the same input, so they are one product
 // [rows x FPAD] x [FPAD x G pd1]; hidden layer l is a grouped product, network
 // g multiplying its column slab g of the previous activations [rows x G pd[l]]
-// by its own weights; the output layer is one product with a block-diagonal
-// [G pd[L-1] x G] matrix (network g's output weights in block g), so that out
-// [rows x K] holds network k's prediction in column k.  (The zeros of the
-// block-diagonal matrix are exact in the FP32 sums; that layer is about 1 % of
-// the work.)  Activations of network g sit in columns [g pd[l], (g+1) pd[l]).
+// by its own weights.  Activations of network g sit in columns
+// [g pd[l], (g+1) pd[l]).  With two hidden layers or more, the last hidden
+// layer's epilogue also applies the one-output layer (EPI_GELU_DOT: BF16
+// activations times BF16-rounded output weights, summed in FP32 per 64-column
+// half tile), so its activations are never stored, and species_out_kernel
+// adds the partial sums and the bias into column k of out [rows x K].  With
+// one hidden layer the output layer is one product with a block-diagonal
+// [G pd[1] x G] matrix (network g's output weights in block g; its zeros are
+// exact in the FP32 sums).
 static hipError_t ens_forward(AnnState *a, const uint16_t *X, int rows, float *out, uint16_t *buf0,
                               uint16_t *buf1, hipStream_t s, PhaseTimer *tm) {
     const int G = a->G, L = a->L;
+    const bool fuse = a->eW != nullptr;   // L >= 3
+    const int S = fuse ? species_slots(a) : 0;
     const uint16_t *in = X;
     uint16_t *bufs[2] = {buf0, buf1};
     for (int l = 0; l < L; ++l) {
+        const bool last = l == L - 1;
+        const int ph = CHEMK_PHASE_LAYER1 + (l < 3 ? l : 3);
+        if (fuse && last) {
+            if (tm) tm->begin(ph, s);
+            hipLaunchKernelGGL(species_out_kernel, dim3((rows * G + 255) / 256), dim3(256), 0, s, a->eP, S, G,
+                               rows, a->eB[l], out);
+            if (tm) tm->end(ph, s);
+            return hipGetLastError();
+        }
         GemmArgs g{};
         g.M = rows;
         g.B = a->Wt[l];
         g.bias = a->eB[l];
-        const bool last = l == L - 1;
-        const int ph = CHEMK_PHASE_LAYER1 + (l < 3 ? l : 3);
         int groups = 1, epi = EPI_BIAS_GELU;
         uint16_t *dst = bufs[l & 1];
         if (l == 0) {
@@ -1351,6 +1398,12 @@ static hipError_t ens_forward(AnnState *a, const uint16_t *X, int rows, float *o
         if (last) {
             g.Cf = out;
             g.ldc = G;
+        } else if (fuse && l == L - 2) {
+            epi = EPI_GELU_DOT;
+            g.Zin = a->eW;            // + z pd[L-1] per network (gsC)
+            g.Cf = a->eP;
+            g.ldc = G * S;
+            g.gsCf = S;
         } else {
             g.Cb = dst;
             g.ldcb = G * a->pd[l + 1];
@@ -1433,6 +1486,8 @@ static hipError_t ensure_infer(AnnState *a, int64_t n) {
     (void)hipFree(a->out);
     (void)hipFree(a->act[0]);
     (void)hipFree(a->act[1]);
+    (void)hipFree(a->eP);
+    a->eP = nullptr;
     a->cap = 0;
     int64_t wmax = 0;
     for (int l = 1; l < a->L; ++l) wmax = std::max<int64_t>(wmax, (int64_t)a->G * a->pd[l]);
@@ -1444,6 +1499,7 @@ static hipError_t ensure_infer(AnnState *a, int64_t n) {
     if ((e = hipMalloc(&a->out, sizeof(float) * n * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->act[0], sizeof(uint16_t) * ch * wmax)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->act[1], sizeof(uint16_t) * ch * wmax)) != hipSuccess) return e;
+    if (a->eW && (e = hipMalloc(&a->eP, sizeof(float) * ch * a->G * species_slots(a))) != hipSuccess) return e;
     a->cap = n;
     a->generation = next_generation();
     return hipSuccess;
@@ -1687,6 +1743,7 @@ static int create_net(chemk_ctx *c, const int32_t *dims, int32_t L, int G) {
             a->Wt.push_back(wt);
             a->eB.push_back(b);
         }
+        if (L >= 3) ANN_TRY(hipMalloc(&a->eW, 4 * (size_t)G * a->pd[L - 1]));
     }
     ANN_TRY(hipMalloc(&a->normdev, 8 * normdev_doubles(a)));
     ANN_TRY(hipMalloc(&a->rowtab, 8 * ROW_TAB_DOUBLES));

@@ -9,7 +9,12 @@ enum GemmEpilogue {
     EPI_BIAS_GELU = 0,   // Cb = bf16(gelu(acc + bias)); Cf (optional) = acc + bias
     EPI_BIAS = 1,        // Cf = acc + bias
     EPI_STORE_F32 = 2,   // Cf = acc
-    EPI_GELU_GRAD = 3    // Cb = bf16(acc * gelu'(Zin))
+    EPI_GELU_GRAD = 3,   // Cb = bf16(acc * gelu'(Zin))
+    // a = bf16(gelu(acc + bias)) dotted with a weight row: for each output
+    // row, each wave-half tile (64 columns) writes sum_c a(row, c) Zin[c] over
+    // its columns c < N to Cf[row * ldc + 2 (n0 / 128) + half] (the per-species
+    // networks' last hidden layer fused with their one-output layer)
+    EPI_GELU_DOT = 4
 };
 
 struct GemmArgs {
@@ -30,8 +35,8 @@ struct GemmArgs {
     // to Cf + z * split_stride
     long long split_stride;
     // groups over gridDim.z > 1 (launch_gemm with groups > 1): group z offsets
-    // A by z gsA, B by z gsB, and bias, Cf, Cb and Zin by z gsC elements
-    long long gsA, gsB, gsC;
+    // A by z gsA, B by z gsB, bias, Cb and Zin by z gsC, Cf by z gsCf elements
+    long long gsA, gsB, gsC, gsCf;
 };
 
 // Any K >= 1 and leading dimensions; operands in whole, 16-byte aligned

@@ -68,7 +68,7 @@ __device__ __forceinline__ void group_offsets(GemmArgs &g) {
         g.B += z * g.gsB;
         const long long c = z * g.gsC;
         if (g.bias) g.bias += c;
-        if (g.Cf) g.Cf += c;
+        if (g.Cf) g.Cf += z * g.gsCf;
         if (g.Cb) g.Cb += c;
         if (g.Zin) g.Zin += c;
     }
@@ -235,6 +235,40 @@ __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16_t (&a
     const bool vz = g.Zin && g.ldz % 4 == 0 && ((uintptr_t)g.Zin & 15) == 0;
     const bool vbias = g.bias && ((uintptr_t)g.bias & 15) == 0;
     const int lr = lane & 31, lc = (lane >> 5) * 4;
+    // The last hidden layer of the per-species networks fused with their
+    // output layer: the activations never leave the registers.  Lane l holds
+    // rows wm + 32 i + (l % 32) and columns wn + 32 j + 8 q + 4 (l / 32) + r;
+    // each lane sums its columns' a Zin products, lanes l and l + 32 (the same
+    // rows) add theirs, and the wave's 64 rows get one partial each.  N is a
+    // multiple of 4, so a quad of columns is inside or outside as a whole.
+    if constexpr (EPI == EPI_GELU_DOT) {
+        const int slot = 2 * (n0 / BN) + (wn ? 1 : 0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            float sum = 0.f;
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int col = n0 + wn + j * 32 + q * 8 + lc;
+                    if (col < g.N) {
+                        const float4 b = *reinterpret_cast<const float4 *>(g.bias + col);
+                        const float4 w = *reinterpret_cast<const float4 *>(g.Zin + col);
+                        const floatx16_t &v = acc[i][j];
+                        const uint32_t p0 = pack_bf16x2(gelu_f(v[4 * q] + b.x), gelu_f(v[4 * q + 1] + b.y));
+                        const uint32_t p1 = pack_bf16x2(gelu_f(v[4 * q + 2] + b.z), gelu_f(v[4 * q + 3] + b.w));
+                        sum = fmaf(__uint_as_float(p0 << 16), w.x, sum);
+                        sum = fmaf(__uint_as_float(p0 & 0xffff0000u), w.y, sum);
+                        sum = fmaf(__uint_as_float(p1 << 16), w.z, sum);
+                        sum = fmaf(__uint_as_float(p1 & 0xffff0000u), w.w, sum);
+                    }
+                }
+            sum += __shfl_xor(sum, 32, 64);
+            const int row = m0 + wm + i * 32 + lr;
+            if (lane < 32 && row < g.M) g.Cf[(size_t)row * g.ldc + slot] = sum;
+        }
+        return;
+    }
     // Forward BF16-only layers on a whole tile: the wave's (BM/2) x (BN/2)
     // output goes through its LDS staging area (rows of BN/2 + 8 elements) so
     // that each global store instruction writes whole 128-byte row segments
@@ -633,7 +667,7 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s, int gr
     const dim3 grid(((tiles + 7) / 8) * 8, 1, groups);
     const int kt = (g.K + TK - 1) / TK;
     // forward layers of the MLP get a K loop unrolled for their slab count
-    constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS);
+    constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS || EP == EPI_GELU_DOT);
 #define GEMM_LAUNCH(VECV)                                                                    \
     hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV>), dim3(grid),         \
                        dim3(NTHREADS), 0, s, g)
@@ -713,6 +747,12 @@ hipError_t launch_gemm(const GemmArgs &g, bool a_kcont, bool b_kcont, int epi, h
             case EPI_BIAS: return launch_case<true, true, EPI_BIAS>(g, vec, s, groups);
             case EPI_GELU_GRAD: return launch_case<true, true, EPI_GELU_GRAD>(g, vec, s, groups);
             case EPI_STORE_F32: return launch_case<true, true, EPI_STORE_F32>(g, vec, s, groups);
+            case EPI_GELU_DOT:
+                // float4 reads of bias and weights; whole column quads
+                if (!g.bias || !g.Zin || !g.Cf || g.N % 4 != 0 || ((uintptr_t)g.bias & 15) ||
+                    ((uintptr_t)g.Zin & 15) || (groups > 1 && g.gsC % 4 != 0))
+                    return hipErrorInvalidValue;
+                return launch_case<true, true, EPI_GELU_DOT>(g, vec, s, groups);
             default: return hipErrorInvalidValue;
         }
     }

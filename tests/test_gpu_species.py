@@ -149,31 +149,38 @@ def _species_ctx(mech, dims1, nets_params):
     return ctx
 
 
-def test_species_networks_equal_the_k_output_network_they_are_cut_from():
+@pytest.mark.parametrize("hidden", [(128,), (128, 64)], ids=["one_hidden", "two_hidden"])
+def test_species_networks_equal_the_k_output_network_they_are_cut_from(hidden):
     """K one-output networks cut from a K-output network (hidden layers
-    shared, output column k) run as the ensemble (one first-layer product,
-    grouped hidden products, a block-diagonal output product) must give the
-    K-output network's outputs: the same BF16 operands and FP32 sums, only
-    exact zeros added in the block-diagonal layer.  Rows: several 128-row
-    tiles and a ragged tail."""
+    shared, output column k) run as the ensemble must give the K-output
+    network's outputs.  One hidden layer: the first-layer product and the
+    block-diagonal output product see the same BF16 operands and FP32 sums as
+    the K-output network, with only exact zeros added, so the outputs are
+    bitwise equal.  Two: the output layer is fused into the grouped last
+    hidden layer, whose FP32 sums run in another order (within 1e-5 of the
+    outputs' spread).  Rows: several 128-row tiles and a ragged tail."""
     from paper_2402_18858_amd import train
     mech = sm.mech_medium()
     K = mech.K
-    dims = [K + 2, 128, 64, K]
+    dims = [K + 2, *hidden, K]
     ctx, params = _net(mech, dims, 35)
     T, p, Y = _states(mech, 700, 55)
     mu_x, sd_x = _set_norm(ctx, mech, T, p, Y)
     out1 = _gpu_out(ctx, T, p, Y)
     ens = _species_ctx(mech, dims[:-1] + [1], [train.species_slice(params, dims, k) for k in range(K)])
     _set_norm(ens, mech, T, p, Y)
-    assert ens.ann_param_count() == K * sum(d * e + e for d, e in zip(dims[:-1], dims[1:-1] + [1]))
-    np.testing.assert_array_equal(ens.ann_get_weights()[:params.size // K],
-                                  train.species_slice(params, dims, 0)[:params.size // K])
+    one = dims[:-1] + [1]
+    assert ens.ann_param_count() == K * sum(d * e + e for d, e in zip(one[:-1], one[1:]))
+    np.testing.assert_array_equal(ens.ann_get_weights(),
+                                  np.concatenate([train.species_slice(params, dims, k) for k in range(K)]))
     out2 = _gpu_out(ens, T, p, Y)
     d = np.abs(out2 - out1)
-    announce(f"ensemble vs the K-output network: max |diff| {d.max():.3e} ({(d == 0).mean() * 100:.2f} % "
-             f"of outputs bitwise equal), outputs' spread {out1.std():.3e}")
-    assert d.max() <= 1e-5 * out1.std()
+    announce(f"ensemble {hidden} vs the K-output network: max |diff| {d.max():.3e} "
+             f"({(d == 0).mean() * 100:.2f} % of outputs bitwise equal), outputs' spread {out1.std():.3e}")
+    if len(hidden) == 1:
+        assert d.max() == 0.0
+    else:
+        assert d.max() <= 1e-5 * out1.std()
 
 
 def test_species_networks_match_oracle_and_drive_the_advance():
