@@ -660,6 +660,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_dma_kernel(GemmArgs g) {
     }
 }
 
+#ifndef SPECIES_STAGES
+#define SPECIES_STAGES 1   // LDS stages of the 25- and 13-slab instances
+#endif
+
 template <bool AKV, bool BKV, int EP>
 static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s, int groups) {
     constexpr int TB = 128, TK = 64;
@@ -683,8 +687,8 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s, int gr
         else if (kt == 4) hipLaunchKernelGGL((gemm_dma_kernel<EP, 4, 2>), dim3(grid), dim3(NTHREADS), 0, s, g);
         // the hidden layers of the per-species networks (1600 -> 800 -> 400,
         // K = 1600 and 832): 1.24 and 1.34 times faster than the register ring
-        else if (kt == 25) hipLaunchKernelGGL((gemm_dma_kernel<EP, 25, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
-        else if (kt == 13) hipLaunchKernelGGL((gemm_dma_kernel<EP, 13, 1>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 25) hipLaunchKernelGGL((gemm_dma_kernel<EP, 25, SPECIES_STAGES>), dim3(grid), dim3(NTHREADS), 0, s, g);
+        else if (kt == 13) hipLaunchKernelGGL((gemm_dma_kernel<EP, 13, SPECIES_STAGES>), dim3(grid), dim3(NTHREADS), 0, s, g);
         else GEMM_LAUNCH(true);
     } else {
         GEMM_LAUNCH(true);

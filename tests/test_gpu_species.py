@@ -234,6 +234,67 @@ def test_species_networks_match_oracle_and_drive_the_advance():
     assert rel < 2e-3 and np.abs(g - o).max() < 1e-2 * o.std()
 
 
+def test_species_networks_graph_replays_match_eager():
+    """ANN mode with use_graph=1 on per-species networks: replays of the
+    captured step equal the eager step bitwise (eager work in between); then
+    the context switches to one K-output network and back to per-species
+    networks, and each time the next captured step again equals the eager
+    one (no graph of the previous network is replayed)."""
+    import torch
+    from paper_2402_18858_amd import chemk, train
+    mech = sm.mech_medium()
+    K = mech.K
+    dims1 = [K + 2, 96, 72, 1]
+    nets = [_with_biases(train.init_params(dims1, 600 + k), dims1, 700 + k) for k in range(K)]
+    ctx = _species_ctx(mech, dims1, nets)
+    n = 3000
+    T, p, Y = _states(mech, n, 62)
+    raw = oann.raw_features(T, p, Y)
+    mu_x, sd_x = oann.norm_stats(raw)
+    sd_y = 10.0 ** np.random.default_rng(63).uniform(-5.5, -2.5, K)
+
+    def setup_norm():
+        ctx.ann_set_norm(mu_x, sd_x, np.zeros(K), sd_y, 5e-7)
+        ctx.ann_set_checks(adj_max=2.5, dT=(-40.0, 60.0))
+
+    setup_norm()
+    Pt, Tt, Yt = dev(p), dev(T), dev(Y)
+    st = torch.full((n,), -1, dtype=torch.int32, device="cuda:0")
+    og = chemk.default_opts(mode=chemk.MODE_ANN, use_graph=1)
+
+    def graph_step():
+        Tt.copy_(dev(T))
+        Yt.copy_(dev(Y))
+        st.fill_(-1)
+        ctx.advance(Tt, Pt, Yt, 5e-7, st, None, opts=og)
+        torch.cuda.synchronize()
+        return host(Tt), host(Yt), host(st)
+
+    outs = []
+    for phase in range(3):
+        ref = _run_ann(ctx, T, p, Y, 5e-7)
+        for rep in range(3):
+            got = graph_step()
+            for a_, b_ in zip(ref, got):
+                assert np.array_equal(a_, b_), (phase, rep)
+            _run_ann(ctx, T[:300], p[:300], Y[:300], 5e-7)
+        nr = int(((ref[2] & chemk.CELL_ROUTED_DI) != 0).sum())
+        announce(f"species graph phase {phase}: 3 replays equal the eager step ({nr} routed)")
+        outs.append(ref[1])
+        if phase == 0:
+            dims = [K + 2, 128, 64, K]
+            ctx.ann_create(dims)
+            ctx.ann_set_weights(_with_biases(train.init_params(dims, 64), dims, 65))
+            setup_norm()
+        elif phase == 1:
+            ctx.ann_create_species(dims1)
+            ctx.ann_set_weights(np.concatenate(nets))
+            setup_norm()
+    # back on the same networks: the same result as the first phase
+    assert np.array_equal(outs[0], outs[2])
+    assert not np.array_equal(outs[0], outs[1])
+
+
 def test_species_networks_at_paper_size_on_the_flame_block():
     """The paper's per-species networks (hidden 1600-800-400, GELU) for all
     K = 32 species, random weights, on the 262,144-cell flame block in the
