@@ -253,7 +253,8 @@ void chemk_tune_cache_clear(void);
 
 /* Phase timing (profiling aid).  While enabled, chemk_advance runs eagerly
  * (use_graph is ignored) and brackets each phase's launches with HIP events
- * on the caller's stream; chemk_timing_read synchronises the stream and
+ * on the caller's stream (chemk_ann_forward_packed brackets its layer
+ * launches too); chemk_timing_read synchronises the stream and
  * returns, per phase, the summed milliseconds and the number of launches
  * since the last read (then resets).  Phases: */
 enum {

@@ -1604,6 +1604,7 @@ hipError_t ann_enqueue_step(AnnState *a, const AnnStepArgs &x, hipStream_t s) {
 // C ABI
 // ---------------------------------------------------------------------------
 AnnState *&ctx_ann(chemk_ctx *c);
+chemk::PhaseTimer *ctx_timer(chemk_ctx *c);
 int ctx_device(chemk_ctx *c);
 int ctx_K(chemk_ctx *c);
 void ctx_set_error(const char *msg);
@@ -2132,9 +2133,11 @@ extern "C" int chemk_ann_forward_packed(chemk_ctx *c, int64_t n, const uint16_t 
     const int chunk = chunk_rows(a);
     ANN_TRY(ensure_infer(a, std::min<int64_t>(n, chunk)));
     hipStream_t s = (hipStream_t)stream;
+    PhaseTimer *tm = ctx_timer(c);   // per-layer phases while timing is on
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
         const int rows = (int)std::min<int64_t>(chunk, n - c0);
-        ANN_TRY(mlp_forward(a, X + c0 * FPAD, rows, out + c0 * a->K, a->act[0], a->act[1], s));
+        ANN_TRY(mlp_forward(a, X + c0 * FPAD, rows, out + c0 * a->K, a->act[0], a->act[1], s, nullptr,
+                            nullptr, tm));
     }
     return CHEMK_OK;
 }

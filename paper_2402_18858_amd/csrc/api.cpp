@@ -194,6 +194,7 @@ static constexpr int kMaxBins = 256;
 // accessors for the learned part (ann.hip)
 AnnState *&ctx_ann(chemk_ctx *c) { return c->ann; }
 void *&ctx_transport(chemk_ctx *c) { return c->transport; }
+chemk::PhaseTimer *ctx_timer(chemk_ctx *c) { return c->timer.on ? &c->timer : nullptr; }
 int ctx_device(chemk_ctx *c) { return c->device; }
 int ctx_K(chemk_ctx *c) { return c->K; }
 void ctx_set_error(const char *msg) { g_err = msg; }
