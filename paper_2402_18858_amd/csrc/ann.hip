@@ -836,16 +836,35 @@ __global__ void ctl_init_kernel(long long *ctl, long long before) {
 constexpr int COLSUM_ROWS = 64;
 
 __global__ void colsum_part_kernel(const uint16_t *__restrict__ dZ, int B, int N, float *part) {
+    const int b0 = blockIdx.y * COLSUM_ROWS;
+    const int rows = B - b0 < COLSUM_ROWS ? B - b0 : COLSUM_ROWS;
+    if (N % 8 == 0) {
+        // eight columns per thread, one 16-byte load per row; rows summed in order
+        const int o = 8 * (blockIdx.x * blockDim.x + threadIdx.x);
+        if (o >= N) return;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const uint16_t *p = dZ + (size_t)b0 * N + o;
+#pragma unroll 8
+        for (int i = 0; i < rows; ++i) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(p + (size_t)i * N);
+            s[0] += __uint_as_float(v.x << 16);
+            s[1] += __uint_as_float(v.x & 0xffff0000u);
+            s[2] += __uint_as_float(v.y << 16);
+            s[3] += __uint_as_float(v.y & 0xffff0000u);
+            s[4] += __uint_as_float(v.z << 16);
+            s[5] += __uint_as_float(v.z & 0xffff0000u);
+            s[6] += __uint_as_float(v.w << 16);
+            s[7] += __uint_as_float(v.w & 0xffff0000u);
+        }
+        float *q = part + (size_t)blockIdx.y * N + o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = s[j];
+        return;
+    }
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= N) return;
-    const int b0 = blockIdx.y * COLSUM_ROWS;
-    // a fixed trip count: the loads are issued back to back, then summed in order
-    float v[COLSUM_ROWS];
-#pragma unroll
-    for (int i = 0; i < COLSUM_ROWS; ++i) v[i] = b0 + i < B ? bf2f(dZ[(size_t)(b0 + i) * N + o]) : 0.f;
     float s = 0.f;
-#pragma unroll
-    for (int i = 0; i < COLSUM_ROWS; ++i) s += v[i];
+    for (int i = 0; i < rows; ++i) s += bf2f(dZ[(size_t)(b0 + i) * N + o]);
     part[(size_t)blockIdx.y * N + o] = s;
 }
 
@@ -1182,10 +1201,16 @@ struct AnnState {
     uint16_t *act[2] = {nullptr, nullptr};
     // training scratch
     int tB = 0;
-    uint16_t *tX = nullptr, *tdZ[2] = {nullptr, nullptr};
+    uint16_t *tX = nullptr;
+    std::vector<uint16_t *> tdZ;      // dLoss/dZ of each layer's output [B x pd[l+1]]
     float *tZt = nullptr, *tOut = nullptr, *tLoss = nullptr, *tGt = nullptr;
-    float *tWork = nullptr;   // split-K and column-sum partials
-    size_t tWorkCap = 0;
+    float *tWork = nullptr;           // per layer: split-K partials, then column-sum partials
+    std::vector<size_t> tWoff;        // offset of layer l's region in tWork
+    // in a captured step the weight gradients run beside the chain of input
+    // gradients: layer l's on side stream l % 4, forked after its dZ and
+    // joined before Adam
+    hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> evFork, evJoin;
     std::vector<float *> tZ;          // pre-activations per hidden layer
     std::vector<uint16_t *> tA;       // activations per layer input
 };
@@ -1224,8 +1249,7 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->act[0]);
     (void)hipFree(a->act[1]);
     (void)hipFree(a->tX);
-    (void)hipFree(a->tdZ[0]);
-    (void)hipFree(a->tdZ[1]);
+    for (auto p : a->tdZ) (void)hipFree(p);
     (void)hipFree(a->tZt);
     (void)hipFree(a->tGt);
     (void)hipFree(a->tOut);
@@ -1233,6 +1257,10 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->tWork);
     for (auto p : a->tZ) (void)hipFree(p);
     for (size_t i = 1; i < a->tA.size(); ++i) (void)hipFree(a->tA[i]);   // tA[0] aliases tX
+    for (auto st : a->side)
+        if (st) (void)hipStreamDestroy(st);
+    for (auto ev : a->evFork) (void)hipEventDestroy(ev);
+    for (auto ev : a->evJoin) (void)hipEventDestroy(ev);
     delete a;
 }
 
@@ -2155,8 +2183,8 @@ static int dw_split(int in, int out, int B) {
 static hipError_t ensure_train(AnnState *a, int B) {
     if (B <= a->tB) return hipSuccess;
     (void)hipFree(a->tX);
-    (void)hipFree(a->tdZ[0]);
-    (void)hipFree(a->tdZ[1]);
+    for (auto p : a->tdZ) (void)hipFree(p);
+    a->tdZ.clear();
     (void)hipFree(a->tZt);
     (void)hipFree(a->tGt);
     (void)hipFree(a->tOut);
@@ -2168,22 +2196,38 @@ static hipError_t ensure_train(AnnState *a, int B) {
     a->tZ.clear();
     a->tA.clear();
     a->tB = 0;
-    int wmax = 0;
-    for (int l = 0; l <= a->L; ++l) wmax = std::max(wmax, a->pd[l]);
     hipError_t e;
     if ((e = hipMalloc(&a->tX, 2 * (size_t)B * FPAD)) != hipSuccess) return e;
-    if ((e = hipMalloc(&a->tdZ[0], 2 * (size_t)B * wmax)) != hipSuccess) return e;
-    if ((e = hipMalloc(&a->tdZ[1], 2 * (size_t)B * wmax)) != hipSuccess) return e;
+    for (int l = 0; l < a->L; ++l) {
+        uint16_t *d = nullptr;
+        if ((e = hipMalloc(&d, 2 * (size_t)B * a->pd[l + 1])) != hipSuccess) return e;
+        a->tdZ.push_back(d);
+    }
+    if (!a->side[0]) {
+        for (auto &st : a->side)
+            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
+        a->evFork.assign(a->L, nullptr);
+        a->evJoin.assign(a->L, nullptr);
+        for (int l = 0; l < a->L; ++l)
+            if ((e = hipEventCreateWithFlags(&a->evFork[l], hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&a->evJoin[l], hipEventDisableTiming)) != hipSuccess)
+                return e;
+    }
     if ((e = hipMalloc(&a->tZt, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tGt, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tOut, 4 * (size_t)B * a->K)) != hipSuccess) return e;
     if ((e = hipMalloc(&a->tLoss, 4)) != hipSuccess) return e;
-    // split-K partials of the largest weight gradient, then the column-sum partials
+    // per layer (the layers' weight gradients run at once): split-K
+    // partials, then the column-sum partials of the bias gradient
     size_t work = 0;
-    for (int l = 0; l < a->L; ++l)
-        work = std::max(work, (size_t)dw_split(a->pd[l], a->pd[l + 1], B) * a->pd[l] * a->pd[l + 1]);
-    a->tWorkCap = work + (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * wmax;
-    if ((e = hipMalloc(&a->tWork, 4 * a->tWorkCap)) != hipSuccess) return e;
+    a->tWoff.assign(a->L, 0);
+    for (int l = 0; l < a->L; ++l) {
+        a->tWoff[l] = work;
+        work += (size_t)dw_split(a->pd[l], a->pd[l + 1], B) * a->pd[l] * a->pd[l + 1] +
+                (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * a->pd[l + 1];
+        work = (work + 63) / 64 * 64;
+    }
+    if ((e = hipMalloc(&a->tWork, 4 * work)) != hipSuccess) return e;
     for (int l = 0; l < a->L - 1; ++l) {
         float *z = nullptr;
         if ((e = hipMalloc(&z, 4 * (size_t)B * a->pd[l + 1])) != hipSuccess) return e;
@@ -2228,15 +2272,28 @@ static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t
         const float inv_wsum = ph.out_w ? 1.0f / ph.out_wsum : 1.0f / (float)K;
         hipLaunchKernelGGL(phys_loss_kernel, dim3((B + 255) / 256), dim3(256), 0, s, a->tOut, a->tZt,
                            hrr ? a->tGt : nullptr, ph.out_w, inv_wsum, B, K, nd.mu_y, nd.sd_y, (float)(1.0 / S),
-                           ph.w_mass, hrr ? ph.w_hrr : 0.f, a->tdZ[0], sink);
+                           ph.w_mass, hrr ? ph.w_hrr : 0.f, a->tdZ[L - 1], sink);
     } else {
         hipLaunchKernelGGL(mse_kernel, dim3(std::min(1024, (B * K + 255) / 256)), dim3(256), 0, s, a->tOut,
-                           a->tZt, B * K, a->tdZ[0], sink);
+                           a->tZt, B * K, a->tdZ[L - 1], sink);
     }
-    int cur = 0;
+    // Backward: the chain of input gradients dZ_{l-1} = (dZ_l W_l^T) * GELU'
+    // runs on s.  Under graph capture each layer's weight and bias gradients
+    // (which only read dZ_l and the layer's input) fork onto a side stream as
+    // soon as dZ_l exists and join s before the caller's Adam step, so that
+    // they become parallel branches of the step's graph.  Eager steps keep
+    // everything on s (no per-step event traffic, one stream per context).
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
+    const bool fork = cs == hipStreamCaptureStatusActive;
     for (int l = L - 1; l >= 0; --l) {
         const int in = a->pd[l], out = a->pd[l + 1];
-        const uint16_t *dZ = a->tdZ[cur];
+        const uint16_t *dZ = a->tdZ[l];
+        hipStream_t sd = fork ? a->side[l % 4] : s;
+        if (fork) {
+            if ((e = hipEventRecord(a->evFork[l], s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(sd, a->evFork[l], 0)) != hipSuccess) return e;
+        }
         GemmArgs gw{};
         gw.M = in;
         gw.N = out;
@@ -2247,12 +2304,16 @@ static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t
         gw.ldb = out;
         gw.Cf = a->grad + a->woff[l];
         gw.ldc = out;
-        if ((e = launch_gemm_splitk(gw, dw_split(in, out, B), a->tWork, s)) != hipSuccess) return e;
+        float *work = a->tWork + a->tWoff[l];
+        const int split = dw_split(in, out, B);
+        if ((e = launch_gemm_splitk(gw, split, work, sd)) != hipSuccess) return e;
         const int P = (B + COLSUM_ROWS - 1) / COLSUM_ROWS;
-        hipLaunchKernelGGL(colsum_part_kernel, dim3((out + 255) / 256, P), dim3(256), 0, s, dZ, B, out,
-                           a->tWork + a->tWorkCap - (size_t)P * out);
-        hipLaunchKernelGGL(colsum_final_kernel, dim3((out + 255) / 256), dim3(256), 0, s,
-                           a->tWork + a->tWorkCap - (size_t)P * out, P, out, a->grad + a->boff[l]);
+        float *part = work + (size_t)split * in * out;
+        const int per = out % 8 == 0 ? 8 : 1;
+        hipLaunchKernelGGL(colsum_part_kernel, dim3((out / per + 63) / 64, P), dim3(64), 0, sd, dZ, B, out, part);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((out + 255) / 256), dim3(256), 0, sd, part, P, out,
+                           a->grad + a->boff[l]);
+        if (fork && (e = hipEventRecord(a->evJoin[l], sd)) != hipSuccess) return e;
         if (l > 0) {
             GemmArgs ga{};
             ga.M = B;
@@ -2262,14 +2323,16 @@ static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t
             ga.lda = out;
             ga.B = a->Wb[l];
             ga.ldb = out;
-            ga.Cb = a->tdZ[cur ^ 1];
+            ga.Cb = a->tdZ[l - 1];
             ga.ldcb = in;
             ga.Zin = a->tZ[l - 1];
             ga.ldz = in;
             if ((e = launch_gemm(ga, true, true, EPI_GELU_GRAD, s)) != hipSuccess) return e;
-            cur ^= 1;
         }
     }
+    if (fork)
+        for (int l = 0; l < L; ++l)
+            if ((e = hipStreamWaitEvent(s, a->evJoin[l], 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 

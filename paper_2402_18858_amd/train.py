@@ -347,7 +347,7 @@ def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed
 
 
 def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, batch=4096, lr0=1e-3,
-                           lr1=1e-5, seed=3001, log=print):
+                           lr1=1e-5, seed=3001, log=print, workers=4):
     """The per-species networks of Sec. II.B: one network per mass fraction,
     hidden widths `hidden` with GELU.  Takes the normalisation, envelope and
     checks already fitted on ctx (train_network) and the same training split
@@ -355,9 +355,18 @@ def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, ba
     network whose data loss weights column k alone (a one-hot out_w), so its
     gradient flows from output k only, and keeps its hidden layers and output
     row k.  Every network starts from its own He-uniform draw and sees the
-    same per-epoch row orders.  Installs the K networks in ctx
+    same per-epoch row orders.  With workers > 1 that many networks train at
+    once, each in its own context on its own stream from its own host thread
+    (one network's GEMMs at batch 4,096 fill a fraction of the GPU); the
+    steps then run without graph capture, so that no capture is open while
+    another thread synchronises the device.  Installs the K networks in ctx
     (chemk_ann_create_species) and returns a history dict."""
+    import concurrent.futures as cf
+    import threading
+
     import torch
+
+    from . import chemk
 
     dev = "cuda:0"
     T, p, Y, Yn, hold = data
@@ -375,21 +384,39 @@ def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, ba
     Z = torch.empty((ntr, K), dtype=torch.float32, device=dev)
     ctx.ann_pack(*Td, X, Z)
     del Td
-    hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "hidden": list(hidden), "loss_last": []}
-    nets = []
+    onehot = torch.eye(K, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
+    workers = max(1, min(int(workers), K))
+    hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "hidden": list(hidden),
+            "workers": workers, "loss_last": [0.0] * K}
+    nets = [None] * K
+    lock = threading.Lock()
     t0 = time.time()
-    for k in range(K):
-        ctx.ann_create(dims)
-        ctx.ann_set_norm(*norm)
-        ctx.ann_set_weights(init_params(dims, seed + 7919 * (k + 1)))
-        ctx.ann_reset_optimizer()
-        w = torch.zeros(K, dtype=torch.float32, device=dev)
-        w[k] = 1.0
-        el, _ = ctx.ann_train(X, Z, epochs, batch=batch, lr0=lr0, lr1=lr1, seed=seed, out_w=w)
-        nets.append(species_slice(ctx.ann_get_weights(), dims, k))
-        hist["loss_last"].append(float(el[-1]))
-        log(f"species {k + 1}/{K}: loss {el[0]:.3e} -> {el[-1]:.3e} ({time.time() - t0:.0f} s)")
+
+    def run(w):
+        c = ctx if workers == 1 else chemk.Context(ctx.mech)
+        st = None if workers == 1 else torch.cuda.Stream()
+        for k in range(w, K, workers):
+            c.ann_create(dims)
+            c.ann_set_norm(*norm)
+            c.ann_set_weights(init_params(dims, seed + 7919 * (k + 1)))
+            c.ann_reset_optimizer()
+            el, _ = c.ann_train(X, Z, epochs, batch=batch, lr0=lr0, lr1=lr1, seed=seed, out_w=onehot[k],
+                                use_graph=workers == 1, stream=st)
+            v = species_slice(c.ann_get_weights(), dims, k)
+            with lock:
+                nets[k] = v
+                hist["loss_last"][k] = float(el[-1])
+                done = sum(x is not None for x in nets)
+            log(f"species {k + 1}/{K}: loss {el[0]:.3e} -> {el[-1]:.3e} ({done} done, {time.time() - t0:.0f} s)")
+
+    if workers == 1:
+        run(0)
+    else:
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            for f in [ex.submit(run, w) for w in range(workers)]:
+                f.result()
+    torch.cuda.synchronize()
     hist["train_s"] = time.time() - t0
     hist["steps"] = (ntr // batch) * epochs * K
     ctx.ann_create_species([K + 2, *hidden, 1])
@@ -533,6 +560,8 @@ def main(argv=None):
     ap.add_argument("--species-hidden", default="1600,800,400")
     ap.add_argument("--species-epochs", type=int, default=20)
     ap.add_argument("--species-out", default=None, help="where to save the per-species networks")
+    ap.add_argument("--species-workers", type=int, default=4,
+                    help="per-species networks trained at once (contexts on their own streams)")
     ap.add_argument("--recipe", default="cfg4", choices=["cfg4", "hfrd"],
                     help="cfg4: noisy trajectories + mixing lines + flame-block states; "
                          "hfrd: the paper's perturbation recipe (generate_pairs_hfrd)")
@@ -577,7 +606,7 @@ def main(argv=None):
     if a.species_nets:
         hidden = tuple(int(v) for v in a.species_hidden.split(","))
         hs = train_species_networks(ctx, (T, p, Y, Yn, hold), a.dt, hidden=hidden, epochs=a.species_epochs,
-                                    batch=a.batch, log=log)
+                                    batch=a.batch, log=log, workers=a.species_workers)
         es = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold], hrr_scale=hrr_unit)
         torch.cuda.synchronize()
         dims1 = [mech.K + 2, *hidden, 1]
@@ -585,6 +614,7 @@ def main(argv=None):
         out_s = a.species_out or a.out.replace(".npz", "_species.npz")
         save(ctx, out_s)
         rep["species"] = {"dims": dims1, "networks": mech.K, "epochs": a.species_epochs,
+                          "workers": hs["workers"],
                           "train_s": hs["train_s"], "train_tflops_wall": fls / hs["train_s"] / 1e12,
                           "loss_last": hs["loss_last"],
                           "holdout_rms_norm_all": es["rms_norm_all"],

@@ -350,3 +350,36 @@ def test_species_networks_refuse_training_and_bad_shapes():
     for bad in ([K + 2, 1], [K + 2, 64, 2], [K + 1, 64, 1]):
         with pytest.raises(chemk.ChemkError):
             ctx.ann_create_species(bad)
+
+
+def test_species_training_on_four_streams_equals_one_at_a_time():
+    """train_species_networks with four networks training at once (own
+    contexts, streams and host threads, eager steps) gives every network
+    bitwise the weights of the one-at-a-time run (graph-replayed steps): the
+    steps are deterministic and the networks independent."""
+    import torch
+    from paper_2402_18858_amd import chemk, train
+    mech = sm.mech_medium()
+    K = mech.K
+    n = 4096 + 512
+    T, p, Y = _states(mech, n, 66)
+    rng = np.random.default_rng(67)
+    Yn = np.clip(Y + rng.normal(0, 1e-4, Y.shape) * Y, 0.0, None)
+    Yn /= Yn.sum(1, keepdims=True)
+    hold = np.arange(n - 512, n)
+    outs = []
+    for workers in (1, 4):
+        ctx = chemk.Context(mech)
+        ctx.ann_create([K + 2, 64, K])
+        # the same normalisation for both runs, from the host (the device fit
+        # sums with atomics, in no fixed order)
+        mu_x, sd_x = oann.norm_stats(oann.raw_features(T[:n - 512], p[:n - 512], Y[:n - 512]))
+        d = (Yn - Y)[:n - 512]
+        ctx.ann_set_norm(mu_x, sd_x, d.mean(0), np.maximum(d.std(0), 1e-12), 5e-7)
+        h = train.train_species_networks(ctx, (T, p, Y, Yn, hold), 5e-7, hidden=(96, 40), epochs=2, batch=1024,
+                                         log=lambda m: None, workers=workers)
+        torch.cuda.synchronize()
+        outs.append(ctx.ann_get_weights())
+        announce(f"species training, {workers} worker(s): {h['train_s']:.2f} s, last losses "
+                 f"{min(h['loss_last']):.3e} .. {max(h['loss_last']):.3e}")
+    assert np.array_equal(outs[0], outs[1])
