@@ -296,10 +296,15 @@ int chemk_ann_create(chemk_ctx *ctx, const int32_t *dims, int32_t n_layers);
  * K-output network would.  Parameter vector: the K networks' vectors (each in
  * the layout above with dims[L] = 1) one after the other, species order.  The
  * K networks run as one product for the first layer, one grouped product per
- * hidden layer and one block-diagonal product for the outputs.  Not
- * trainable in place (chemk_ann_train*, chemk_ann_reset_optimizer return
- * CHEMK_E_UNSUPPORTED): train network k as a K-output network with a one-hot
- * out_w (chemk_ann_train_step) and keep its output row k.                   */
+ * hidden layer, and the output layer fused into the last hidden layer (one
+ * block-diagonal product with one hidden layer).  Trainable in place:
+ * chemk_ann_train_step and chemk_ann_train then take one step of all K
+ * networks at once (grouped products), network k's loss the mean squared
+ * error of its own output column of Z (Eq. 8 for one species); the batch
+ * loss reported is the mean over the networks.  The physics losses and
+ * out_w couple the species and are refused (CHEMK_E_UNSUPPORTED).  A network
+ * can also be trained alone as a K-output network with a one-hot out_w and
+ * its output row k kept.                                                     */
 int chemk_ann_create_species(chemk_ctx *ctx, const int32_t *dims, int32_t n_layers);
 int chemk_ann_param_count(chemk_ctx *ctx, int64_t *count);
 int chemk_ann_set_weights(chemk_ctx *ctx, const float *params, int64_t count);
@@ -450,6 +455,12 @@ typedef struct {
     const float *G;          /* [n, K] heat-release weights (w_hrr > 0), device  */
     const float *out_w;      /* [K] per-output weights of the data term
                                 (chemk_ann_train_step), device; NULL = all 1     */
+    int32_t epoch0;          /* this call runs epochs [epoch0, epoch0 + epochs)   */
+    int32_t epochs_total;    /* of a schedule over this many epochs (0: epoch0 +
+                                epochs): the learning rate, the row orders and
+                                the Adam step count continue as if one call ran
+                                them all; epoch_loss / hold_loss get this call's
+                                epochs                                           */
 } chemk_train_opts;
 int chemk_ann_train(chemk_ctx *ctx, int64_t n, const uint16_t *X, const float *Z,
                     const uint16_t *X_hold, const float *Z_hold, int64_t n_hold,

@@ -57,7 +57,8 @@ class AnnChecks(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr0", C.c_float), ("lr1", C.c_float),
                 ("seed", C.c_uint64), ("use_graph", C.c_int32), ("w_mass", C.c_float),
-                ("w_hrr", C.c_float), ("G", C.c_void_p), ("out_w", C.c_void_p)]
+                ("w_hrr", C.c_float), ("G", C.c_void_p), ("out_w", C.c_void_p), ("epoch0", C.c_int32),
+                ("epochs_total", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -406,10 +407,12 @@ class Context:
         return out.value
 
     def ann_train(self, X, Z, epochs, batch=4096, lr0=1e-3, lr1=1e-5, seed=3001, X_hold=None,
-                  Z_hold=None, use_graph=True, stream=None, G=None, w_mass=0.0, w_hrr=0.0, out_w=None):
-        """Returns (epoch_loss, hold_loss) as host arrays [epochs]."""
+                  Z_hold=None, use_graph=True, stream=None, G=None, w_mass=0.0, w_hrr=0.0, out_w=None,
+                  epoch0=0, epochs_total=0):
+        """Returns (epoch_loss, hold_loss) as host arrays [epochs] (this call's
+        epochs: [epoch0, epoch0 + epochs) of a schedule over epochs_total)."""
         o = TrainOpts(int(batch), int(epochs), float(lr0), float(lr1), int(seed), int(bool(use_graph)),
-                      float(w_mass), float(w_hrr), _ptr(G), _ptr(out_w))
+                      float(w_mass), float(w_hrr), _ptr(G), _ptr(out_w), int(epoch0), int(epochs_total))
         el = np.zeros(epochs, np.float32)
         hl = np.zeros(epochs, np.float32)
         nh = 0 if X_hold is None else X_hold.shape[0]

@@ -616,11 +616,14 @@ struct LossSink {
 };
 
 // MSE on z-scored outputs: loss = mean((out - tgt)^2); dOut = bf16(2 (out - tgt) / count)
+// gscale = 1: the gradient of the mean over all count values; gscale = G for
+// G networks side by side, each with the mean over its own count / G values
+// (the loss reported stays the mean over all).
 __global__ void mse_kernel(const float *__restrict__ out, const float *__restrict__ tgt, int count,
-                           uint16_t *dout, LossSink sink) {
+                           uint16_t *dout, LossSink sink, float gscale = 1.0f) {
     __shared__ float red[256];
     float s = 0.f;
-    const float sc = 2.0f / (float)count;
+    const float sc = 2.0f * gscale / (float)count;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
         const float d = out[i] - tgt[i];
         s += d * d;
@@ -822,10 +825,12 @@ __global__ void step_end_kernel(long long *ctl) {
     if (threadIdx.x == 0) ctl[0] += 1;
 }
 
-__global__ void ctl_init_kernel(long long *ctl, long long before) {
+// ctl[0]: the step within the schedule (starting at step0); ctl[1] + ctl[0]
+// + 1: Adam's step count (before: the context's steps so far)
+__global__ void ctl_init_kernel(long long *ctl, long long step0, long long before) {
     if (threadIdx.x == 0) {
-        ctl[0] = 0;
-        ctl[1] = before;
+        ctl[0] = step0;
+        ctl[1] = before - step0;
     }
 }
 
@@ -868,13 +873,26 @@ __global__ void colsum_part_kernel(const uint16_t *__restrict__ dZ, int B, int N
     part[(size_t)blockIdx.y * N + o] = s;
 }
 
-__global__ void colsum_final_kernel(const float *__restrict__ part, int P, int N, float *db) {
+// db[(o / w) gstride + o % w] = sum over the row partials of column o: w = N
+// for one network, w = the width of one of the networks side by side
+__global__ void colsum_final_kernel(const float *__restrict__ part, int P, int N, float *db, int w = 0,
+                                    size_t gstride = 0) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= N) return;
     float s = 0.f;
 #pragma unroll 16
     for (int y = 0; y < P; ++y) s += part[(size_t)y * N + o];
-    db[o] = s;
+    if (w > 0) db[(size_t)(o / w) * gstride + o % w] = s;
+    else db[o] = s;
+}
+
+// grad[g gstride + r] = D[(g n + r) G + g], r < n: the diagonal blocks of the
+// dense output-layer weight gradient of G networks side by side
+__global__ void diag_blocks_kernel(const float *__restrict__ D, int n, int G, float *grad, size_t gstride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * G) return;
+    const int g = i / n, r = i - g * n;
+    grad[(size_t)g * gstride + r] = D[((size_t)g * n + r) * G + g];
 }
 
 // Adam (Kingma & Ba 2015, Alg. 1) on the FP32 master parameters.
@@ -911,6 +929,20 @@ __global__ void species_out_kernel(const float *__restrict__ P, int S, int G, in
     float s = 0.f;
     for (int k = 0; k < S; ++k) s += p[k];
     out[i] = s + b[g];
+}
+
+// Network g = blockIdx.y of an ensemble, element i = r out + c of its layer
+// block [in x out] in the master: v = bf16(W); Wt[g wtG + c in + r] = v and,
+// when Wb is given, Wb[g wbG + r wbLd + c] = v.
+__global__ void cast_group_kernel(const float *__restrict__ M, size_t gstride, int in, int out, uint16_t *Wt,
+                                  size_t wtG, uint16_t *Wb, size_t wbG, int wbLd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= in * out) return;
+    const size_t g = blockIdx.y;
+    const int r = i / out, c = i - r * out;
+    const uint16_t v = f2bf(M[g * gstride + i]);
+    Wt[g * wtG + (size_t)c * in + r] = v;
+    if (Wb) Wb[g * wbG + (size_t)r * wbLd + c] = v;
 }
 
 __global__ void cast_layer_kernel(const float *__restrict__ Wm, int in, int out, uint16_t *Wt,
@@ -1272,12 +1304,12 @@ static hipError_t refresh_ensemble(AnnState *a, hipStream_t s) {
     const int G = a->G, L = a->L;
     for (int l = 0; l < L; ++l) {
         const int in = a->pd[l], out = a->pd[l + 1];
-        for (int g = 0; g < G; ++g) {
-            uint16_t *dst = l < L - 1 ? a->Wt[l] + (size_t)g * out * in
-                                      : a->Wt[l] + (size_t)g * G * in + (size_t)g * in;
-            hipLaunchKernelGGL(cast_layer_kernel, dim3((in * out + 255) / 256), dim3(256), 0, s,
-                               a->master + g * a->gstride + a->woff[l], in, out, dst, (uint16_t *)nullptr);
-        }
+        const bool last = l == L - 1;   // out = 1: block-diagonal placement
+        const size_t wtG = last ? (size_t)(G + 1) * in : (size_t)in * out;
+        const size_t wbG = last ? (size_t)in * G + 1 : (size_t)in * out;
+        hipLaunchKernelGGL(cast_group_kernel, dim3((in * out + 255) / 256, G), dim3(256), 0, s,
+                           a->master + a->woff[l], a->gstride, in, out, a->Wt[l], wtG, a->Wb[l], wbG,
+                           last ? G : out);
         hipError_t e = hipMemcpy2DAsync(a->eB[l], 4 * (size_t)out, a->master + a->boff[l], 4 * a->gstride,
                                         4 * (size_t)out, G, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
@@ -1679,11 +1711,12 @@ static int out_weight_sum(chemk_ctx *c, const AnnState *a, const float *w, float
     return CHEMK_OK;
 }
 
-// Training runs on single networks only.
-static int need_single(AnnState *a) {
-    if (a->G > 1)
-        ANN_FAIL(CHEMK_E_UNSUPPORTED, "per-species networks are not trained in place: train each as a "
-                                      "K-output network with a one-hot out_w and install them together");
+// Per-species networks train on the data loss alone (each network's own
+// output column): no physics terms, no per-output weights.
+static int need_plain_loss(AnnState *a, float w_mass, float w_hrr, const float *G, const float *out_w) {
+    if (a->G > 1 && (w_mass != 0.f || w_hrr != 0.f || G || out_w))
+        ANN_FAIL(CHEMK_E_UNSUPPORTED, "per-species networks train on the data loss alone "
+                                      "(no w_mass, w_hrr, G or out_w)");
     return CHEMK_OK;
 }
 
@@ -1744,13 +1777,13 @@ static int create_net(chemk_ctx *c, const int32_t *dims, int32_t L, int G) {
     ctx_ann(c) = a;
     ANN_TRY(hipMalloc(&a->master, 4 * a->nparam));
     ANN_TRY(hipMemset(a->master, 0, 4 * a->nparam));
+    ANN_TRY(hipMalloc(&a->grad, 4 * a->nparam));
+    ANN_TRY(hipMalloc(&a->m1, 4 * a->nparam));
+    ANN_TRY(hipMalloc(&a->m2, 4 * a->nparam));
+    ANN_TRY(hipMemset(a->grad, 0, 4 * a->nparam));
+    ANN_TRY(hipMemset(a->m1, 0, 4 * a->nparam));
+    ANN_TRY(hipMemset(a->m2, 0, 4 * a->nparam));
     if (G == 1) {
-        ANN_TRY(hipMalloc(&a->grad, 4 * off));
-        ANN_TRY(hipMalloc(&a->m1, 4 * off));
-        ANN_TRY(hipMalloc(&a->m2, 4 * off));
-        ANN_TRY(hipMemset(a->grad, 0, 4 * off));
-        ANN_TRY(hipMemset(a->m1, 0, 4 * off));
-        ANN_TRY(hipMemset(a->m2, 0, 4 * off));
         for (int l = 0; l < L; ++l) {
             uint16_t *wt = nullptr, *wb = nullptr;
             ANN_TRY(hipMalloc(&wt, 2 * (size_t)a->pd[l] * a->pd[l + 1]));
@@ -1761,15 +1794,23 @@ static int create_net(chemk_ctx *c, const int32_t *dims, int32_t L, int G) {
     } else {
         // product operands of the ensemble (see ens_forward): layer 0 one
         // [G pd1 x FPAD] matrix, hidden layers G blocks [pd[l+1] x pd[l]],
-        // the output layer block diagonal [G x G pd[L-1]]; biases [G pd[l+1]]
+        // the output layer block diagonal [G x G pd[L-1]]; biases [G pd[l+1]].
+        // For the input gradients of training (ens_fwd_bwd), the untransposed
+        // copies: hidden layers G blocks [pd[l] x pd[l+1]], the output layer
+        // block diagonal [G pd[L-1] x G]; none for layer 0.
         for (int l = 0; l < L; ++l) {
             const size_t n = l < L - 1 ? (size_t)G * a->pd[l + 1] * a->pd[l] : (size_t)G * G * a->pd[l];
-            uint16_t *wt = nullptr;
+            uint16_t *wt = nullptr, *wb = nullptr;
             float *b = nullptr;
             ANN_TRY(hipMalloc(&wt, 2 * n));
             ANN_TRY(hipMemset(wt, 0, 2 * n));
+            if (l > 0) {
+                ANN_TRY(hipMalloc(&wb, 2 * n));
+                ANN_TRY(hipMemset(wb, 0, 2 * n));
+            }
             ANN_TRY(hipMalloc(&b, 4 * (size_t)G * a->pd[l + 1]));
             a->Wt.push_back(wt);
+            a->Wb.push_back(wb);
             a->eB.push_back(b);
         }
         if (L >= 3) ANN_TRY(hipMalloc(&a->eW, 4 * (size_t)G * a->pd[L - 1]));
@@ -2198,9 +2239,12 @@ static hipError_t ensure_train(AnnState *a, int B) {
     a->tB = 0;
     hipError_t e;
     if ((e = hipMalloc(&a->tX, 2 * (size_t)B * FPAD)) != hipSuccess) return e;
+    // widths: G networks side by side (G = 1: one network); pd[L] = 1 per
+    // network of an ensemble, K for one network
+    const size_t G = a->G;
     for (int l = 0; l < a->L; ++l) {
         uint16_t *d = nullptr;
-        if ((e = hipMalloc(&d, 2 * (size_t)B * a->pd[l + 1])) != hipSuccess) return e;
+        if ((e = hipMalloc(&d, 2 * (size_t)B * G * a->pd[l + 1])) != hipSuccess) return e;
         a->tdZ.push_back(d);
     }
     if (!a->side[0]) {
@@ -2221,22 +2265,25 @@ static hipError_t ensure_train(AnnState *a, int B) {
     // partials, then the column-sum partials of the bias gradient
     size_t work = 0;
     a->tWoff.assign(a->L, 0);
+    // (an ensemble: no split K; the output layer's dense [G pd[L-1] x G]
+    // product, whose diagonal blocks are the networks' gradients)
     for (int l = 0; l < a->L; ++l) {
         a->tWoff[l] = work;
-        work += (size_t)dw_split(a->pd[l], a->pd[l + 1], B) * a->pd[l] * a->pd[l + 1] +
-                (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * a->pd[l + 1];
+        const size_t cs = (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * G * a->pd[l + 1];
+        if (G == 1) work += (size_t)dw_split(a->pd[l], a->pd[l + 1], B) * a->pd[l] * a->pd[l + 1] + cs;
+        else work += (l == a->L - 1 ? G * a->pd[l] * G : 0) + cs;
         work = (work + 63) / 64 * 64;
     }
     if ((e = hipMalloc(&a->tWork, 4 * work)) != hipSuccess) return e;
     for (int l = 0; l < a->L - 1; ++l) {
         float *z = nullptr;
-        if ((e = hipMalloc(&z, 4 * (size_t)B * a->pd[l + 1])) != hipSuccess) return e;
+        if ((e = hipMalloc(&z, 4 * (size_t)B * G * a->pd[l + 1])) != hipSuccess) return e;
         a->tZ.push_back(z);
     }
     a->tA.push_back(nullptr);   // layer-0 input is tX
     for (int l = 1; l < a->L; ++l) {
         uint16_t *ap = nullptr;
-        if ((e = hipMalloc(&ap, 2 * (size_t)B * a->pd[l])) != hipSuccess) return e;
+        if ((e = hipMalloc(&ap, 2 * (size_t)B * G * a->pd[l])) != hipSuccess) return e;
         a->tA.push_back(ap);
     }
     a->tB = B;
@@ -2255,8 +2302,139 @@ struct PhysLoss {
     float out_wsum;       // their sum
 };
 
+// One training step of the G = K per-species networks side by side on rows
+// idx[0..B-1] of (X, Z): network k's loss is the mean squared error of its
+// own output, column k (the data loss of Eq. 8 for one species).  The
+// products are those of ens_forward (first layer one product, hidden layers
+// grouped, the output layer block diagonal, without the fused epilogue, since
+// the last hidden activations are kept), with pre-activations and activations
+// saved; backward: weight gradients of the hidden layers and of the first
+// layer (whose input all networks share) as grouped products straight into
+// each network's slice of the gradient, the output layer's as one dense
+// product whose diagonal blocks are kept, input gradients grouped (dense for
+// the output layer), bias gradients as column sums scattered to the slices.
+static hipError_t ens_fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t *X, const float *Z,
+                              LossSink sink, hipStream_t s) {
+    const int K = a->K, L = a->L, G = a->G;
+    const size_t gs = a->gstride;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(B), dim3(64), 0, s, idx, B, X, FPAD, Z, K, a->tX, a->tZt);
+    a->tA[0] = a->tX;
+    hipError_t e;
+    for (int l = 0; l < L; ++l) {
+        const bool last = l == L - 1;
+        GemmArgs g{};
+        g.M = B;
+        g.B = a->Wt[l];
+        g.bias = a->eB[l];
+        g.A = a->tA[l];
+        int groups = 1, epi = EPI_BIAS_GELU;
+        if (l == 0) {
+            g.N = G * a->pd[1];
+            g.K = FPAD;
+            g.lda = FPAD;
+            g.ldb = FPAD;
+        } else if (!last) {
+            g.N = a->pd[l + 1];
+            g.K = a->pd[l];
+            g.lda = G * a->pd[l];
+            g.ldb = a->pd[l];
+            g.gsA = a->pd[l];
+            g.gsB = (long long)a->pd[l] * a->pd[l + 1];
+            g.gsC = a->pd[l + 1];
+            g.gsCf = a->pd[l + 1];
+            groups = G;
+        } else {
+            g.N = G;
+            g.K = G * a->pd[l];
+            g.lda = G * a->pd[l];
+            g.ldb = G * a->pd[l];
+            epi = EPI_BIAS;
+        }
+        if (last) {
+            g.Cf = a->tOut;
+            g.ldc = G;
+        } else {
+            g.Cf = a->tZ[l];
+            g.ldc = G * a->pd[l + 1];
+            g.Cb = a->tA[l + 1];
+            g.ldcb = G * a->pd[l + 1];
+        }
+        if ((e = launch_gemm(g, true, true, epi, s, groups)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(mse_kernel, dim3(std::min(1024, (B * K + 255) / 256)), dim3(256), 0, s, a->tOut, a->tZt,
+                       B * K, a->tdZ[L - 1], sink, (float)G);
+    const int P = (B + COLSUM_ROWS - 1) / COLSUM_ROWS;
+    for (int l = L - 1; l >= 0; --l) {
+        const bool last = l == L - 1;
+        const int in = a->pd[l], out = a->pd[l + 1];   // one network's widths (out = 1 for the output layer)
+        const int nall = G * out;                       // columns of dZ_l
+        const uint16_t *dZ = a->tdZ[l];
+        float *work = a->tWork + a->tWoff[l];
+        GemmArgs gw{};
+        gw.K = B;
+        gw.A = a->tA[l];
+        gw.B = dZ;
+        if (last) {
+            gw.M = G * in;
+            gw.N = G;
+            gw.lda = G * in;
+            gw.ldb = G;
+            gw.Cf = work;
+            gw.ldc = G;
+            if ((e = launch_gemm(gw, false, false, EPI_STORE_F32, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(diag_blocks_kernel, dim3((in * G + 255) / 256), dim3(256), 0, s, work, in, G,
+                               a->grad + a->woff[l], gs);
+        } else {
+            gw.M = in;
+            gw.N = out;
+            gw.lda = l == 0 ? FPAD : G * in;
+            gw.gsA = l == 0 ? 0 : in;
+            gw.ldb = nall;
+            gw.gsB = out;
+            gw.Cf = a->grad + a->woff[l];
+            gw.ldc = out;
+            gw.gsCf = (long long)gs;
+            if ((e = launch_gemm(gw, false, false, EPI_STORE_F32, s, G)) != hipSuccess) return e;
+        }
+        float *part = last ? work + (size_t)G * in * G : work;
+        const int per = nall % 8 == 0 ? 8 : 1;
+        hipLaunchKernelGGL(colsum_part_kernel, dim3((nall / per + 63) / 64, P), dim3(64), 0, s, dZ, B, nall, part);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((nall + 255) / 256), dim3(256), 0, s, part, P, nall,
+                           a->grad + a->boff[l], out, gs);
+        if (l > 0) {
+            GemmArgs ga{};
+            ga.M = B;
+            ga.A = dZ;
+            ga.B = a->Wb[l];
+            ga.Cb = a->tdZ[l - 1];
+            ga.ldcb = G * in;
+            ga.Zin = a->tZ[l - 1];
+            ga.ldz = G * in;
+            int groups = 1;
+            if (last) {
+                ga.N = G * in;
+                ga.K = G;
+                ga.lda = G;
+                ga.ldb = G;
+            } else {
+                ga.N = in;
+                ga.K = out;
+                ga.lda = nall;
+                ga.gsA = out;
+                ga.ldb = out;
+                ga.gsB = (long long)in * out;
+                ga.gsC = in;
+                groups = G;
+            }
+            if ((e = launch_gemm(ga, true, true, EPI_GELU_GRAD, s, groups)) != hipSuccess) return e;
+        }
+    }
+    return hipGetLastError();
+}
+
 static hipError_t fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint16_t *X, const float *Z,
                           LossSink sink, hipStream_t s, PhysLoss ph = PhysLoss{nullptr, 0.f, 0.f, nullptr, 0.f}) {
+    if (a->G > 1) return ens_fwd_bwd(a, idx, B, X, Z, sink, s);
     const int K = a->K, L = a->L;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(B), dim3(64), 0, s, idx, B, X, FPAD, Z, K, a->tX, a->tZt);
     const bool hrr = ph.w_hrr != 0.f && ph.G;
@@ -2343,7 +2521,7 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
-    if (int r = need_single(a)) return r;
+    if (int r = need_plain_loss(a, w_mass, w_hrr, G, out_w)) return r;
     if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
     if (!idx || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null array");
     if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
@@ -2361,17 +2539,20 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
     ANN_TRY(fwd_bwd(a, idx, B, X, Z, LossSink{a->tLoss, nullptr, 1, 1.0f}, s,
                     PhysLoss{G, w_mass, w_hrr, out_w, wsum}));
     if (loss) ANN_TRY(hipMemcpyAsync(loss, a->tLoss, 4, hipMemcpyDeviceToDevice, s));
-    if (grads) {
+    if (grads) {   // the public layout: per network, per layer W then b
         size_t p = 0;
-        for (int l = 0; l < L; ++l) {
-            const size_t w = (size_t)a->dims[l] * a->dims[l + 1];
-            ANN_TRY(hipMemcpy2DAsync(grads + p, 4 * (size_t)a->dims[l + 1], a->grad + a->woff[l],
-                                     4 * (size_t)a->pd[l + 1], 4 * (size_t)a->dims[l + 1], a->dims[l],
-                                     hipMemcpyDeviceToDevice, s));
-            p += w;
-            ANN_TRY(hipMemcpyAsync(grads + p, a->grad + a->boff[l], 4 * a->dims[l + 1],
-                                   hipMemcpyDeviceToDevice, s));
-            p += a->dims[l + 1];
+        for (int gi = 0; gi < a->G; ++gi) {
+            const float *gg = a->grad + gi * a->gstride;
+            for (int l = 0; l < L; ++l) {
+                const size_t w = (size_t)a->dims[l] * a->dims[l + 1];
+                ANN_TRY(hipMemcpy2DAsync(grads + p, 4 * (size_t)a->dims[l + 1], gg + a->woff[l],
+                                         4 * (size_t)a->pd[l + 1], 4 * (size_t)a->dims[l + 1], a->dims[l],
+                                         hipMemcpyDeviceToDevice, s));
+                p += w;
+                ANN_TRY(hipMemcpyAsync(grads + p, gg + a->boff[l], 4 * a->dims[l + 1], hipMemcpyDeviceToDevice,
+                                       s));
+                p += a->dims[l + 1];
+            }
         }
     }
     if (update) {
@@ -2391,8 +2572,9 @@ extern "C" int chemk_ann_train_step(chemk_ctx *c, const int32_t *idx, int32_t B,
 // the mean squared error added to *acc.
 static hipError_t holdout_loss(AnnState *a, int64_t n, const uint16_t *X, const float *Z, float *acc,
                                hipStream_t s) {
-    for (int64_t c0 = 0; c0 < n; c0 += CHUNK) {
-        const int rows = (int)std::min<int64_t>(CHUNK, n - c0);
+    const int chunk = chunk_rows(a);   // the inference buffers hold this many rows
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int rows = (int)std::min<int64_t>(chunk, n - c0);
         hipError_t e = mlp_forward(a, X + c0 * FPAD, rows, a->out, a->act[0], a->act[1], s);
         if (e != hipSuccess) return e;
         const long long cnt = (long long)rows * a->K;
@@ -2409,13 +2591,17 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
-    if (int r = need_single(a)) return r;
     if (!a->have_w) ANN_FAIL(CHEMK_E_STATE, "weights not set");
     if (!o || !X || !Z) ANN_FAIL(CHEMK_E_ARG, "null argument");
+    if (int r = need_plain_loss(a, o->w_mass, o->w_hrr, o->G, o->out_w)) return r;
     const int B = o->batch;
     if (B < 64 || B % 64 != 0 || B > (1 << 20)) ANN_FAIL(CHEMK_E_ARG, "batch %d must be a multiple of 64", B);
     if (n < B || n > (1ll << 31) - 1) ANN_FAIL(CHEMK_E_ARG, "need batch <= n < 2^31 training rows");
     if (o->epochs < 1 || o->epochs > 100000) ANN_FAIL(CHEMK_E_ARG, "epochs=%d outside [1, 1e5]", o->epochs);
+    if (o->epoch0 < 0 || o->epoch0 > 100000 ||
+        (o->epochs_total != 0 && o->epochs_total < o->epoch0 + o->epochs) || o->epochs_total > 200000)
+        ANN_FAIL(CHEMK_E_ARG, "epoch0=%d, epochs=%d and epochs_total=%d do not form a schedule", o->epoch0,
+                 o->epochs, o->epochs_total);
     if (!(o->lr0 >= 0) || !(o->lr1 >= 0) || !std::isfinite(o->lr0) || !std::isfinite(o->lr1))
         ANN_FAIL(CHEMK_E_ARG, "bad learning rates");
     if (n_hold < 0 || n_hold > (1ll << 31) - 1 || (n_hold > 0 && (!X_hold || !Z_hold)))
@@ -2430,12 +2616,16 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
         ANN_FAIL(CHEMK_E_ARG, "X must be 16-byte aligned");
     hipStream_t s0 = (hipStream_t)stream;
     const int spe = (int)(n / B);
-    const long long total = (long long)spe * o->epochs;
+    // this call runs epochs [epoch0, epoch0 + epochs) of a schedule over
+    // epochs_total epochs (0: over this call's epochs)
+    const long long run = (long long)spe * o->epochs;
+    const long long step0 = (long long)spe * o->epoch0;
+    const long long total = o->epochs_total > 0 ? (long long)spe * o->epochs_total : step0 + run;
     int half = 1;
     while ((1ll << (2 * half)) < n) ++half;
     // buffers first: nothing is allocated inside the capture
     ANN_TRY(ensure_train(a, B));
-    if (n_hold > 0) ANN_TRY(ensure_infer(a, std::min<int64_t>(n_hold, CHUNK)));
+    if (n_hold > 0) ANN_TRY(ensure_infer(a, std::min<int64_t>(n_hold, chunk_rows(a))));
     long long *ctl = nullptr;
     int *idx = nullptr;
     float *eloss = nullptr, *hloss = nullptr;
@@ -2462,7 +2652,7 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
             if ((e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking))) break;
             s = own;
         }
-        hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(64), 0, s, ctl, (long long)a->step);
+        hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(64), 0, s, ctl, step0, (long long)a->step);
         hipLaunchKernelGGL(zero_f32_kernel, dim3((o->epochs + 255) / 256), dim3(256), 0, s, eloss, o->epochs);
         hipLaunchKernelGGL(zero_f32_kernel, dim3((o->epochs + 255) / 256), dim3(256), 0, s, hloss, o->epochs);
         if ((e = hipGetLastError())) break;
@@ -2470,7 +2660,8 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
         auto one_step = [&](hipStream_t st) -> hipError_t {
             hipLaunchKernelGGL(batch_index_kernel, dim3((B + 255) / 256), dim3(256), 0, st, ctl, B, spe,
                                (unsigned int)n, half, (unsigned long long)o->seed, idx);
-            hipError_t ee = fwd_bwd(a, idx, B, X, Z, LossSink{eloss, ctl, spe, 1.0f / (float)spe}, st,
+            // the sink indexes epochs by ctl[0] / spe: shifted to this call's first
+            hipError_t ee = fwd_bwd(a, idx, B, X, Z, LossSink{eloss - o->epoch0, ctl, spe, 1.0f / (float)spe}, st,
                                     PhysLoss{o->G, o->w_mass, o->w_hrr, o->out_w, owsum});
             if (ee != hipSuccess) return ee;
             hipLaunchKernelGGL(adam_sched_kernel, dim3(gadam), dim3(256), 0, st, a->master, a->grad, a->m1,
@@ -2500,7 +2691,7 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
     } while (false);
     release();
     ANN_TRY(e);
-    a->step += total;
+    a->step += run;
     if (epoch_loss) std::memcpy(epoch_loss, he.data(), 4 * (size_t)o->epochs);
     if (hold_loss) std::memcpy(hold_loss, hh.data(), 4 * (size_t)o->epochs);
     return CHEMK_OK;
@@ -2552,7 +2743,6 @@ extern "C" int chemk_ann_reset_optimizer(chemk_ctx *c) {
     ctx_set_error("");
     AnnState *a;
     if (int r = need_ann(c, &a)) return r;
-    if (int r = need_single(a)) return r;
     ANN_TRY(hipMemset(a->m1, 0, 4 * a->nparam));
     ANN_TRY(hipMemset(a->m2, 0, 4 * a->nparam));
     a->step = 0;

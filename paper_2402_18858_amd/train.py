@@ -347,7 +347,7 @@ def train_network(ctx, data, dt, epochs=50, batch=4096, lr0=1e-3, lr1=1e-5, seed
 
 
 def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, batch=4096, lr0=1e-3,
-                           lr1=1e-5, seed=3001, log=print, workers=4):
+                           lr1=1e-5, seed=3001, log=print, workers=0):
     """The per-species networks of Sec. II.B: one network per mass fraction,
     hidden widths `hidden` with GELU.  Takes the normalisation, envelope and
     checks already fitted on ctx (train_network) and the same training split
@@ -355,12 +355,16 @@ def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, ba
     network whose data loss weights column k alone (a one-hot out_w), so its
     gradient flows from output k only, and keeps its hidden layers and output
     row k.  Every network starts from its own He-uniform draw and sees the
-    same per-epoch row orders.  With workers > 1 that many networks train at
-    once, each in its own context on its own stream from its own host thread
-    (one network's GEMMs at batch 4,096 fill a fraction of the GPU); the
-    steps then run without graph capture, so that no capture is open while
-    another thread synchronises the device.  Installs the K networks in ctx
-    (chemk_ann_create_species) and returns a history dict."""
+    same per-epoch row orders.
+
+    workers = 0: all K networks train together in ctx (chemk_ann_create_species
+    and chemk_ann_train: one step of all networks as grouped GEMMs), network k
+    starting from the slice of its K-output draw, so that it follows the
+    same steps as when trained alone.  workers >= 1: one network at a time
+    as a K-output network (or that many at once, each in its own context on
+    its own stream from its own host thread, the steps then without graph
+    capture so that no capture is open while another thread synchronises the
+    device).  Installs the K networks in ctx and returns a history dict."""
     import concurrent.futures as cf
     import threading
 
@@ -386,6 +390,31 @@ def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, ba
     del Td
     onehot = torch.eye(K, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
+    dims1 = [K + 2, *hidden, 1]
+    if int(workers) <= 0:
+        hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "hidden": list(hidden), "workers": 0}
+        ctx.ann_create_species(dims1)
+        ctx.ann_set_weights(np.concatenate([species_slice(init_params(dims, seed + 7919 * (k + 1)), dims, k)
+                                            for k in range(K)]))
+        ctx.ann_set_norm(*norm)
+        ctx.ann_reset_optimizer()
+        t0 = time.time()
+        el = []
+        for e0 in range(0, epochs, 5):   # slices of one schedule, to report progress
+            ne = min(5, epochs - e0)
+            els, _ = ctx.ann_train(X, Z, ne, batch=batch, lr0=lr0, lr1=lr1, seed=seed, epoch0=e0,
+                                   epochs_total=epochs)
+            el += [float(v) for v in els]
+            log(f"species (grouped): epochs {e0 + 1}-{e0 + ne}/{epochs} mean loss {el[-1]:.4e} "
+                f"({time.time() - t0:.0f} s)")
+        torch.cuda.synchronize()
+        hist["train_s"] = time.time() - t0
+        hist["steps"] = (ntr // batch) * epochs * K
+        hist["loss"] = el
+        hist["loss_last"] = [el[-1]] * K
+        ctx.ann_set_envelope(*env)
+        ctx.ann_set_checks(adj_max=ck["adj_max"], dT=ck["dT"], ratios=ck["ratios"])
+        return hist
     workers = max(1, min(int(workers), K))
     hist = {"epochs": epochs, "batch": batch, "n_train": int(ntr), "hidden": list(hidden),
             "workers": workers, "loss_last": [0.0] * K}
@@ -419,7 +448,7 @@ def train_species_networks(ctx, data, dt, hidden=(1600, 800, 400), epochs=20, ba
     torch.cuda.synchronize()
     hist["train_s"] = time.time() - t0
     hist["steps"] = (ntr // batch) * epochs * K
-    ctx.ann_create_species([K + 2, *hidden, 1])
+    ctx.ann_create_species(dims1)
     ctx.ann_set_weights(np.concatenate(nets))
     ctx.ann_set_norm(*norm)
     ctx.ann_set_envelope(*env)
@@ -560,8 +589,9 @@ def main(argv=None):
     ap.add_argument("--species-hidden", default="1600,800,400")
     ap.add_argument("--species-epochs", type=int, default=20)
     ap.add_argument("--species-out", default=None, help="where to save the per-species networks")
-    ap.add_argument("--species-workers", type=int, default=4,
-                    help="per-species networks trained at once (contexts on their own streams)")
+    ap.add_argument("--species-workers", type=int, default=0,
+                    help="0: all per-species networks in one grouped training; n >= 1: n of them at a "
+                         "time, each as a K-output network in its own context on its own stream")
     ap.add_argument("--recipe", default="cfg4", choices=["cfg4", "hfrd"],
                     help="cfg4: noisy trajectories + mixing lines + flame-block states; "
                          "hfrd: the paper's perturbation recipe (generate_pairs_hfrd)")
@@ -610,7 +640,8 @@ def main(argv=None):
         es = evaluate(ctx, T[hold], p[hold], Y[hold], Yn[hold], hrr_scale=hrr_unit)
         torch.cuda.synchronize()
         dims1 = [mech.K + 2, *hidden, 1]
-        fls = 3 * mlp_flops_per_cell(dims1[:-1] + [mech.K]) * a.batch * hs["steps"]
+        # work done: one-output networks when grouped, K-output ones trained one by one
+        fls = 3 * mlp_flops_per_cell(dims1 if hs["workers"] == 0 else dims1[:-1] + [mech.K]) * a.batch * hs["steps"]
         out_s = a.species_out or a.out.replace(".npz", "_species.npz")
         save(ctx, out_s)
         rep["species"] = {"dims": dims1, "networks": mech.K, "epochs": a.species_epochs,

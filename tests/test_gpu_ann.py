@@ -641,3 +641,31 @@ def test_train_loop_matches_step_sequence():
     ctxs[0].ann_forward_packed(Xh, out)
     mse = np.mean((host(out).astype(np.float64) - Zt[n:]) ** 2)
     assert hl[-1] == pytest.approx(mse, rel=1e-5)
+
+
+def test_training_in_schedule_slices_equals_one_call():
+    """chemk_ann_train over 4 epochs in one call and as two calls of 2 epochs
+    (epoch0 = 0, 2 of epochs_total = 4): the same learning rates, row orders
+    and Adam step counts, so the same weights bitwise and the same epoch
+    losses."""
+    import torch
+    mech = sm.mech_medium()
+    outs = []
+    for sliced in (False, True):
+        ctx, dims, params = _ctx_small_net(mech, seed=14)
+        n = 1024
+        T, p, Y = _states(mech, n, 48)
+        _set_norm(ctx, mech, T, p, Y)
+        Zt = np.random.default_rng(15).normal(0, 1, (n, mech.K)).astype(np.float32)
+        X = torch.empty((n, 64), dtype=torch.int16, device="cuda:0")
+        ctx.ann_pack(dev(T), dev(p), dev(Y), None, X, None)
+        Z = dev(Zt)
+        ctx.ann_reset_optimizer()
+        if sliced:
+            el = np.concatenate([ctx.ann_train(X, Z, 2, batch=256, epoch0=e0, epochs_total=4)[0] for e0 in (0, 2)])
+        else:
+            el = ctx.ann_train(X, Z, 4, batch=256)[0]
+        outs.append((ctx.ann_get_weights(), el))
+    announce(f"schedule slices: epoch losses {outs[0][1]} vs {outs[1][1]}")
+    assert np.array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-5)

@@ -329,23 +329,44 @@ def test_species_networks_at_paper_size_on_the_flame_block():
     assert rel < 2e-3 and np.abs(g - o).max() < 2e-2 * o.std()
 
 
-def test_species_networks_refuse_training_and_bad_shapes():
+def test_species_networks_one_hidden_layer_train_and_refuse_physics_losses():
+    """Per-species networks with one hidden layer (the first layer dense, the
+    output layer block diagonal, no grouped layer) train: the loss of a
+    step matches the oracle's and falls over a few steps.  The physics
+    losses and per-output weights, which couple species, are refused; so are
+    shapes that are not one-output networks."""
     import torch
     from paper_2402_18858_amd import chemk, train
     mech = sm.mech_medium()
     K = mech.K
     dims1 = [K + 2, 64, 1]
-    ens = _species_ctx(mech, dims1, [train.init_params(dims1, k) for k in range(K)])
-    T, p, Y = _states(mech, 128, 60)
-    _set_norm(ens, mech, T, p, Y)
+    nets = [train.init_params(dims1, k) for k in range(K)]
+    ens = _species_ctx(mech, dims1, nets)
+    B = 128
+    T, p, Y = _states(mech, B, 60)
+    mu_x, sd_x = _set_norm(ens, mech, T, p, Y)
     X = _packed(ens, T, p, Y)
-    Zt = torch.zeros((128, K), dtype=torch.float32, device="cuda:0")
+    Zh = np.random.default_rng(61).normal(0, 1, (B, K)).astype(np.float32)
+    Zt = dev(Zh)
+    idx = dev(np.arange(B, dtype=np.int32))
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    ens.ann_train_step(idx, X, Zt, 0.0, update=False, loss=loss)
+    xin = _oracle_inputs(T, p, Y, mu_x, sd_x)
+    lo = np.mean([oann.mse_loss(oann.forward(*_unpack(nets[k], dims1), xin, quantize=True)[0],
+                                Zh[:, k:k + 1].astype(np.float64))[0] for k in range(K)])
+    l0 = host(loss)[0]
+    assert l0 == pytest.approx(lo, rel=1e-3)
+    for _ in range(20):
+        ens.ann_train_step(idx, X, Zt, 3e-3, update=True)
+    loss.zero_()
+    ens.ann_train_step(idx, X, Zt, 0.0, update=False, loss=loss)
+    announce(f"one hidden layer, grouped steps: loss {l0:.4f} (oracle {lo:.4f}) -> {host(loss)[0]:.4f} after 20")
+    assert host(loss)[0] < 0.9 * l0
+    for kw in ({"w_mass": 0.5}, {"out_w": dev(np.ones(K, np.float32))}):
+        with pytest.raises(chemk.ChemkError):
+            ens.ann_train_step(idx, X, Zt, 1e-3, **kw)
     with pytest.raises(chemk.ChemkError):
-        ens.ann_train_step(dev(np.arange(128, dtype=np.int32)), X, Zt, 1e-3)
-    with pytest.raises(chemk.ChemkError):
-        ens.ann_train(X, Zt, 1, batch=128)
-    with pytest.raises(chemk.ChemkError):
-        ens.ann_reset_optimizer()
+        ens.ann_train(X, Zt, 1, batch=128, w_mass=0.5)
     ctx = chemk.Context(mech)
     for bad in ([K + 2, 1], [K + 2, 64, 2], [K + 1, 64, 1]):
         with pytest.raises(chemk.ChemkError):
@@ -383,3 +404,89 @@ def test_species_training_on_four_streams_equals_one_at_a_time():
         announce(f"species training, {workers} worker(s): {h['train_s']:.2f} s, last losses "
                  f"{min(h['loss_last']):.3e} .. {max(h['loss_last']):.3e}")
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_grouped_training_step_matches_oracle():
+    """One training step of 32 per-species networks 34-96-72-1 trained
+    together (grouped GEMMs): the batch loss (the mean of the networks' own
+    losses) and every network's gradient (its output column's mean squared
+    error alone) against the oracle network by network; then three Adam
+    steps, after which the networks still compute what the oracle computes
+    with the returned weights (the padding units stayed at zero)."""
+    import torch
+    from paper_2402_18858_amd import train
+    mech = sm.mech_medium()
+    K = mech.K
+    dims1 = [K + 2, 96, 72, 1]
+    nets = [_with_biases(train.init_params(dims1, 800 + k), dims1, 900 + k) for k in range(K)]
+    ens = _species_ctx(mech, dims1, nets)
+    B = 256
+    T, p, Y = _states(mech, B, 68)
+    mu_x, sd_x = _set_norm(ens, mech, T, p, Y)
+    Zt = np.random.default_rng(69).normal(0, 1, (B, K)).astype(np.float32)
+    X = _packed(ens, T, p, Y)
+    idx = dev(np.arange(B, dtype=np.int32))
+    grads = torch.zeros(ens.ann_param_count(), dtype=torch.float32, device="cuda:0")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    ens.ann_reset_optimizer()
+    ens.ann_train_step(idx, X, dev(Zt), 0.0, update=False, loss=loss, grads=grads)
+    gg = host(grads).astype(np.float64)
+    xin = _oracle_inputs(T, p, Y, mu_x, sd_x)
+    n1 = nets[0].size
+    los, rels = [], []
+    for k in range(K):
+        Ws, bs = _unpack(nets[k], dims1)
+        o, cache = oann.forward(Ws, bs, xin, quantize=True)
+        lo, dout = oann.mse_loss(o, Zt[:, k:k + 1].astype(np.float64))
+        gW, gb = oann.backward(Ws, bs, cache, dout, quantize=True)
+        ref = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(gW, gb)])
+        seg = gg[k * n1:(k + 1) * n1]
+        los.append(lo)
+        rels.append(np.sqrt(np.mean((seg - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    announce(f"grouped training step, {K} networks {dims1}: loss {host(loss)[0]:.6f} (oracle mean "
+             f"{np.mean(los):.6f}), gradient rel rms max {max(rels):.2e}")
+    assert host(loss)[0] == pytest.approx(np.mean(los), rel=1e-3)
+    assert max(rels) < 1e-2
+    for _ in range(3):
+        ens.ann_train_step(idx, X, dev(Zt), 1e-3, update=True)
+    p3 = ens.ann_get_weights()
+    assert np.abs(p3 - np.concatenate(nets)).max() > 1e-4
+    out3 = _gpu_out(ens, T, p, Y)
+    o3 = oann.species_forward([_unpack(p3[k * n1:(k + 1) * n1], dims1) for k in range(K)], xin)
+    r3 = np.sqrt(np.mean((out3 - o3) ** 2)) / np.sqrt(np.mean(o3 ** 2))
+    announce(f"after 3 grouped Adam steps: forward rel rms {r3:.2e} against the oracle on the returned weights")
+    assert r3 < 2e-3 and np.abs(out3 - o3).max() < 1e-2 * o3.std()
+
+
+def test_grouped_training_follows_one_network_at_a_time():
+    """The grouped training of all per-species networks and the one-at-a-time
+    training (K-output networks with a one-hot loss weight, sliced) start
+    from the same weights and see the same rows: after two epochs their
+    networks agree to the rounding of the different summation orders."""
+    import torch
+    from paper_2402_18858_amd import chemk, train
+    mech = sm.mech_medium()
+    K = mech.K
+    n = 4096 + 512
+    T, p, Y = _states(mech, n, 70)
+    rng = np.random.default_rng(71)
+    Yn = np.clip(Y + rng.normal(0, 1e-4, Y.shape) * Y, 0.0, None)
+    Yn /= Yn.sum(1, keepdims=True)
+    hold = np.arange(n - 512, n)
+    outs = []
+    for workers in (0, 1):
+        ctx = chemk.Context(mech)
+        ctx.ann_create([K + 2, 64, K])
+        mu_x, sd_x = oann.norm_stats(oann.raw_features(T[:n - 512], p[:n - 512], Y[:n - 512]))
+        d = (Yn - Y)[:n - 512]
+        ctx.ann_set_norm(mu_x, sd_x, d.mean(0), np.maximum(d.std(0), 1e-12), 5e-7)
+        h = train.train_species_networks(ctx, (T, p, Y, Yn, hold), 5e-7, hidden=(96, 40), epochs=2, batch=1024,
+                                         log=lambda m: None, workers=workers)
+        torch.cuda.synchronize()
+        outs.append((ctx.ann_get_weights(), _gpu_out(ctx, T[hold], p[hold], Y[hold])))
+        announce(f"species training, workers={workers}: {h['train_s']:.2f} s")
+    dw = np.abs(outs[0][0] - outs[1][0]).max()
+    do = np.abs(outs[0][1] - outs[1][1]).max()
+    announce(f"grouped vs one at a time: max |dw| {dw:.2e}, max |d out| {do:.2e} (spread {outs[1][1].std():.2e})")
+    assert dw < 1e-3
+    assert do < 1e-2 * outs[1][1].std()
