@@ -886,6 +886,27 @@ __global__ void colsum_final_kernel(const float *__restrict__ part, int P, int N
     else db[o] = s;
 }
 
+// dst[c ldd + r] = src[r lds + c] for r < R, c < C (BF16), through a 64 x 64
+// LDS tile: both the reads and the writes go along rows
+constexpr int TP_TILE = 64;
+__global__ void __launch_bounds__(256) transpose_bf16_kernel(const uint16_t *__restrict__ src, int R, int C,
+                                                             int lds, uint16_t *__restrict__ dst, int ldd) {
+    __shared__ uint16_t t[TP_TILE][TP_TILE + 2];
+    const int c0 = blockIdx.x * TP_TILE, r0 = blockIdx.y * TP_TILE;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = ty; i < TP_TILE; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        t[i][tx] = (r < R && c < C) ? src[(size_t)r * lds + c] : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = ty; i < TP_TILE; i += 4) {
+        const int c = c0 + i, r = r0 + tx;
+        if (c < C && r < R) dst[(size_t)c * ldd + r] = t[tx][i];
+    }
+}
+
 // grad[g gstride + r] = D[(g n + r) G + g], r < n: the diagonal blocks of the
 // dense output-layer weight gradient of G networks side by side
 __global__ void diag_blocks_kernel(const float *__restrict__ D, int n, int G, float *grad, size_t gstride) {
@@ -943,6 +964,35 @@ __global__ void cast_group_kernel(const float *__restrict__ M, size_t gstride, i
     const uint16_t v = f2bf(M[g * gstride + i]);
     Wt[g * wtG + (size_t)c * in + r] = v;
     if (Wb) Wb[g * wbG + (size_t)r * wbLd + c] = v;
+}
+
+// The same for a layer with out > 1, through a 64 x 64 LDS tile per block so
+// that the transposed Wt writes go along rows: block (bx, by, g) takes rows
+// [64 by, +64) and columns [64 bx, +64) of network g's [in x out] block.
+__global__ void __launch_bounds__(256) cast_group_tiled_kernel(const float *__restrict__ M, size_t gstride, int in,
+                                                               int out, uint16_t *Wt, size_t wtG, uint16_t *Wb,
+                                                               size_t wbG, int wbLd) {
+    __shared__ uint16_t t[64][66];
+    const size_t g = blockIdx.z;
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const float *Mg = M + g * gstride;
+#pragma unroll
+    for (int i = ty; i < 64; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        uint16_t v = 0;
+        if (r < in && c < out) {
+            v = f2bf(Mg[(size_t)r * out + c]);
+            if (Wb) Wb[g * wbG + (size_t)r * wbLd + c] = v;
+        }
+        t[i][tx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i, r = r0 + tx;
+        if (c < out && r < in) Wt[g * wtG + (size_t)c * in + r] = t[tx][i];
+    }
 }
 
 __global__ void cast_layer_kernel(const float *__restrict__ Wm, int in, int out, uint16_t *Wt,
@@ -1243,6 +1293,9 @@ struct AnnState {
     // joined before Adam
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> evFork, evJoin;
+    // per-species networks: transposed activations and dZ of the layer whose
+    // weight gradient is being formed ([width x B], batch contiguous)
+    uint16_t *tT[2] = {nullptr, nullptr};
     std::vector<float *> tZ;          // pre-activations per hidden layer
     std::vector<uint16_t *> tA;       // activations per layer input
 };
@@ -1289,6 +1342,8 @@ void ann_destroy(AnnState *a) {
     (void)hipFree(a->tWork);
     for (auto p : a->tZ) (void)hipFree(p);
     for (size_t i = 1; i < a->tA.size(); ++i) (void)hipFree(a->tA[i]);   // tA[0] aliases tX
+    (void)hipFree(a->tT[0]);
+    (void)hipFree(a->tT[1]);
     for (auto st : a->side)
         if (st) (void)hipStreamDestroy(st);
     for (auto ev : a->evFork) (void)hipEventDestroy(ev);
@@ -1307,9 +1362,12 @@ static hipError_t refresh_ensemble(AnnState *a, hipStream_t s) {
         const bool last = l == L - 1;   // out = 1: block-diagonal placement
         const size_t wtG = last ? (size_t)(G + 1) * in : (size_t)in * out;
         const size_t wbG = last ? (size_t)in * G + 1 : (size_t)in * out;
-        hipLaunchKernelGGL(cast_group_kernel, dim3((in * out + 255) / 256, G), dim3(256), 0, s,
-                           a->master + a->woff[l], a->gstride, in, out, a->Wt[l], wtG, a->Wb[l], wbG,
-                           last ? G : out);
+        if (last)   // out = 1: Wt runs along r already
+            hipLaunchKernelGGL(cast_group_kernel, dim3((in * out + 255) / 256, G), dim3(256), 0, s,
+                               a->master + a->woff[l], a->gstride, in, out, a->Wt[l], wtG, a->Wb[l], wbG, G);
+        else
+            hipLaunchKernelGGL(cast_group_tiled_kernel, dim3((out + 63) / 64, (in + 63) / 64, G), dim3(256), 0, s,
+                               a->master + a->woff[l], a->gstride, in, out, a->Wt[l], wtG, a->Wb[l], wbG, out);
         hipError_t e = hipMemcpy2DAsync(a->eB[l], 4 * (size_t)out, a->master + a->boff[l], 4 * a->gstride,
                                         4 * (size_t)out, G, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
@@ -2223,6 +2281,9 @@ static int dw_split(int in, int out, int B) {
 
 static hipError_t ensure_train(AnnState *a, int B) {
     if (B <= a->tB) return hipSuccess;
+    (void)hipFree(a->tT[0]);
+    (void)hipFree(a->tT[1]);
+    a->tT[0] = a->tT[1] = nullptr;
     (void)hipFree(a->tX);
     for (auto p : a->tdZ) (void)hipFree(p);
     a->tdZ.clear();
@@ -2285,6 +2346,15 @@ static hipError_t ensure_train(AnnState *a, int B) {
         uint16_t *ap = nullptr;
         if ((e = hipMalloc(&ap, 2 * (size_t)B * G * a->pd[l])) != hipSuccess) return e;
         a->tA.push_back(ap);
+    }
+    if (G > 1) {
+        size_t win = FPAD, wout = 0;
+        for (int l = 0; l < a->L; ++l) {
+            if (l > 0) win = std::max(win, G * a->pd[l]);
+            wout = std::max(wout, G * a->pd[l + 1]);
+        }
+        if ((e = hipMalloc(&a->tT[0], 2 * (size_t)B * win)) != hipSuccess) return e;
+        if ((e = hipMalloc(&a->tT[1], 2 * (size_t)B * wout)) != hipSuccess) return e;
     }
     a->tB = B;
     return hipSuccess;
@@ -2370,31 +2440,37 @@ static hipError_t ens_fwd_bwd(AnnState *a, const int32_t *idx, int B, const uint
         const int nall = G * out;                       // columns of dZ_l
         const uint16_t *dZ = a->tdZ[l];
         float *work = a->tWork + a->tWoff[l];
+        // weight gradient dW = A^T dZ, contracted over the batch: both
+        // operands are first transposed so that the batch is contiguous (the
+        // product then loads whole 16-byte chunks without transposing)
+        const int wa = l == 0 ? FPAD : G * in;   // columns of this layer's input
+        hipLaunchKernelGGL(transpose_bf16_kernel, dim3((wa + TP_TILE - 1) / TP_TILE, (B + TP_TILE - 1) / TP_TILE),
+                           dim3(256), 0, s, a->tA[l], B, wa, wa, a->tT[0], B);
+        hipLaunchKernelGGL(transpose_bf16_kernel, dim3((nall + TP_TILE - 1) / TP_TILE, (B + TP_TILE - 1) / TP_TILE),
+                           dim3(256), 0, s, dZ, B, nall, nall, a->tT[1], B);
         GemmArgs gw{};
         gw.K = B;
-        gw.A = a->tA[l];
-        gw.B = dZ;
+        gw.A = a->tT[0];
+        gw.lda = B;
+        gw.B = a->tT[1];
+        gw.ldb = B;
         if (last) {
             gw.M = G * in;
             gw.N = G;
-            gw.lda = G * in;
-            gw.ldb = G;
             gw.Cf = work;
             gw.ldc = G;
-            if ((e = launch_gemm(gw, false, false, EPI_STORE_F32, s)) != hipSuccess) return e;
+            if ((e = launch_gemm(gw, true, true, EPI_STORE_F32, s)) != hipSuccess) return e;
             hipLaunchKernelGGL(diag_blocks_kernel, dim3((in * G + 255) / 256), dim3(256), 0, s, work, in, G,
                                a->grad + a->woff[l], gs);
         } else {
             gw.M = in;
             gw.N = out;
-            gw.lda = l == 0 ? FPAD : G * in;
-            gw.gsA = l == 0 ? 0 : in;
-            gw.ldb = nall;
-            gw.gsB = out;
+            gw.gsA = l == 0 ? 0 : (long long)in * B;
+            gw.gsB = (long long)out * B;
             gw.Cf = a->grad + a->woff[l];
             gw.ldc = out;
             gw.gsCf = (long long)gs;
-            if ((e = launch_gemm(gw, false, false, EPI_STORE_F32, s, G)) != hipSuccess) return e;
+            if ((e = launch_gemm(gw, true, true, EPI_STORE_F32, s, G)) != hipSuccess) return e;
         }
         float *part = last ? work + (size_t)G * in * G : work;
         const int per = nall % 8 == 0 ? 8 : 1;

@@ -671,7 +671,8 @@ static hipError_t launch_case(const GemmArgs &g, bool vec, hipStream_t s, int gr
     const dim3 grid(((tiles + 7) / 8) * 8, 1, groups);
     const int kt = (g.K + TK - 1) / TK;
     // forward layers of the MLP get a K loop unrolled for their slab count
-    constexpr bool fwd = AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS || EP == EPI_GELU_DOT);
+    constexpr bool fwd =
+        AKV && BKV && (EP == EPI_BIAS_GELU || EP == EPI_BIAS || EP == EPI_GELU_DOT || EP == EPI_GELU_GRAD);
 #define GEMM_LAUNCH(VECV)                                                                    \
     hipLaunchKernelGGL((gemm_bf16_kernel<TB, TB, TK, AKV, BKV, EP, VECV>), dim3(grid),         \
                        dim3(NTHREADS), 0, s, g)
