@@ -67,7 +67,7 @@ def measured_traffic(key, routed=None):
         return None
     srcs = {"di_kernel": ("di.hip", "chemk_dev.h"), "di_kernel_routed": ("di.hip", "chemk_dev.h"),
             "gemm_layer2": ("gemm.hip",), "post_kernel": ("ann.hip",),
-            "ingest_kernel": ("ann.hip",)}[key]
+            "ingest_kernel": ("ann.hip",), "species_layer2": ("gemm.hip",)}[key]
     h = hashlib.sha1()
     for f in srcs:
         with open(os.path.join(ROOT, "paper_2402_18858_amd", "csrc", f), "rb") as fh:
@@ -183,7 +183,11 @@ def species_timing(ctx, mech, Tin, P, Yin, log, reps=5, hidden=(1600, 800, 400))
             "flops_per_cell": fl, "tflops": tf, "peak_tflops": PEAK_BF16_TFLOPS,
             "frac": tf / PEAK_BF16_TFLOPS, "per_layer": per_layer,
             "roofline": {"bound": "mfma", "achieved": per_layer[dom]["tflops"], "peak": PEAK_BF16_TFLOPS,
-                         "unit": "TFLOP/s", "frac": per_layer[dom]["frac"], "traffic": None,
+                         "unit": "TFLOP/s", "frac": per_layer[dom]["frac"],
+                         # HBM bytes of a full-chunk (17,408-row) layer-2 launch, scaled to
+                         # the average launch's rows like "achieved"
+                         "traffic": (measured_traffic("species_layer2") * per_layer[dom]["rows_per_launch"] / 17408
+                                     if dom == "layer2" and measured_traffic("species_layer2") else None),
                          "kernel": f"gemm_dma_kernel grouped over {K} networks, {dom} "
                                    f"({dims1[int(dom[-1]) - 1]} -> {dims1[int(dom[-1])]})",
                          "flops_per_launch": per_layer[dom]["flops_per_launch"]},
