@@ -36,12 +36,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector
 PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
 PEAK_HBM_GBS = 8000.0
-EXP_FLOPS = 25                # an FP64 exp/log counted as 25 operations
+# an FP64 exp as compiled for gfx950 (a kernel of one exp(): 19 FP64
+# instructions, 13 of them FMAs) counted as 32 operations
+EXP_FLOPS = 32
 
 
 def di_flops_per_step(K, R):
     """Algorithmic FLOPs of one RODAS step on one cell, N = K + 1 unknowns:
-    6 right-hand sides (each R reactions at 12 operations and two exp/log,
+    6 right-hand sides (each R reactions at 12 operations and two exp,
     plus 20 per species), one analytic Jacobian (40 per reaction, 20 per
     species), one LU of the N x N iteration matrix (2N^3/3) and 6 triangular
     solves (2N^2 each)."""
