@@ -269,3 +269,33 @@ def test_autotune_cache_and_factorisation_axis(tmp_path, monkeypatch):
         assert np.array_equal(x, y_)
     monkeypatch.delenv("CHEMK_TUNE_CACHE")
     chemk.tune_cache_clear()
+
+
+def test_di_takes_the_oracles_steps():
+    """The GPU integrator is the oracle's algorithm: on 384 flame-block cells
+    (a third from each region) both run RODAS at the same tolerances from the
+    same first step, so they accept and reject the same steps.  Step counts
+    agree cell by cell (an accept/reject decision can only flip where the
+    error estimate sits within rounding of 1), and the states agree far
+    below the parity bar (both carry the same truncation error)."""
+    from paper_2402_18858_amd import chemk
+    mech = sm.mech_medium()
+    ctx = chemk.Context(mech)
+    T0, p0, Y0, region = sw.flame_block(mech, 32, 2004)
+    rng = np.random.default_rng(5)
+    idx = np.sort(np.concatenate([rng.choice(np.nonzero(region == r)[0], 128, replace=False) for r in range(3)]))
+    T, p, Y = T0[idx], p0[idx], np.ascontiguousarray(Y0[idx])
+    o = chemk.default_opts(rtol=1e-7)
+    Tg, Yg, st, ns = _run(ctx, T, p, Y, 5e-7, rtol=o.rtol)
+    To, Yo, so, nso = oracle.OracleMech(mech).advance(T, p, Y, 5e-7, rtol=o.rtol, atol_Y=o.atol_Y, atol_T=o.atol_T,
+                                                      h0_frac=o.h0_frac, max_steps=o.max_steps)
+    same = (ns == nso).mean()
+    d = np.abs(ns.astype(np.int64) - nso)
+    ry, dT = _parity(Yg, Tg, Yo, To)
+    announce(f"steps vs the oracle's: {same * 100:.1f} % of cells equal, max |diff| {d.max()} of "
+             f"{nso.max()}, means {ns.mean():.2f} / {nso.mean():.2f}; max rel Y {ry:.2e}, |dT| {dT:.2e} K")
+    assert (st == 0).all() and (so == 0).all()
+    assert same >= 0.98
+    assert np.all(d <= np.maximum(2, 0.02 * nso))
+    assert abs(ns.mean() - nso.mean()) <= 0.005 * nso.mean()
+    assert ry < 1e-8 and dT < 1e-6
