@@ -669,3 +669,7 @@ def test_training_in_schedule_slices_equals_one_call():
     announce(f"schedule slices: epoch losses {outs[0][1]} vs {outs[1][1]}")
     assert np.array_equal(outs[0][0], outs[1][0])
     np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-5)
+    from paper_2402_18858_amd import chemk
+    for e0, tot in ((-1, 0), (3, 4), (0, 1)):     # negative start; slice past the end; total < epochs
+        with pytest.raises(chemk.ChemkError):
+            ctx.ann_train(X, Z, 2, batch=256, epoch0=e0, epochs_total=tot)

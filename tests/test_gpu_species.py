@@ -490,3 +490,41 @@ def test_grouped_training_follows_one_network_at_a_time():
     announce(f"grouped vs one at a time: max |dw| {dw:.2e}, max |d out| {do:.2e} (spread {outs[1][1].std():.2e})")
     assert dw < 1e-3
     assert do < 1e-2 * outs[1][1].std()
+
+
+def test_species_networks_for_53_species():
+    """Per-species networks on the 53-species mechanism: 53 groups (not a
+    multiple of 8) and an output count that is not a multiple of 8 (the
+    block-diagonal and column-sum kernels take their element-wise paths);
+    forward and one grouped training step against the oracle."""
+    import torch
+    from paper_2402_18858_amd import train
+    mech = sm.mech_large()
+    K = mech.K
+    dims1 = [K + 2, 64, 40, 1]
+    nets = [_with_biases(train.init_params(dims1, 1000 + k), dims1, 1100 + k) for k in range(K)]
+    ens = _species_ctx(mech, dims1, nets)
+    B = 192
+    T, p, Y = _states(mech, B, 72)
+    mu_x, sd_x = _set_norm(ens, mech, T, p, Y)
+    xin = _oracle_inputs(T, p, Y, mu_x, sd_x)
+    out = _gpu_out(ens, T, p, Y)
+    o = oann.species_forward([_unpack(v, dims1) for v in nets], xin)
+    rel = np.sqrt(np.mean((out - o) ** 2)) / np.sqrt(np.mean(o ** 2))
+    Zt = np.random.default_rng(73).normal(0, 1, (B, K)).astype(np.float32)
+    X = _packed(ens, T, p, Y)
+    grads = torch.zeros(ens.ann_param_count(), dtype=torch.float32, device="cuda:0")
+    ens.ann_train_step(dev(np.arange(B, dtype=np.int32)), X, dev(Zt), 0.0, update=False, grads=grads)
+    gg = host(grads).astype(np.float64)
+    n1 = nets[0].size
+    rels = []
+    for k in range(K):
+        Ws, bs = _unpack(nets[k], dims1)
+        ok, cache = oann.forward(Ws, bs, xin, quantize=True)
+        _, dout = oann.mse_loss(ok, Zt[:, k:k + 1].astype(np.float64))
+        gW, gb = oann.backward(Ws, bs, cache, dout, quantize=True)
+        ref = np.concatenate([np.concatenate([w.ravel(), b]) for w, b in zip(gW, gb)])
+        rels.append(np.sqrt(np.mean((gg[k * n1:(k + 1) * n1] - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
+    announce(f"53 per-species networks {dims1}: forward rel rms {rel:.2e}; gradient rel rms max {max(rels):.2e}")
+    assert rel < 2e-3 and np.abs(out - o).max() < 1e-2 * o.std()
+    assert max(rels) < 1e-2
