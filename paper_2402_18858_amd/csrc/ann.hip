@@ -795,9 +795,20 @@ __global__ void batch_index_kernel(const long long *ctl, int B, int spe, unsigne
 // Adam (Kingma & Ba 2015, Alg. 1) with the step count t = ctl[1] + ctl[0] + 1
 // and the cosine learning rate lr1 + (lr0 - lr1)(1 + cos(pi s / total)) / 2,
 // s = ctl[0], both read from the device.
+// The BF16 operand copies of one network's layers, refreshed by the Adam
+// pass that updates their masters (adam_sched_kernel): a weight at master
+// index woff[l] + r out[l] + c goes to Wb[l][r out[l] + c] and
+// Wt[l][c in[l] + r].  L = 0: no copies (refreshed apart).
+struct CastTable {
+    int L;
+    long long woff[16], boff[16];
+    int in[16], out[16];
+    uint16_t *Wt[16], *Wb[16];
+};
+
 __global__ void adam_sched_kernel(float *p, const float *__restrict__ g, float *mo, float *vo, int64_t n,
                                   const long long *ctl, double lr0, double lr1, long long total, double b1d,
-                                  double b2d, float eps) {
+                                  double b2d, float eps, CastTable ct) {
     __shared__ float sh[3];
     const float b1 = (float)b1d, b2 = (float)b2d;
     if (threadIdx.x == 0) {
@@ -817,7 +828,17 @@ __global__ void adam_sched_kernel(float *p, const float *__restrict__ g, float *
         const float v = b2 * vo[i] + (1.f - b2) * gi * gi;
         mo[i] = m;
         vo[i] = v;
-        p[i] -= lr * (m * bc1) / (sqrtf(v * bc2) + eps);
+        const float pn = p[i] - lr * (m * bc1) / (sqrtf(v * bc2) + eps);
+        p[i] = pn;
+        for (int l = 0; l < ct.L; ++l)
+            if (i >= ct.woff[l] && i < ct.boff[l]) {
+                const int e = (int)(i - ct.woff[l]);
+                const int r = e / ct.out[l], c = e - r * ct.out[l];
+                const uint16_t b = f2bf(pn);
+                ct.Wb[l][e] = b;
+                ct.Wt[l][(size_t)c * ct.in[l] + r] = b;
+                break;
+            }
     }
 }
 
@@ -2733,6 +2754,19 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
         hipLaunchKernelGGL(zero_f32_kernel, dim3((o->epochs + 255) / 256), dim3(256), 0, s, hloss, o->epochs);
         if ((e = hipGetLastError())) break;
         const int gadam = (int)std::min<size_t>(4096, (a->nparam + 255) / 256);
+        // one network: the Adam pass writes the BF16 copies itself
+        CastTable ct{};
+        if (a->G == 1) {
+            ct.L = a->L;
+            for (int l = 0; l < a->L; ++l) {
+                ct.woff[l] = (long long)a->woff[l];
+                ct.boff[l] = (long long)a->boff[l];
+                ct.in[l] = a->pd[l];
+                ct.out[l] = a->pd[l + 1];
+                ct.Wt[l] = a->Wt[l];
+                ct.Wb[l] = a->Wb[l];
+            }
+        }
         auto one_step = [&](hipStream_t st) -> hipError_t {
             hipLaunchKernelGGL(batch_index_kernel, dim3((B + 255) / 256), dim3(256), 0, st, ctl, B, spe,
                                (unsigned int)n, half, (unsigned long long)o->seed, idx);
@@ -2742,8 +2776,8 @@ extern "C" int chemk_ann_train(chemk_ctx *c, int64_t n, const uint16_t *X, const
             if (ee != hipSuccess) return ee;
             hipLaunchKernelGGL(adam_sched_kernel, dim3(gadam), dim3(256), 0, st, a->master, a->grad, a->m1,
                                a->m2, (int64_t)a->nparam, ctl, (double)o->lr0, (double)o->lr1, total, 0.9,
-                               0.999, 1e-8f);
-            if ((ee = refresh_bf16(a, st)) != hipSuccess) return ee;
+                               0.999, 1e-8f, ct);
+            if (a->G > 1 && (ee = refresh_bf16(a, st)) != hipSuccess) return ee;
             hipLaunchKernelGGL(step_end_kernel, dim3(1), dim3(64), 0, st, ctl);
             return hipGetLastError();
         };
