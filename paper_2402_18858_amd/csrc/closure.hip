@@ -6,6 +6,7 @@
 // wavefront per cell, lane k < K on species k, as in the advance.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -79,6 +80,121 @@ __global__ void __launch_bounds__(256) transport_kernel(DevMech m, const double 
         mu_out[c] = mix;
         if (lam_out) lam_out[c] = 0.5 * (la + 1.0 / lh);
     }
+}
+
+// Mechanisms of at most 32 species: two cells per wave, lanes 32 h + i on
+// species i of the wave's cell h.  Sums and maxima stay within a half.
+constexpr int HALF = 32;
+
+__device__ __forceinline__ double half_sum(double v) {
+#pragma unroll
+    for (int o = HALF / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ double half_max(double v) {
+#pragma unroll
+    for (int o = HALF / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+constexpr int PAIR_WAVES = 4;                  // waves per workgroup
+constexpr int PAIR_CELLS = 2 * PAIR_WAVES;     // cells per workgroup pass
+
+// Transport of K <= 32 species, two cells per wave.  Each workgroup stages
+// Wilke's factors once in LDS as pairs (w_ij, c_ij) at j K + i, so that the
+// lanes of a half read consecutive pairs for each j, and then walks the
+// cells PAIR_CELLS at a time.  Each lane keeps 1/sqrt(mu_i); the half's
+// mole fractions and those reciprocals sit in LDS for the j loop.
+__global__ void __launch_bounds__(64 * PAIR_WAVES) transport_pair_kernel(DevMech m, const double *__restrict__ tab,
+                                                                         int n, const double *__restrict__ T,
+                                                                         const double *__restrict__ Y, double *mu_out,
+                                                                         double *lam_out) {
+    __shared__ double2 wc[HALF * HALF];
+    __shared__ double2 xs[PAIR_WAVES][2][HALF];
+    const int K = m.K;
+    const double *muc = tab, *lac = tab + 4 * K, *wt = tab + 8 * K, *ct = wt + K * K;
+    for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
+        const int j = t / K, i = t - j * K;
+        wc[t] = make_double2(wt[i * K + j], ct[i * K + j]);
+    }
+    const int lane = lane_id();
+    const int h = lane / HALF, i = lane % HALF;
+    const int w = threadIdx.x / WAVE;
+    const bool sp = i < K;
+    const int ii = sp ? i : 0;   // lanes past K read a valid pair, unused
+    for (int base = blockIdx.x * PAIR_CELLS; base < n; base += gridDim.x * PAIR_CELLS) {
+        __syncthreads();   // the table is in place; the last pass's xs is read
+        const int c = base + 2 * w + h;
+        const bool live = c < n;
+        const double Tc = live ? T[c] : 1000.0;
+        const double lt = ln_pos(Tc);
+        const double nk = (sp && live) ? Y[(size_t)c * K + i] * m.invW[i] : 0.0;
+        const double tot = half_sum(nk);
+        const double X = live ? nk / tot : 0.0;
+        const double mu = sp ? poly3_exp(muc + 4 * i, lt) : 1.0;
+        const double lam = sp ? poly3_exp(lac + 4 * i, lt) : 1.0;
+        const double s = sqrt(mu);
+        xs[w][h][i] = make_double2(X, 1.0 / s);
+        __syncthreads();
+        double den = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const double2 xj = xs[w][h][j];
+            const double2 p = wc[j * K + ii];
+            const double f = fma(s * xj.y, p.x, 1.0);
+            den = fma(f * f, xj.x * p.y, den);
+        }
+        const double mix = half_sum(sp ? X * mu / den : 0.0);
+        const double la = half_sum(sp ? X * lam : 0.0);
+        const double lh = half_sum(sp ? X / lam : 0.0);
+        if (i == 0 && live) {
+            mu_out[c] = mix;
+            if (lam_out) lam_out[c] = 0.5 * (la + 1.0 / lh);
+        }
+    }
+}
+
+// The PaSR closure (see pasr_kernel) of K <= 32 species, two cells per wave.
+__global__ void __launch_bounds__(256) pasr_pair_kernel(DevMech m, int n, const double *__restrict__ T,
+                                                        const double *__restrict__ p, const double *__restrict__ Y0,
+                                                        const double *__restrict__ Y1, double dt,
+                                                        const double *__restrict__ ksgs,
+                                                        const double *__restrict__ delta,
+                                                        const double *__restrict__ mu, double c_eps, double y_min,
+                                                        double *kappa_out, double *omega_out, double *Yout) {
+    const int K = m.K;
+    const int lane = lane_id();
+    const int h = lane / HALF, i = lane % HALF;
+    const int c = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * 2 + h;
+    const bool live = c < n;
+    const bool sp = live && i < K;
+    const double y0 = sp ? Y0[(size_t)c * K + i] : 0.0;
+    const double y1 = sp ? Y1[(size_t)c * K + i] : 0.0;
+    const double Tc = live ? T[c] : 1.0, pc = live ? p[c] : 1.0;
+    const double rho = pc / (R_SI * Tc * half_sum(sp ? y0 * m.invW[i] * 1e3 : 0.0));
+    const double om = rho * (y1 - y0) / dt;
+    const double tk = (sp && om > 0.0 && y1 >= y_min) ? rho * y1 / om : -1.0;
+    const double tau_c = half_max(tk);
+    if (!live) return;
+    double kappa = 1.0;
+    if (tau_c >= 0.0) {
+        const double k = ksgs[c];
+        if (k <= 0.0) {
+            kappa = 0.0;
+        } else {
+            const double up = sqrt(2.0 * k / 3.0);
+            const double tau_d = delta[c] / up;
+            const double eps = c_eps * k * sqrt(k) / delta[c];
+            const double tau_k = sqrt(mu[c] / rho / eps);
+            const double tau_mix = sqrt(tau_d * tau_k);
+            kappa = tau_c / (tau_c + tau_mix);
+        }
+    }
+    if (sp) {
+        if (omega_out) omega_out[(size_t)c * K + i] = kappa * om;
+        if (Yout) Yout[(size_t)c * K + i] = y0 + kappa * (y1 - y0);
+    }
+    if (i == 0 && kappa_out) kappa_out[c] = kappa;
 }
 
 // One wave per cell: the PaSR closure of one step (see chemk_pasr).
@@ -195,9 +311,17 @@ extern "C" int chemk_transport(chemk_ctx *c, int64_t n, const double *T, const d
     if (n == 0) return CHEMK_OK;
     if (!T || !Y || !mu) return fail_arg("null array");
     if (hipSetDevice(ctx_device(c)) != hipSuccess) return CHEMK_E_HIP;
-    const int per = 4;   // cells (waves) per workgroup
-    hipLaunchKernelGGL(transport_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(64 * per), 0,
-                       (hipStream_t)stream, ctx_devmech(c), tr->d, (int)n, T, Y, mu, lam);
+    if (tr->K <= HALF) {
+        // about eight workgroups per CU, each staging the factor table once
+        const int64_t passes = (n + PAIR_CELLS - 1) / PAIR_CELLS;
+        hipLaunchKernelGGL(transport_pair_kernel, dim3((unsigned)std::min<int64_t>(passes, 2048)),
+                           dim3(64 * PAIR_WAVES), 0, (hipStream_t)stream, ctx_devmech(c), tr->d, (int)n, T, Y, mu,
+                           lam);
+    } else {
+        const int per = 4;   // cells (waves) per workgroup
+        hipLaunchKernelGGL(transport_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(64 * per), 0,
+                           (hipStream_t)stream, ctx_devmech(c), tr->d, (int)n, T, Y, mu, lam);
+    }
     if (hipGetLastError() != hipSuccess) {
         ctx_set_error("transport launch");
         return CHEMK_E_HIP;
@@ -218,9 +342,18 @@ extern "C" int chemk_pasr(chemk_ctx *c, int64_t n, const double *T, const double
     if (!(c_eps > 0) || !std::isfinite(c_eps) || !(y_min >= 0) || !std::isfinite(y_min))
         return fail_arg("c_eps must be > 0 and y_min >= 0");
     if (hipSetDevice(ctx_device(c)) != hipSuccess) return CHEMK_E_HIP;
-    const int per = 4;
-    hipLaunchKernelGGL(pasr_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(64 * per), 0, (hipStream_t)stream,
-                       ctx_devmech(c), (int)n, T, p, Y0, Y1, dt, k_sgs, delta, mu, c_eps, y_min, kappa, omega, Y_out);
+    const DevMech dm = ctx_devmech(c);
+    if (dm.K <= HALF) {
+        const int per = 8;   // cells per workgroup: two per wave
+        hipLaunchKernelGGL(pasr_pair_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0,
+                           (hipStream_t)stream, dm, (int)n, T, p, Y0, Y1, dt, k_sgs, delta, mu, c_eps, y_min, kappa,
+                           omega, Y_out);
+    } else {
+        const int per = 4;
+        hipLaunchKernelGGL(pasr_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(64 * per), 0,
+                           (hipStream_t)stream, dm, (int)n, T, p, Y0, Y1, dt, k_sgs, delta, mu, c_eps, y_min, kappa,
+                           omega, Y_out);
+    }
     if (hipGetLastError() != hipSuccess) {
         ctx_set_error("PaSR launch");
         return CHEMK_E_HIP;

@@ -37,10 +37,37 @@ def test_transport_matches_oracle(which):
     assert rm < 1e-12 and rl < 1e-12
 
 
-def test_pasr_matches_oracle():
+@pytest.mark.parametrize("which", ["medium", "large"])
+def test_transport_at_block_size_matches_oracle_on_sampled_cells(which):
+    """The full-block launch (several passes of each workgroup over its
+    cells, and a ragged last pass) on 262,147 cells; the oracle on the first
+    and last cells and a random sample between."""
     import torch
     from paper_2402_18858_amd import chemk
-    mech = sm.mech_medium()
+    mech = getattr(sm, f"mech_{which}")()
+    ctx = chemk.Context(mech)
+    mu_c, lam_c = st.transport_fits(mech)
+    ctx.transport_set(mu_c, lam_c)
+    n = 262_147
+    T, p, Y = sw.uniform_cells(mech, n, 34, T_range=(300, 3000))
+    mu = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    lam = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    ctx.transport(dev(T), dev(Y), mu, lam)
+    rng = np.random.default_rng(35)
+    idx = np.unique(np.concatenate([np.arange(40), np.arange(n - 40, n), rng.integers(0, n, 120)]))
+    W = mech.composition.astype(float) @ np.asarray(mech.element_mass, float)
+    mo, lo = oc.transport(mu_c, lam_c, W, T[idx], Y[idx])
+    rm = np.abs(host(mu)[idx] / mo - 1).max()
+    rl = np.abs(host(lam)[idx] / lo - 1).max()
+    announce(f"transport {which}: {n} cells, {idx.size} sampled, max rel mu {rm:.2e}, lambda {rl:.2e}")
+    assert rm < 1e-12 and rl < 1e-12
+
+
+@pytest.mark.parametrize("which", ["small", "medium", "large"])
+def test_pasr_matches_oracle(which):
+    import torch
+    from paper_2402_18858_amd import chemk
+    mech = getattr(sm, f"mech_{which}")()
     ctx = chemk.Context(mech)
     W = mech.composition.astype(float) @ np.asarray(mech.element_mass, float)
     n = 777
