@@ -114,12 +114,23 @@ def closure_timing(ctx, mech, Tin, P, Yin, T_a, Y_a, dt, log, reps=10):
     t_pa = timed(lambda: ctx.pasr(Tin, P, Yin, Y1, dt, ksgs, delta, mu, kappa=kap, omega=om, Y_out=Yb))
     b_tr = 8 * (1 + K) + 16                   # T, Y in; mu, lambda out
     b_pa = 8 * (2 + 2 * K + 3) + 8 * (1 + 2 * K)   # T, p, Y0, Y1, k, delta, mu in; kappa, omega, Y out
+    # transport's algorithmic FP64 work: 7 operations per species pair in
+    # Wilke's sum (ratio, fused multiply-add, square, product, accumulate)
+    # and per species two polynomial exps (6 + EXP_FLOPS each) and about 14
+    # more (mole fraction, square root, the three mixture sums)
+    f_tr = 7 * K * K + (2 * (6 + EXP_FLOPS) + 14) * K
+    tr_tf = f_tr * n / (t_tr * 1e-3) / 1e12
+    pa_gbs = b_pa * n / (t_pa * 1e-3) / 1e9
     k_h = kap.cpu().numpy()
-    log(f"closure: transport {t_tr:.3f} ms, PaSR {t_pa:.3f} ms on {n} cells")
+    log(f"closure: transport {t_tr:.3f} ms ({tr_tf:.2f} TFLOP/s), PaSR {t_pa:.3f} ms ({pa_gbs:.0f} GB/s) on {n} cells")
     return {"cells": n, "transport_ms": t_tr, "transport_bytes_per_cell": b_tr,
             "transport_GB_per_s": b_tr * n / (t_tr * 1e-3) / 1e9,
             "pasr_ms": t_pa, "pasr_bytes_per_cell": b_pa,
-            "pasr_GB_per_s": b_pa * n / (t_pa * 1e-3) / 1e9, "peak_GB_per_s": PEAK_HBM_GBS,
+            "pasr_GB_per_s": pa_gbs, "peak_GB_per_s": PEAK_HBM_GBS,
+            "transport_roofline": {"bound": "alu", "achieved": tr_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": tr_tf / PEAK_FP64_TFLOPS, "flops_per_cell": f_tr},
+            "pasr_roofline": {"bound": "hbm", "achieved": pa_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": pa_gbs / PEAK_HBM_GBS},
             "kappa_p10_p50_p90": [float(np.percentile(k_h, q)) for q in (10, 50, 90)],
             "inputs": "transport fits of synth/transport.py; k_sgs ~ 10^U[-1,2] m^2/s^2, delta = 1 mm"}
 
