@@ -2,8 +2,9 @@
 // the transport-property update (Sec. II.A: properties from temperature
 // polynomials) and the PaSR closure that consumes the advance's output
 // (Sec. III: chemical time from the slowest species formation rate, mixing
-// time the geometric mean of the sub-grid and Kolmogorov times).  One
-// wavefront per cell, lane k < K on species k, as in the advance.
+// time the geometric mean of the sub-grid and Kolmogorov times).  Lane k
+// of a cell's lanes works on species k: two cells per wavefront for
+// mechanisms of at most 32 species, one per wavefront above that.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -104,8 +105,8 @@ constexpr int PAIR_CELLS = 2 * PAIR_WAVES;     // cells per workgroup pass
 // Transport of K <= 32 species, two cells per wave.  Each workgroup stages
 // Wilke's factors once in LDS as pairs (w_ij, c_ij) at j K + i, so that the
 // lanes of a half read consecutive pairs for each j, and then walks the
-// cells PAIR_CELLS at a time.  Each lane keeps 1/sqrt(mu_i); the half's
-// mole fractions and those reciprocals sit in LDS for the j loop.
+// cells PAIR_CELLS at a time.  Each lane keeps sqrt(mu_i) and publishes
+// its reciprocal, with its mole fraction, in LDS for the half's j loop.
 __global__ void __launch_bounds__(64 * PAIR_WAVES) transport_pair_kernel(DevMech m, const double *__restrict__ tab,
                                                                          int n, const double *__restrict__ T,
                                                                          const double *__restrict__ Y, double *mu_out,
