@@ -155,7 +155,12 @@ __global__ void __launch_bounds__(64 * PAIR_WAVES) transport_pair_kernel(DevMech
     }
 }
 
-// The PaSR closure (see pasr_kernel) of K <= 32 species, two cells per wave.
+constexpr int PASR_PAIRS = 4;   // cell pairs per wave
+
+// The PaSR closure (see pasr_kernel) of K <= 32 species, two cells per wave
+// and PASR_PAIRS pairs per wave, adjacent in memory: every load of the
+// wave's cells is issued before the first pair's arithmetic, so that more
+// bytes are in flight per wave.
 __global__ void __launch_bounds__(256) pasr_pair_kernel(DevMech m, int n, const double *__restrict__ T,
                                                         const double *__restrict__ p, const double *__restrict__ Y0,
                                                         const double *__restrict__ Y1, double dt,
@@ -166,36 +171,52 @@ __global__ void __launch_bounds__(256) pasr_pair_kernel(DevMech m, int n, const 
     const int K = m.K;
     const int lane = lane_id();
     const int h = lane / HALF, i = lane % HALF;
-    const int c = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * 2 + h;
-    const bool live = c < n;
-    const bool sp = live && i < K;
-    const double y0 = sp ? Y0[(size_t)c * K + i] : 0.0;
-    const double y1 = sp ? Y1[(size_t)c * K + i] : 0.0;
-    const double Tc = live ? T[c] : 1.0, pc = live ? p[c] : 1.0;
-    const double rho = pc / (R_SI * Tc * half_sum(sp ? y0 * m.invW[i] * 1e3 : 0.0));
-    const double om = rho * (y1 - y0) / dt;
-    const double tk = (sp && om > 0.0 && y1 >= y_min) ? rho * y1 / om : -1.0;
-    const double tau_c = half_max(tk);
-    if (!live) return;
-    double kappa = 1.0;
-    if (tau_c >= 0.0) {
-        const double k = ksgs[c];
-        if (k <= 0.0) {
-            kappa = 0.0;
-        } else {
-            const double up = sqrt(2.0 * k / 3.0);
-            const double tau_d = delta[c] / up;
-            const double eps = c_eps * k * sqrt(k) / delta[c];
-            const double tau_k = sqrt(mu[c] / rho / eps);
-            const double tau_mix = sqrt(tau_d * tau_k);
-            kappa = tau_c / (tau_c + tau_mix);
+    const int wave = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    const double invW = i < K ? m.invW[i] : 0.0;
+    double y0[PASR_PAIRS], y1[PASR_PAIRS], Tc[PASR_PAIRS], pc[PASR_PAIRS], kc[PASR_PAIRS], dc[PASR_PAIRS],
+        mc[PASR_PAIRS];
+#pragma unroll
+    for (int q = 0; q < PASR_PAIRS; ++q) {
+        const int c = (wave * PASR_PAIRS + q) * 2 + h;
+        const bool live = c < n;
+        const bool sp = live && i < K;
+        y0[q] = sp ? Y0[(size_t)c * K + i] : 0.0;
+        y1[q] = sp ? Y1[(size_t)c * K + i] : 0.0;
+        Tc[q] = live ? T[c] : 1.0;
+        pc[q] = live ? p[c] : 1.0;
+        kc[q] = live ? ksgs[c] : 0.0;
+        dc[q] = live ? delta[c] : 1.0;
+        mc[q] = live ? mu[c] : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PASR_PAIRS; ++q) {
+        const int c = (wave * PASR_PAIRS + q) * 2 + h;
+        const bool live = c < n;
+        const bool sp = live && i < K;
+        const double rho = pc[q] / (R_SI * Tc[q] * half_sum(sp ? y0[q] * invW * 1e3 : 0.0));
+        const double om = rho * (y1[q] - y0[q]) / dt;
+        const double tk = (sp && om > 0.0 && y1[q] >= y_min) ? rho * y1[q] / om : -1.0;
+        const double tau_c = half_max(tk);
+        double kappa = 1.0;
+        if (tau_c >= 0.0) {
+            const double k = kc[q];
+            if (k <= 0.0) {
+                kappa = 0.0;
+            } else {
+                const double up = sqrt(2.0 * k / 3.0);
+                const double tau_d = dc[q] / up;
+                const double eps = c_eps * k * sqrt(k) / dc[q];
+                const double tau_k = sqrt(mc[q] / rho / eps);
+                const double tau_mix = sqrt(tau_d * tau_k);
+                kappa = tau_c / (tau_c + tau_mix);
+            }
         }
+        if (sp) {
+            if (omega_out) omega_out[(size_t)c * K + i] = kappa * om;
+            if (Yout) Yout[(size_t)c * K + i] = y0[q] + kappa * (y1[q] - y0[q]);
+        }
+        if (live && i == 0 && kappa_out) kappa_out[c] = kappa;
     }
-    if (sp) {
-        if (omega_out) omega_out[(size_t)c * K + i] = kappa * om;
-        if (Yout) Yout[(size_t)c * K + i] = y0 + kappa * (y1 - y0);
-    }
-    if (i == 0 && kappa_out) kappa_out[c] = kappa;
 }
 
 // One wave per cell: the PaSR closure of one step (see chemk_pasr).
@@ -345,7 +366,7 @@ extern "C" int chemk_pasr(chemk_ctx *c, int64_t n, const double *T, const double
     if (hipSetDevice(ctx_device(c)) != hipSuccess) return CHEMK_E_HIP;
     const DevMech dm = ctx_devmech(c);
     if (dm.K <= HALF) {
-        const int per = 8;   // cells per workgroup: two per wave
+        const int64_t per = 4 * 2 * PASR_PAIRS;   // cells per workgroup of four waves
         hipLaunchKernelGGL(pasr_pair_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0,
                            (hipStream_t)stream, dm, (int)n, T, p, Y0, Y1, dt, k_sgs, delta, mu, c_eps, y_min, kappa,
                            omega, Y_out);
