@@ -96,3 +96,35 @@ def test_pasr_matches_oracle(which):
     np.testing.assert_allclose(host(Yb), yo, rtol=0, atol=1e-15)
     announce(f"PaSR: {n} cells, kappa in [{ko.min():.3f}, {ko.max():.3f}], max rel kappa "
              f"{np.abs(kg / np.where(ko > 0, ko, 1) - np.where(ko > 0, 1, 0)).max():.2e}")
+
+
+@pytest.mark.parametrize("which", ["medium", "large"])
+def test_pasr_at_block_size_matches_oracle_on_sampled_cells(which):
+    """The full-block PaSR launch on 262,147 cells (a ragged last
+    workgroup); the oracle on the first and last cells and a random sample."""
+    import torch
+    from paper_2402_18858_amd import chemk
+    mech = getattr(sm, f"mech_{which}")()
+    ctx = chemk.Context(mech)
+    W = mech.composition.astype(float) @ np.asarray(mech.element_mass, float)
+    n = 262_147
+    T, p, Y0 = sw.uniform_cells(mech, n, 36, T_range=(900, 2400))
+    rng = np.random.default_rng(37)
+    dY = rng.normal(0, 1e-3, Y0.shape)
+    dY -= dY.mean(1, keepdims=True)
+    Y1 = np.clip(Y0 + dY, 0, None)
+    Y1 /= Y1.sum(1, keepdims=True)
+    k = 10.0 ** rng.uniform(-1, 2, n)
+    delta = 10.0 ** rng.uniform(-4, -2.5, n)
+    mu = rng.uniform(2e-5, 8e-5, n)
+    dt = 1e-6
+    kap = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    om = torch.zeros((n, mech.K), dtype=torch.float64, device="cuda:0")
+    Yb = torch.zeros((n, mech.K), dtype=torch.float64, device="cuda:0")
+    ctx.pasr(dev(T), dev(p), dev(Y0), dev(Y1), dt, dev(k), dev(delta), dev(mu), kappa=kap, omega=om, Y_out=Yb)
+    idx = np.unique(np.concatenate([np.arange(40), np.arange(n - 40, n), rng.integers(0, n, 120)]))
+    ko, oo, yo = oc.pasr(W, T[idx], p[idx], Y0[idx], Y1[idx], dt, k[idx], delta[idx], mu[idx])
+    np.testing.assert_allclose(host(kap)[idx], ko, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(host(om)[idx], oo, rtol=1e-11, atol=1e-13 * np.abs(oo).max())
+    np.testing.assert_allclose(host(Yb)[idx], yo, rtol=0, atol=1e-15)
+    announce(f"PaSR {which}: {n} cells, {idx.size} sampled, kappa in [{ko.min():.3f}, {ko.max():.3f}]")
