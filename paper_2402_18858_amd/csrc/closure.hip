@@ -47,7 +47,8 @@ __device__ __forceinline__ double poly3_exp(const double *c, double lt) {
 }
 
 // One wave per cell: mixture viscosity (Wilke) and conductivity (Mathur,
-// Tondon and Saxena) from the species polynomials.
+// Tondon and Saxena) from the species polynomials, the factor table read
+// from global memory (mechanisms whose table does not fit a workgroup's LDS).
 __global__ void __launch_bounds__(256) transport_kernel(DevMech m, const double *__restrict__ tab, int n,
                                                         const double *__restrict__ T, const double *__restrict__ Y,
                                                         double *mu_out, double *lam_out) {
@@ -100,19 +101,29 @@ __device__ __forceinline__ double half_max(double v) {
 }
 
 constexpr int PAIR_WAVES = 4;                  // waves per workgroup
-constexpr int PAIR_CELLS = 2 * PAIR_WAVES;     // cells per workgroup pass
 
-// Transport of K <= 32 species, two cells per wave.  Each workgroup stages
-// Wilke's factors once in LDS as pairs (w_ij, c_ij) at j K + i, so that the
-// lanes of a half read consecutive pairs for each j, and then walks the
-// cells PAIR_CELLS at a time.  Each lane keeps sqrt(mu_i) and publishes
-// its reciprocal, with its mole fraction, in LDS for the half's j loop.
-__global__ void __launch_bounds__(64 * PAIR_WAVES) transport_pair_kernel(DevMech m, const double *__restrict__ tab,
-                                                                         int n, const double *__restrict__ T,
-                                                                         const double *__restrict__ Y, double *mu_out,
-                                                                         double *lam_out) {
-    __shared__ double2 wc[HALF * HALF];
-    __shared__ double2 xs[PAIR_WAVES][2][HALF];
+// Sum over the LN = WAVE / CPW lanes of one cell (CPW cells per wave).
+template <int CPW> __device__ __forceinline__ double cell_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / CPW / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Transport, CPW cells per wave (2 for K <= 32, else 1), lane i of a cell's
+// lanes on species i.  Each workgroup stages Wilke's factors once in LDS
+// (dynamic, K K pairs (w_ij, c_ij) at j K + i, so that a cell's lanes read
+// consecutive pairs for each j) and then walks the cells PAIR_WAVES CPW at
+// a time.  Each lane keeps sqrt(mu_i) and publishes its reciprocal, with
+// its mole fraction, in LDS for the cell's j loop.
+template <int CPW>
+__global__ void __launch_bounds__(64 * PAIR_WAVES) transport_lds_kernel(DevMech m, const double *__restrict__ tab,
+                                                                        int n, const double *__restrict__ T,
+                                                                        const double *__restrict__ Y, double *mu_out,
+                                                                        double *lam_out) {
+    constexpr int LN = WAVE / CPW;   // lanes per cell
+    constexpr int CELLS = PAIR_WAVES * CPW;
+    extern __shared__ double2 wc[];   // [K K]
+    __shared__ double2 xs[PAIR_WAVES][CPW][LN];
     const int K = m.K;
     const double *muc = tab, *lac = tab + 4 * K, *wt = tab + 8 * K, *ct = wt + K * K;
     for (int t = threadIdx.x; t < K * K; t += blockDim.x) {
@@ -120,18 +131,18 @@ __global__ void __launch_bounds__(64 * PAIR_WAVES) transport_pair_kernel(DevMech
         wc[t] = make_double2(wt[i * K + j], ct[i * K + j]);
     }
     const int lane = lane_id();
-    const int h = lane / HALF, i = lane % HALF;
+    const int h = lane / LN, i = lane % LN;
     const int w = threadIdx.x / WAVE;
     const bool sp = i < K;
     const int ii = sp ? i : 0;   // lanes past K read a valid pair, unused
-    for (int base = blockIdx.x * PAIR_CELLS; base < n; base += gridDim.x * PAIR_CELLS) {
+    for (int base = blockIdx.x * CELLS; base < n; base += gridDim.x * CELLS) {
         __syncthreads();   // the table is in place; the last pass's xs is read
-        const int c = base + 2 * w + h;
+        const int c = base + CPW * w + h;
         const bool live = c < n;
         const double Tc = live ? T[c] : 1000.0;
         const double lt = ln_pos(Tc);
         const double nk = (sp && live) ? Y[(size_t)c * K + i] * m.invW[i] : 0.0;
-        const double tot = half_sum(nk);
+        const double tot = cell_sum<CPW>(nk);
         const double X = live ? nk / tot : 0.0;
         const double mu = sp ? poly3_exp(muc + 4 * i, lt) : 1.0;
         const double lam = sp ? poly3_exp(lac + 4 * i, lt) : 1.0;
@@ -145,9 +156,9 @@ __global__ void __launch_bounds__(64 * PAIR_WAVES) transport_pair_kernel(DevMech
             const double f = fma(s * xj.y, p.x, 1.0);
             den = fma(f * f, xj.x * p.y, den);
         }
-        const double mix = half_sum(sp ? X * mu / den : 0.0);
-        const double la = half_sum(sp ? X * lam : 0.0);
-        const double lh = half_sum(sp ? X / lam : 0.0);
+        const double mix = cell_sum<CPW>(sp ? X * mu / den : 0.0);
+        const double la = cell_sum<CPW>(sp ? X * lam : 0.0);
+        const double lh = cell_sum<CPW>(sp ? X / lam : 0.0);
         if (i == 0 && live) {
             mu_out[c] = mix;
             if (lam_out) lam_out[c] = 0.5 * (la + 1.0 / lh);
@@ -333,11 +344,17 @@ extern "C" int chemk_transport(chemk_ctx *c, int64_t n, const double *T, const d
     if (n == 0) return CHEMK_OK;
     if (!T || !Y || !mu) return fail_arg("null array");
     if (hipSetDevice(ctx_device(c)) != hipSuccess) return CHEMK_E_HIP;
+    // about eight workgroups per CU, each staging the factor table once
+    const size_t lds = sizeof(double2) * (size_t)tr->K * tr->K;
     if (tr->K <= HALF) {
-        // about eight workgroups per CU, each staging the factor table once
-        const int64_t passes = (n + PAIR_CELLS - 1) / PAIR_CELLS;
-        hipLaunchKernelGGL(transport_pair_kernel, dim3((unsigned)std::min<int64_t>(passes, 2048)),
-                           dim3(64 * PAIR_WAVES), 0, (hipStream_t)stream, ctx_devmech(c), tr->d, (int)n, T, Y, mu,
+        const int64_t passes = (n + 2 * PAIR_WAVES - 1) / (2 * PAIR_WAVES);
+        hipLaunchKernelGGL(transport_lds_kernel<2>, dim3((unsigned)std::min<int64_t>(passes, 2048)),
+                           dim3(64 * PAIR_WAVES), lds, (hipStream_t)stream, ctx_devmech(c), tr->d, (int)n, T, Y, mu,
+                           lam);
+    } else if (lds + sizeof(double2) * WAVE * PAIR_WAVES <= 64 * 1024) {
+        const int64_t passes = (n + PAIR_WAVES - 1) / PAIR_WAVES;
+        hipLaunchKernelGGL(transport_lds_kernel<1>, dim3((unsigned)std::min<int64_t>(passes, 2048)),
+                           dim3(64 * PAIR_WAVES), lds, (hipStream_t)stream, ctx_devmech(c), tr->d, (int)n, T, Y, mu,
                            lam);
     } else {
         const int per = 4;   // cells (waves) per workgroup
